@@ -1,0 +1,463 @@
+"""Plain FP64 CPU oracle for the inter-visibility hot path.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the bench's CPU
+baseline may import this package; the GPU library never does, and the two share
+no code.  Each function says which passage of the paper it follows.
+
+* ``Oracle`` wraps ivm_oracle.c (plain C, FP64, OpenMP over rows): pair
+  visibility (Section II-B), point-facet visibility and LoS (Section III-B,
+  Table II), and 128-bit exactness audits.
+* ``candidates_enum`` / ``candidates_matmul``: image-tree reflection candidates
+  (Section III-B, Table II; Section III-C) computed twice, by enumerating walks
+  and by integer vector-matrix products.
+* ``morton_treelets``: the Morton (Z-order) partition of triangles into 32
+  contiguous equal-count groups, written from its definition.
+* ``image_paths``: exact image-method specular paths on tiny scenes (the
+  image method of Section II and case study 2, Section IV-B), used to pin that
+  pruning keeps every valid path.
+* ``mlp_*``: FP64 reference of the occluder-ordering network (forward, BCE,
+  backward, Adam) and a finite-difference check.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ivm_oracle.c")
+_LIB = os.path.join(_HERE, "libivm_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O3, no FP contraction, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.ivo_create.restype = P
+        lib.ivo_create.argtypes = [i32, i32, i32, P, P, P, P, P]
+        lib.ivo_free.argtypes = [P]
+        lib.ivo_segtri.restype = i32
+        lib.ivo_segtri.argtypes = [P, P, P, P, P]
+        lib.ivo_orient.restype = ctypes.c_double
+        lib.ivo_orient.argtypes = [P, i32, P]
+        lib.ivo_pair.restype = i32
+        lib.ivo_pair.argtypes = [P, i32, i32]
+        lib.ivo_pair_directed.restype = i32
+        lib.ivo_pair_directed.argtypes = [P, i32, i32]
+        lib.ivo_matrix.restype = i64
+        lib.ivo_matrix.argtypes = [P, P, i32, i32]
+        lib.ivo_pairs.argtypes = [P, i32, P, P, P, i32]
+        lib.ivo_point_visible.restype = i32
+        lib.ivo_point_visible.argtypes = [P, P, i32]
+        lib.ivo_txrx.argtypes = [P, i32, P, P, P, P, P, i32]
+        lib.ivo_point_facets.argtypes = [P, i32, P, P, P, i32]
+        lib.ivo_los.argtypes = [P, i32, P, P, P]
+        lib.ivo_segment_clear.restype = i32
+        lib.ivo_segment_clear.argtypes = [P, P, P, i32, i32]
+        lib.ivo_pairs_occluder_groups.argtypes = [P, i32, P, P, P, P, i32]
+        lib.ivo_exact_audit.restype = i64
+        lib.ivo_exact_audit.argtypes = [i32, P, P, P, P, P, i32, P]
+        lib.ivo_orient_audit.restype = i64
+        lib.ivo_orient_audit.argtypes = [i32, P, P, P, P, i32]
+        lib.ivo_num_threads.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(3))
+
+
+class Oracle:
+    """The brute-force oracle bound to one scene (arrays as produced by scenegen)."""
+
+    def __init__(self, scene):
+        self.lib = _load()
+        self.scene = scene
+        self._keep = [np.ascontiguousarray(scene.vertices, np.float32),
+                      np.ascontiguousarray(scene.tri_vertices, np.int32),
+                      np.ascontiguousarray(scene.tri_facet, np.int32),
+                      np.ascontiguousarray(scene.sample_offsets, np.int32),
+                      np.ascontiguousarray(scene.samples, np.float32)]
+        v, tv, tf, so, sm = self._keep
+        self.F, self.T, self.S = scene.n_facets, scene.n_triangles, scene.n_samples
+        self.h = self.lib.ivo_create(self.F, self.T, self.S, _ptr(v), _ptr(tv), _ptr(tf), _ptr(so), _ptr(sm))
+
+    def close(self):
+        if self.h:
+            self.lib.ivo_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- Section II-B: facet pairs ------------------------------------------
+    def pair(self, i: int, j: int) -> int:
+        return int(self.lib.ivo_pair(self.h, i, j))
+
+    def pair_directed(self, i: int, j: int) -> int:
+        return int(self.lib.ivo_pair_directed(self.h, i, j))
+
+    def matrix(self, audit: bool = False, threads: int = 0) -> Tuple[np.ndarray, int]:
+        M = np.zeros((self.F, self.F), dtype=np.uint8)
+        mism = self.lib.ivo_matrix(self.h, _ptr(M), 1 if audit else 0, threads)
+        return M.astype(bool), int(mism)
+
+    def pairs(self, I: Sequence[int], J: Sequence[int], threads: int = 0) -> np.ndarray:
+        I = np.ascontiguousarray(I, np.int32)
+        J = np.ascontiguousarray(J, np.int32)
+        out = np.zeros(len(I), np.uint8)
+        self.lib.ivo_pairs(self.h, len(I), _ptr(I), _ptr(J), _ptr(out), threads)
+        return out.astype(bool)
+
+    def orient(self, f: int, x) -> float:
+        return float(self.lib.ivo_orient(self.h, f, _ptr(_f64(x))))
+
+    def segment_clear(self, p, q, ex1: int = -1, ex2: int = -1) -> bool:
+        return bool(self.lib.ivo_segment_clear(self.h, _ptr(_f64(p)), _ptr(_f64(q)), ex1, ex2))
+
+    # -- Section III-B: specific points ---------------------------------------
+    def point_visible(self, X, f: int) -> bool:
+        return bool(self.lib.ivo_point_visible(self.h, _ptr(_f64(X)), f))
+
+    def txrx(self, tx: np.ndarray, rx: np.ndarray, threads: int = 0):
+        tx = np.ascontiguousarray(tx, np.float32)
+        rx = np.ascontiguousarray(rx, np.float32)
+        N = tx.shape[0]
+        tv = np.zeros((N, self.F), np.uint8)
+        rv = np.zeros((N, self.F), np.uint8)
+        los = np.zeros(N, np.uint8)
+        self.lib.ivo_txrx(self.h, N, _ptr(tx), _ptr(rx), _ptr(tv), _ptr(rv), _ptr(los), threads)
+        return tv.astype(bool), rv.astype(bool), los.astype(bool)
+
+    def point_facets(self, X: np.ndarray, f: Sequence[int], threads: int = 0) -> np.ndarray:
+        X = np.ascontiguousarray(X, np.float32).reshape(-1, 3)
+        f = np.ascontiguousarray(f, np.int32)
+        out = np.zeros(len(f), np.uint8)
+        self.lib.ivo_point_facets(self.h, len(f), _ptr(X), _ptr(f), _ptr(out), threads)
+        return out.astype(bool)
+
+    def los(self, A: np.ndarray, B: np.ndarray) -> np.ndarray:
+        A = np.ascontiguousarray(A, np.float32).reshape(-1, 3)
+        B = np.ascontiguousarray(B, np.float32).reshape(-1, 3)
+        out = np.zeros(A.shape[0], np.uint8)
+        self.lib.ivo_los(self.h, A.shape[0], _ptr(A), _ptr(B), _ptr(out))
+        return out.astype(bool)
+
+    def occluder_groups(self, I, J, group_of_tri: np.ndarray, threads: int = 0) -> np.ndarray:
+        I = np.ascontiguousarray(I, np.int32)
+        J = np.ascontiguousarray(J, np.int32)
+        g = np.ascontiguousarray(group_of_tri, np.int32)
+        out = np.zeros(len(I), np.uint32)
+        self.lib.ivo_pairs_occluder_groups(self.h, len(I), _ptr(I), _ptr(J), _ptr(g), _ptr(out), threads)
+        return out
+
+
+def segtri(p, q, a, b, c) -> bool:
+    return bool(_load().ivo_segtri(_ptr(_f64(p)), _ptr(_f64(q)), _ptr(_f64(a)), _ptr(_f64(b)), _ptr(_f64(c))))
+
+
+def exact_audit(P, Q, A, B, C, grid_log2: int) -> Tuple[int, int]:
+    """(number of FP64/exact disagreements, number of exactly-zero determinants)."""
+    arrs = [np.ascontiguousarray(x, np.float32).reshape(-1, 3) for x in (P, Q, A, B, C)]
+    zeros = np.zeros(1, np.int64)
+    bad = _load().ivo_exact_audit(arrs[0].shape[0], *[_ptr(a) for a in arrs], grid_log2, _ptr(zeros))
+    return int(bad), int(zeros[0])
+
+
+def orient_audit(X, A, B, C, grid_log2: int) -> int:
+    arrs = [np.ascontiguousarray(x, np.float32).reshape(-1, 3) for x in (X, A, B, C)]
+    return int(_load().ivo_orient_audit(arrs[0].shape[0], *[_ptr(a) for a in arrs], grid_log2))
+
+
+def num_threads() -> int:
+    return int(_load().ivo_num_threads())
+
+
+# ---------------------------------------------------------------------------
+# Image-tree candidates (Section III-B, Table II: parent Tx -> reference face ->
+# aim face from the matrix; Section III-C: reflections up to the order needed)
+# ---------------------------------------------------------------------------
+
+def candidates_enum(M: np.ndarray, tx_vis: np.ndarray, rx_vis: np.ndarray, los: np.ndarray,
+                    K: int) -> Tuple[np.ndarray, List[List[List[Tuple[int, ...]]]]]:
+    """Enumerate walks f1 -> ... -> fk (k <= K) with vis_T(f1), M[f_m][f_m+1] and
+    vis_R(fk).  counts[n][0] = LoS; lists[n][k-1] are the k-tuples in
+    lexicographic order."""
+    M = np.asarray(M, bool)
+    N, F = tx_vis.shape
+    counts = np.zeros((N, K + 1), np.int64)
+    lists: List[List[List[Tuple[int, ...]]]] = []
+    nbrs = [list(np.nonzero(M[f])[0]) for f in range(F)]
+    for n in range(N):
+        counts[n, 0] = int(bool(los[n]))
+        per_order: List[List[Tuple[int, ...]]] = [[] for _ in range(K)]
+
+        def walk(prefix):
+            k = len(prefix)
+            if rx_vis[n, prefix[-1]]:
+                per_order[k - 1].append(tuple(prefix))
+            if k == K:
+                return
+            for f in nbrs[prefix[-1]]:
+                walk(prefix + [int(f)])
+
+        for f1 in range(F):
+            if tx_vis[n, f1]:
+                walk([f1])
+        for k in range(K):
+            per_order[k].sort()
+            counts[n, k + 1] = len(per_order[k])
+        lists.append(per_order)
+    return counts, lists
+
+
+def candidates_matmul(M: np.ndarray, tx_vis: np.ndarray, rx_vis: np.ndarray, los: np.ndarray,
+                      K: int) -> np.ndarray:
+    """Same counts by integer vector-matrix products: c_k = t^T M^(k-1) r."""
+    Mi = np.asarray(M, np.int64)
+    t = np.asarray(tx_vis, np.int64)
+    r = np.asarray(rx_vis, np.int64)
+    N = t.shape[0]
+    counts = np.zeros((N, K + 1), np.int64)
+    counts[:, 0] = np.asarray(los, np.int64)
+    w = t.copy()
+    for k in range(1, K + 1):
+        counts[:, k] = (w * r).sum(1)
+        w = w @ Mi
+    return counts
+
+
+# ---------------------------------------------------------------------------
+# Morton partition of triangles (Z-order curve, Morton 1966)
+# ---------------------------------------------------------------------------
+
+def morton_treelets(scene, n_groups: int = 32) -> Tuple[np.ndarray, np.ndarray]:
+    """Sort triangles by the 30-bit Morton code of their centroid (index breaks
+    ties) and cut the order into n_groups contiguous equal-count groups.
+
+    The centroid is quantised exactly in integers: with vertex coordinates in
+    grid units, c3 = a + b + c (three times the centroid) and the scene box
+    [lo, hi] over all triangle vertices, q = floor((c3 - 3 lo) * 1024 / (3 (hi - lo) + 1))
+    per axis, in [0, 1023].  Bits interleave as x, y, z from the top.
+    Returns (order, group_of_tri): order[r] = triangle at sorted rank r; group
+    of rank r = floor(r * n_groups / T)."""
+    scale = 2 ** scene.g
+    V = np.rint(scene.vertices.astype(np.float64) * scale).astype(np.int64)
+    assert np.all(V == scene.vertices.astype(np.float64) * scale)
+    tv = V[scene.tri_vertices]                      # T x 3 x 3
+    lo = tv.reshape(-1, 3).min(0)
+    hi = tv.reshape(-1, 3).max(0)
+    c3 = tv.sum(1)
+    den = 3 * (hi - lo) + 1
+    q = ((c3 - 3 * lo) * 1024) // den               # floor division, non-negative
+    assert q.min() >= 0 and q.max() <= 1023
+    T = tv.shape[0]
+    codes = np.zeros(T, np.int64)
+    for bit in range(10):
+        for ax, shift in ((0, 2), (1, 1), (2, 0)):
+            codes |= ((q[:, ax] >> bit) & 1) << (3 * bit + shift)
+    order = np.lexsort((np.arange(T), codes))
+    group_of_rank = (np.arange(T) * n_groups) // max(T, 1)
+    group_of_tri = np.empty(T, np.int32)
+    group_of_tri[order] = group_of_rank
+    return order.astype(np.int32), group_of_tri
+
+
+# ---------------------------------------------------------------------------
+# Image-method specular paths (for the pruning-recall pin)
+# ---------------------------------------------------------------------------
+
+def _facet_planes(scene):
+    V = scene.vertices.astype(np.float64)
+    F = scene.n_facets
+    first = np.full(F, -1)
+    for t in range(scene.n_triangles - 1, -1, -1):
+        first[scene.tri_facet[t]] = t
+    a = V[scene.tri_vertices[first, 0]]
+    b = V[scene.tri_vertices[first, 1]]
+    c = V[scene.tri_vertices[first, 2]]
+    n = np.cross(b - a, c - a)
+    return a, n
+
+
+def _in_facet(scene, f, x, tol=1e-9):
+    V = scene.vertices.astype(np.float64)
+    tris = np.nonzero(scene.tri_facet == f)[0]
+    for t in tris:
+        a, b, c = V[scene.tri_vertices[t]]
+        n = np.cross(b - a, c - a)
+        nn = np.dot(n, n)
+        w0 = np.dot(np.cross(b - a, x - a), n) / nn
+        w1 = np.dot(np.cross(c - b, x - b), n) / nn
+        w2 = np.dot(np.cross(a - c, x - c), n) / nn
+        if w0 >= -tol and w1 >= -tol and w2 >= -tol:
+            return True
+    return False
+
+
+def image_paths(scene, orc: Oracle, T, R, K: int) -> List[Tuple[int, ...]]:
+    """All valid specular reflection paths T -> f1 -> ... -> fk -> R (k <= K) by the
+    image method: mirror T successively in the planes of f1..fk, trace back from
+    R, require each reflection point inside its facet with the segment crossing
+    the plane between its ends, and every leg clear (excluding the facets at its
+    ends).  Float64 with a small tolerance; for well-conditioned pins only."""
+    a, n = _facet_planes(scene)
+    F = scene.n_facets
+    T = np.asarray(T, np.float64)
+    R = np.asarray(R, np.float64)
+    out = []
+
+    def reflect(x, f):
+        return x - 2.0 * np.dot(x - a[f], n[f]) / np.dot(n[f], n[f]) * n[f]
+
+    def valid(walk):
+        imgs = [T]
+        for f in walk:
+            imgs.append(reflect(imgs[-1], f))
+        pts = [None] * len(walk)
+        target = R
+        for m in range(len(walk) - 1, -1, -1):
+            f = walk[m]
+            I = imgs[m + 1]
+            da = np.dot(target - a[f], n[f])
+            db = np.dot(I - a[f], n[f])
+            if not (da > 1e-12 and db < -1e-12):
+                return False
+            s = da / (da - db)
+            P = target + s * (I - target)
+            if not _in_facet(scene, f, P):
+                return False
+            pts[m] = P
+            target = P
+        chain = [T] + pts + [R]
+        facs = [-1] + list(walk) + [-1]
+        for m in range(len(chain) - 1):
+            if not orc.segment_clear(chain[m], chain[m + 1], facs[m], facs[m + 1]):
+                return False
+        return True
+
+    def rec(walk):
+        if walk and valid(walk):
+            out.append(tuple(walk))
+        if len(walk) == K:
+            return
+        for f in range(F):
+            if walk and walk[-1] == f:
+                continue
+            rec(walk + [f])
+
+    rec([])
+    return sorted(out, key=lambda w: (len(w), w))
+
+
+# ---------------------------------------------------------------------------
+# Occluder-ordering network, FP64 reference
+# ---------------------------------------------------------------------------
+
+MLP_SIZES = (24, 128, 128, 128, 32)
+
+
+def mlp_init(seed: int = 0, sizes=MLP_SIZES) -> Dict[str, np.ndarray]:
+    """Deterministic He-uniform initialisation (numpy PCG64 with the given seed)."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for l in range(len(sizes) - 1):
+        fan_in = sizes[l]
+        bound = np.sqrt(6.0 / fan_in)
+        p[f"W{l}"] = rng.uniform(-bound, bound, size=(sizes[l + 1], sizes[l]))
+        p[f"b{l}"] = np.zeros(sizes[l + 1])
+    return p
+
+
+def mlp_forward(p: Dict[str, np.ndarray], X: np.ndarray):
+    """ReLU hidden layers, linear output.  Returns (logits, activations)."""
+    acts = [np.asarray(X, np.float64)]
+    L = len([k for k in p if k.startswith("W")])
+    h = acts[0]
+    for l in range(L):
+        z = h @ p[f"W{l}"].T + p[f"b{l}"]
+        h = np.maximum(z, 0.0) if l < L - 1 else z
+        acts.append(h)
+    return h, acts
+
+
+def bce_with_logits(z: np.ndarray, y: np.ndarray) -> float:
+    """Mean over all outputs of max(z,0) - z y + log(1 + exp(-|z|))."""
+    return float(np.mean(np.maximum(z, 0.0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+
+
+def mlp_loss_grad(p: Dict[str, np.ndarray], X: np.ndarray, Y: np.ndarray):
+    """Loss and gradients of the mean BCE-with-logits loss."""
+    z, acts = mlp_forward(p, X)
+    loss = bce_with_logits(z, Y)
+    L = len([k for k in p if k.startswith("W")])
+    dz = (1.0 / (1.0 + np.exp(-z)) - Y) / z.size
+    g = {}
+    for l in range(L - 1, -1, -1):
+        g[f"W{l}"] = dz.T @ acts[l]
+        g[f"b{l}"] = dz.sum(0)
+        if l > 0:
+            dh = dz @ p[f"W{l}"]
+            dz = dh * (acts[l] > 0.0)
+    return loss, g
+
+
+def adam_step(p, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba 2015) with bias correction."""
+    state["t"] = state.get("t", 0) + 1
+    t = state["t"]
+    for k in p:
+        m = state.setdefault("m_" + k, np.zeros_like(p[k]))
+        v = state.setdefault("v_" + k, np.zeros_like(p[k]))
+        m[:] = b1 * m + (1 - b1) * g[k]
+        v[:] = b2 * v + (1 - b2) * g[k] * g[k]
+        mh = m / (1 - b1 ** t)
+        vh = v / (1 - b2 ** t)
+        p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+    return p
+
+
+def mlp_fd_check(p, X, Y, n_probe: int = 20, h: float = 1e-6, seed: int = 0) -> float:
+    """Largest relative difference between analytic and central-difference gradients."""
+    rng = np.random.default_rng(seed)
+    _, g = mlp_loss_grad(p, X, Y)
+    worst = 0.0
+    for k in p:
+        for _ in range(max(1, n_probe // len(p))):
+            idx = tuple(rng.integers(0, s) for s in p[k].shape)
+            old = p[k][idx]
+            p[k][idx] = old + h
+            lp, _ = mlp_loss_grad(p, X, Y)
+            p[k][idx] = old - h
+            lm, _ = mlp_loss_grad(p, X, Y)
+            p[k][idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[k][idx]
+            worst = max(worst, abs(fd - an) / max(1e-8, abs(fd) + abs(an)))
+    return worst
