@@ -1,0 +1,219 @@
+/*
+ * ivm.h -- C ABI of libivm: facet inter-visibility pre-processing for dynamic
+ * ray tracing on AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the pre-processing pipeline of Yang et al., "An Efficient
+ * Pre-Processing Method for 6G Dynamic Ray-Tracing Channel Modeling" (IEEE TVT
+ * 2024): the scenario database (Section III-C, flow chart of Fig. 7) becomes
+ * ivm_build_scene; the static inter-visibility matrix (Section II-A/B) becomes
+ * ivm_intervisibility_matrix; the inter-visibility table for specific points
+ * along a trajectory (Section III-B, Table II; Section III-C) becomes
+ * ivm_txrx_visibility_table; the image tree that table prunes (Section II,
+ * Section III-B) becomes ivm_image_tree_candidates.
+ *
+ * Visibility is decided exactly in 3-D over deterministic per-facet sample
+ * points:
+ *   orient(f, x) = (x - a_f) . ((b_f - a_f) x (c_f - a_f)) with (a_f, b_f, c_f)
+ *     the first triangle of facet f; > 0 means x is on f's visible side
+ *     (Section II-B, eq. 2: only the side facing away from the building is
+ *     visible, and no ray leaves a face through its back side).
+ *   Facets i != j see each other iff some sample p of i and q of j have
+ *     orient(i, q) > 0, orient(j, p) > 0 and the open segment (p, q) meets no
+ *     closed triangle of any other facet transversally (Section II-B: two faces
+ *     see each other when no other obstacle lies between them; a third face
+ *     blocks).
+ *   A point X sees facet f iff orient(f, X) > 0 and some sample p of f has
+ *     (X, p) clear of every triangle outside f (Section III-B).
+ *
+ * Conventions
+ *   - Every call returns an ivm_status; 0 is success, negative values errors.
+ *     No C++ exception crosses this interface.
+ *   - Pointers named d_* are device pointers; the caller owns them.  Calls are
+ *     asynchronous and ordered on the given stream; results are valid after the
+ *     stream has been synchronised.
+ *   - Hot calls (matrix, table, candidates in count mode) allocate no device
+ *     memory; all device state lives in the caller-provided scene workspace.
+ *   - Read-only calls on one scene (table, candidates) may run concurrently on
+ *     different streams; ivm_intervisibility_matrix uses the scene's scratch
+ *     area and must not overlap another matrix call on the same scene.
+ *   - Bit layout of every facet bit set: bit j of row r is word j >> 6, bit
+ *     j & 63, of row r; rows have W = ceil(F / 64) uint64 words; padding bits
+ *     are zero.
+ */
+#ifndef IVM_H
+#define IVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ivm_status;
+
+#define IVM_OK 0
+#define IVM_ERR_INVALID_ARGUMENT (-1) /* null pointer, bad size, unsorted tri_facet, index out of range */
+#define IVM_ERR_WORKSPACE (-2)        /* workspace smaller than ivm_scene_workspace_size */
+#define IVM_ERR_GRID (-3)             /* coordinate off its dyadic grid, or FP64 exactness budget exceeded */
+#define IVM_ERR_DEGENERATE (-4)       /* zero-area first triangle, non-planar facet, or facet without triangles */
+#define IVM_ERR_HIP (-5)              /* a HIP runtime call or kernel launch failed */
+#define IVM_ERR_CAPACITY (-6)         /* output list capacity too small (counts are still valid) */
+#define IVM_ERR_MODEL (-7)            /* learned order requested without a usable model */
+
+/* Scene description.  Sizes are host values; array pointers are device pointers
+ * that must stay valid while the scene handle exists.
+ *   vertices        float[n_vertices][3], metres, every coordinate a multiple of
+ *                   2^-grid_vertex_log2 and exactly representable in FP32.
+ *   tri_vertices    int32[n_triangles][3] vertex indices.
+ *   tri_facet       int32[n_triangles], facet id in [0, n_facets), non-decreasing:
+ *                   the triangles of one facet are contiguous.  The winding of a
+ *                   facet's first triangle defines its visible side.
+ *   sample_offsets  int32[n_facets + 1], CSR offsets into samples.
+ *   samples         float[n_samples][3], every coordinate a multiple of
+ *                   2^-grid_sample_log2 (grid_sample_log2 >= grid_vertex_log2).
+ * The scene is accepted only if every predicate above is exact in FP64:
+ * with D the largest coordinate extent of vertices and samples and E the largest
+ * triangle edge component, (6 D E^2 + 12 D^2 E) 2^(3g + 2(gs - g)) < 2^53 and
+ * D 2^gs < 2^24, g = grid_vertex_log2, gs = grid_sample_log2. */
+typedef struct ivm_scene_desc {
+    int32_t n_vertices;
+    int32_t n_triangles;
+    int32_t n_facets;
+    int32_t n_samples;
+    const float *vertices;
+    const int32_t *tri_vertices;
+    const int32_t *tri_facet;
+    const int32_t *sample_offsets;
+    const float *samples;
+    int32_t grid_vertex_log2;
+    int32_t grid_sample_log2;
+    int32_t flags; /* IVM_SCENE_* */
+} ivm_scene_desc;
+
+/* desc.flags: reserve room for a learned traversal order of every facet pair
+ * (8 bytes per unordered pair) so IVM_ORDER_LEARNED can be used on the scene. */
+#define IVM_SCENE_LEARNED 1
+
+typedef struct ivm_scene ivm_scene; /* opaque host handle */
+
+/* Scene facts filled by ivm_scene_info (host memory). */
+typedef struct ivm_scene_info_t {
+    int32_t n_facets;
+    int32_t n_triangles;
+    int32_t n_samples;
+    int32_t words_per_row;     /* W = ceil(F / 64) */
+    int32_t n_treelets;        /* top-level BVH subtrees (32, fewer when T < 32) */
+    int32_t max_samples_per_facet;
+    int64_t n_nodes;
+    size_t workspace_bytes;
+} ivm_scene_info_t;
+
+/* Device-side counters, accumulated by the hot calls (the caller zeroes them).
+ * segments: segments traversed; node_visits: internal BVH nodes whose child
+ * boxes were tested; tri_tests: segment/triangle tests; rechecks: tests whose
+ * FP32 margin was too small and which were decided in FP64; fallbacks: subtrees
+ * scanned linearly because the traversal stack was full. */
+typedef struct ivm_stats {
+    uint64_t pairs_total;
+    uint64_t pairs_candidate;
+    uint64_t pairs_visible;
+    uint64_t segments;
+    uint64_t node_visits;
+    uint64_t tri_tests;
+    uint64_t rechecks;
+    uint64_t fallbacks;
+    uint64_t point_items;
+    uint64_t flags; /* bit 0: learned order fell back to the plain order */
+    uint64_t reserved[6];
+} ivm_stats;
+
+#define IVM_ORDER_PLAIN 0    /* treelets nearest the pair's segment box first */
+#define IVM_ORDER_LEARNED 1  /* treelets by the occluder-ordering network's score */
+#define IVM_ORDER_INDEX 2    /* treelets in Morton (index) order */
+#define IVM_ORDER_REVERSED 3 /* reverse of the plain order (a control) */
+
+/* Traversal options.  None of them changes a result bit. */
+typedef struct ivm_matrix_opts {
+    int32_t order_mode;     /* IVM_ORDER_* */
+    int32_t fp64_only;      /* 1: decide every segment/triangle test in FP64 */
+    int32_t stack_depth;    /* 2..IVM_MAX_STACK; 0 = default; overflow scans linearly */
+    int32_t waves_per_cu;   /* persistent grid size; 0 = default */
+    float eps;              /* FP32 filter margin relative to the magnitude bound;
+                               0 = default 1e-5; values < 1e-5 are raised to 1e-5;
+                               +inf sends every test to FP64 */
+    int32_t reserved[3];
+} ivm_matrix_opts;
+
+#define IVM_MAX_STACK 32
+
+const char *ivm_status_string(ivm_status s);
+
+/* Bytes of device workspace ivm_build_scene needs for this description
+ * (host-only, synchronous; reads only the size fields). */
+ivm_status ivm_scene_workspace_size(const ivm_scene_desc *desc, size_t *bytes);
+
+/* Validate the description, copy and lay out the scene in the workspace, and
+ * build the Morton-code LBVH (32 treelets of contiguous Morton ranges).
+ * The handle is host memory; d_workspace (>= ivm_scene_workspace_size bytes,
+ * 256-byte aligned) is caller-owned and must outlive the handle.
+ * Synchronous errors: IVM_ERR_INVALID_ARGUMENT, IVM_ERR_WORKSPACE, IVM_ERR_HIP.
+ * Device-side validation (off-grid coordinates, exactness budget, degenerate
+ * facets, unsorted tri_facet, indices out of range) is reported by
+ * ivm_scene_status. */
+ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t workspace_bytes,
+                           hipStream_t stream, ivm_scene **out);
+
+/* Synchronises the scene's build stream and returns the first device-reported
+ * validation error of the scene (or of a later Tx/Rx position check), else IVM_OK. */
+ivm_status ivm_scene_status(ivm_scene *scene);
+
+ivm_status ivm_scene_info(const ivm_scene *scene, ivm_scene_info_t *info);
+
+ivm_status ivm_destroy_scene(ivm_scene *scene);
+
+/* The static inter-visibility matrix (Section II-A/B): d_M is uint64[F][W],
+ * symmetric, zero diagonal.  opts may be NULL (defaults).  d_stats may be NULL.
+ * Errors: IVM_ERR_INVALID_ARGUMENT, IVM_ERR_MODEL (learned order without a model
+ * attached: the call still runs in plain order and sets stats flag bit 0),
+ * IVM_ERR_HIP. */
+ivm_status ivm_intervisibility_matrix(ivm_scene *scene, const ivm_matrix_opts *opts, uint64_t *d_M,
+                                      ivm_stats *d_stats, hipStream_t stream);
+
+/* Inter-visibility table for specific points (Section III-B, Table II) along a
+ * trajectory (Section III-C): for each snapshot n, the facets visible from
+ * d_tx[n] and from d_rx[n] (uint64[N][W] each) and line of sight between them
+ * (uint8[N]).  Positions are float[N][3] on the sample grid; off-grid positions
+ * or positions that break the exactness budget are reported by ivm_scene_status.
+ * opts may be NULL.  Errors: IVM_ERR_INVALID_ARGUMENT, IVM_ERR_HIP. */
+ivm_status ivm_txrx_visibility_table(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_snap,
+                                     const float *d_tx, const float *d_rx, uint64_t *d_tx_vis,
+                                     uint64_t *d_rx_vis, uint8_t *d_los, ivm_stats *d_stats,
+                                     hipStream_t stream);
+
+/* Image-tree reflection candidates up to max_order (1..2) per snapshot: walks
+ * f1 -> ... -> fk with tx_vis(f1), M[f_m][f_m+1] and rx_vis(fk) (Section III-B,
+ * Table II: transmitter -> reference face -> aim face).  d_counts is
+ * int64[N][max_order + 1] with column 0 = line of sight.  If d_paths is NULL
+ * only counts are produced (asynchronous).  Otherwise d_offsets (int64[N *
+ * max_order + 1]) receives CSR offsets of the lists (snapshot-major, order-minor)
+ * and d_paths the k-tuples as int32 in lexicographic order; this mode
+ * synchronises the stream once to check paths_cap (in int32 elements) and
+ * returns IVM_ERR_CAPACITY, with valid counts and offsets, when it is too small. */
+ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int32_t n_snap,
+                                     const uint64_t *d_tx_vis, const uint64_t *d_rx_vis,
+                                     const uint8_t *d_los, int32_t max_order, int64_t *d_counts,
+                                     int64_t *d_offsets, int32_t *d_paths, size_t paths_cap,
+                                     hipStream_t stream);
+
+/* Treelet (Morton group) index of every triangle in the caller's triangle order:
+ * d_group is int32[T].  Treelet k holds sorted ranks [ceil(k T / 32), ceil((k+1) T / 32)). */
+ivm_status ivm_triangle_groups(const ivm_scene *scene, int32_t *d_group, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IVM_H */

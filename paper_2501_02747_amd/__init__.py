@@ -1,0 +1,314 @@
+"""Python binding of libivm (facet inter-visibility pre-processing on MI355X).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+of ``libivm.so`` behind the C ABI of ``include/ivm.h``.  PyTorch supplies device
+memory and the current HIP stream.  There is no CPU fallback: if the library is
+missing or no GPU is present, the calls raise.
+
+The functions below carry the names of the C entry points; ``GpuScene`` bundles
+a scene handle with the device tensors it references.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libivm.so")
+
+IVM_OK = 0
+IVM_ERR_INVALID_ARGUMENT = -1
+IVM_ERR_WORKSPACE = -2
+IVM_ERR_GRID = -3
+IVM_ERR_DEGENERATE = -4
+IVM_ERR_HIP = -5
+IVM_ERR_CAPACITY = -6
+IVM_ERR_MODEL = -7
+
+IVM_ORDER_PLAIN, IVM_ORDER_LEARNED, IVM_ORDER_INDEX, IVM_ORDER_REVERSED = 0, 1, 2, 3
+IVM_SCENE_LEARNED = 1
+IVM_MAX_STACK = 32
+
+EXPORTED = [
+    "ivm_status_string", "ivm_scene_workspace_size", "ivm_build_scene", "ivm_scene_status",
+    "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
+    "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups",
+]
+
+
+class IvmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class ivm_scene_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_int32), ("n_triangles", ctypes.c_int32),
+        ("n_facets", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+        ("vertices", ctypes.c_void_p), ("tri_vertices", ctypes.c_void_p),
+        ("tri_facet", ctypes.c_void_p), ("sample_offsets", ctypes.c_void_p),
+        ("samples", ctypes.c_void_p),
+        ("grid_vertex_log2", ctypes.c_int32), ("grid_sample_log2", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class ivm_scene_info_t(ctypes.Structure):
+    _fields_ = [
+        ("n_facets", ctypes.c_int32), ("n_triangles", ctypes.c_int32),
+        ("n_samples", ctypes.c_int32), ("words_per_row", ctypes.c_int32),
+        ("n_treelets", ctypes.c_int32), ("max_samples_per_facet", ctypes.c_int32),
+        ("n_nodes", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class ivm_matrix_opts(ctypes.Structure):
+    _fields_ = [
+        ("order_mode", ctypes.c_int32), ("fp64_only", ctypes.c_int32),
+        ("stack_depth", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+        ("eps", ctypes.c_float), ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+STATS_FIELDS = ["pairs_total", "pairs_candidate", "pairs_visible", "segments", "node_visits",
+                "tri_tests", "rechecks", "fallbacks", "point_items", "flags"]
+STATS_WORDS = 16
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libivm.so (torch is imported first so the process has one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (brings in torch's HIP runtime before ours)
+    if not os.path.exists(path):
+        raise ImportError(f"libivm.so not built at {path}; run paper_2501_02747_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.ivm_status_string.restype = ctypes.c_char_p
+    lib.ivm_status_string.argtypes = [i32]
+    lib.ivm_scene_workspace_size.restype = i32
+    lib.ivm_scene_workspace_size.argtypes = [ctypes.POINTER(ivm_scene_desc), ctypes.POINTER(sz)]
+    lib.ivm_build_scene.restype = i32
+    lib.ivm_build_scene.argtypes = [ctypes.POINTER(ivm_scene_desc), P, sz, P, ctypes.POINTER(P)]
+    lib.ivm_scene_status.restype = i32
+    lib.ivm_scene_status.argtypes = [P]
+    lib.ivm_scene_info.restype = i32
+    lib.ivm_scene_info.argtypes = [P, ctypes.POINTER(ivm_scene_info_t)]
+    lib.ivm_destroy_scene.restype = i32
+    lib.ivm_destroy_scene.argtypes = [P]
+    lib.ivm_intervisibility_matrix.restype = i32
+    lib.ivm_intervisibility_matrix.argtypes = [P, ctypes.POINTER(ivm_matrix_opts), P, P, P]
+    lib.ivm_txrx_visibility_table.restype = i32
+    lib.ivm_txrx_visibility_table.argtypes = [P, ctypes.POINTER(ivm_matrix_opts), i32, P, P, P, P, P, P, P]
+    lib.ivm_image_tree_candidates.restype = i32
+    lib.ivm_image_tree_candidates.argtypes = [P, P, i32, P, P, P, i32, P, P, P, sz, P]
+    lib.ivm_triangle_groups.restype = i32
+    lib.ivm_triangle_groups.argtypes = [P, P, P]
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load_library().ivm_status_string(status).decode()
+    except Exception:
+        return str(status)
+
+
+def _check(status: int, where: str, ok=(IVM_OK,)):
+    if status not in ok:
+        raise IvmError(status, where)
+    return status
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def make_opts(order_mode: int = IVM_ORDER_PLAIN, fp64_only: bool = False, stack_depth: int = 0,
+              waves_per_cu: int = 0, eps: float = 0.0) -> ivm_matrix_opts:
+    o = ivm_matrix_opts()
+    o.order_mode, o.fp64_only, o.stack_depth = order_mode, int(fp64_only), stack_depth
+    o.waves_per_cu, o.eps = waves_per_cu, eps
+    return o
+
+
+def new_stats(device="cuda"):
+    import torch
+    return torch.zeros(STATS_WORDS, dtype=torch.int64, device=device)
+
+
+def stats_dict(stats) -> dict:
+    v = stats.cpu().numpy().astype(np.uint64)
+    return {k: int(v[i]) for i, k in enumerate(STATS_FIELDS)}
+
+
+class GpuScene:
+    """A scene resident in HBM with its LBVH built by ivm_build_scene.
+
+    Takes host arrays (any object with the ``vertices``, ``tri_vertices``,
+    ``tri_facet``, ``sample_offsets``, ``samples``, ``g``, ``k`` attributes,
+    or explicit arrays) and copies them to the device once."""
+
+    def __init__(self, vertices, tri_vertices, tri_facet, sample_offsets, samples, g: int, gs: int,
+                 learned: bool = False, device: str = "cuda", stream=None):
+        import torch
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libivm needs a HIP GPU; none is visible")
+        dev = torch.device(device)
+        self.vertices = torch.as_tensor(np.ascontiguousarray(vertices, np.float32)).to(dev)
+        self.tri_vertices = torch.as_tensor(np.ascontiguousarray(tri_vertices, np.int32)).to(dev)
+        self.tri_facet = torch.as_tensor(np.ascontiguousarray(tri_facet, np.int32)).to(dev)
+        self.sample_offsets = torch.as_tensor(np.ascontiguousarray(sample_offsets, np.int32)).to(dev)
+        self.samples = torch.as_tensor(np.ascontiguousarray(samples, np.float32)).to(dev)
+        d = ivm_scene_desc()
+        d.n_vertices = self.vertices.shape[0]
+        d.n_triangles = self.tri_vertices.shape[0]
+        d.n_facets = self.sample_offsets.shape[0] - 1
+        d.n_samples = self.samples.shape[0]
+        d.vertices, d.tri_vertices = _ptr(self.vertices), _ptr(self.tri_vertices)
+        d.tri_facet, d.sample_offsets = _ptr(self.tri_facet), _ptr(self.sample_offsets)
+        d.samples = _ptr(self.samples)
+        d.grid_vertex_log2, d.grid_sample_log2 = g, gs
+        d.flags = IVM_SCENE_LEARNED if learned else 0
+        self.desc = d
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.ivm_scene_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), "ivm_scene_workspace_size")
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        base = int(self.workspace.data_ptr())
+        aligned = (base + 255) & ~255
+        self.handle = ctypes.c_void_p()
+        _check(lib.ivm_build_scene(ctypes.byref(d), aligned, int(nbytes.value), _stream(stream),
+                                   ctypes.byref(self.handle)), "ivm_build_scene")
+        info = ivm_scene_info_t()
+        _check(lib.ivm_scene_info(self.handle, ctypes.byref(info)), "ivm_scene_info")
+        self.F, self.T, self.S, self.W = info.n_facets, info.n_triangles, info.n_samples, info.words_per_row
+        self.n_treelets = info.n_treelets
+        self.device = dev
+
+    @classmethod
+    def from_scene(cls, sc, **kw) -> "GpuScene":
+        return cls(sc.vertices, sc.tri_vertices, sc.tri_facet, sc.sample_offsets, sc.samples,
+                   sc.g, sc.g + sc.k, **kw)
+
+    def status(self) -> int:
+        return ivm_scene_status(self)
+
+    def check(self):
+        _check(self.status(), "scene validation")
+        return self
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load_library().ivm_destroy_scene(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- entry points with the C names ---------------------------------------------
+
+def ivm_scene_status(scene: GpuScene) -> int:
+    return int(load_library().ivm_scene_status(scene.handle))
+
+
+def ivm_intervisibility_matrix(scene: GpuScene, opts: Optional[ivm_matrix_opts] = None, out=None, stats=None,
+                               stream=None, allow_model_fallback: bool = False):
+    """Returns the bit-packed matrix as an int64 tensor [F, W] (bit j of row i = word j>>6, bit j&63)."""
+    import torch
+    if out is None:
+        out = torch.empty((scene.F, scene.W), dtype=torch.int64, device=scene.device)
+    st = load_library().ivm_intervisibility_matrix(scene.handle, ctypes.byref(opts) if opts is not None else None,
+                                                   _ptr(out), _ptr(stats), _stream(stream))
+    _check(st, "ivm_intervisibility_matrix", ok=(IVM_OK, IVM_ERR_MODEL) if allow_model_fallback else (IVM_OK,))
+    return out
+
+
+def ivm_txrx_visibility_table(scene: GpuScene, tx, rx, opts: Optional[ivm_matrix_opts] = None, stats=None,
+                              out=None, stream=None):
+    """tx, rx: float32 device tensors [N, 3].  Returns (tx_vis [N, W] int64, rx_vis, los uint8 [N])."""
+    import torch
+    N = int(tx.shape[0])
+    if out is None:
+        out = (torch.empty((N, scene.W), dtype=torch.int64, device=scene.device),
+               torch.empty((N, scene.W), dtype=torch.int64, device=scene.device),
+               torch.empty((N,), dtype=torch.uint8, device=scene.device))
+    tv, rv, los = out
+    _check(load_library().ivm_txrx_visibility_table(
+        scene.handle, ctypes.byref(opts) if opts is not None else None, N, _ptr(tx), _ptr(rx),
+        _ptr(tv), _ptr(rv), _ptr(los), _ptr(stats), _stream(stream)), "ivm_txrx_visibility_table")
+    return tv, rv, los
+
+
+def ivm_image_tree_candidates(scene: GpuScene, M, tx_vis, rx_vis, los, max_order: int = 2, lists: bool = False,
+                              paths_cap: Optional[int] = None, counts=None, stream=None):
+    """Counts int64 [N, K+1]; with lists=True also (offsets int64 [N*K+1], paths int32)."""
+    import torch
+    N = int(tx_vis.shape[0])
+    if counts is None:
+        counts = torch.empty((N, max_order + 1), dtype=torch.int64, device=scene.device)
+    lib = load_library()
+    if not lists:
+        _check(lib.ivm_image_tree_candidates(scene.handle, _ptr(M), N, _ptr(tx_vis), _ptr(rx_vis), _ptr(los),
+                                             max_order, _ptr(counts), None, None, 0, _stream(stream)),
+               "ivm_image_tree_candidates")
+        return counts
+    offsets = torch.empty((N * max_order + 1,), dtype=torch.int64, device=scene.device)
+    cap = paths_cap if paths_cap is not None else 1
+    paths = torch.empty((max(cap, 1),), dtype=torch.int32, device=scene.device)
+    st = lib.ivm_image_tree_candidates(scene.handle, _ptr(M), N, _ptr(tx_vis), _ptr(rx_vis), _ptr(los), max_order,
+                                       _ptr(counts), _ptr(offsets), _ptr(paths), cap, _stream(stream))
+    if st == IVM_ERR_CAPACITY and paths_cap is None:
+        need = int(offsets[-1].item())
+        paths = torch.empty((max(need, 1),), dtype=torch.int32, device=scene.device)
+        st = lib.ivm_image_tree_candidates(scene.handle, _ptr(M), N, _ptr(tx_vis), _ptr(rx_vis), _ptr(los),
+                                           max_order, _ptr(counts), _ptr(offsets), _ptr(paths), need,
+                                           _stream(stream))
+    _check(st, "ivm_image_tree_candidates")
+    return counts, offsets, paths
+
+
+def ivm_triangle_groups(scene: GpuScene, stream=None):
+    import torch
+    out = torch.empty((max(scene.T, 1),), dtype=torch.int32, device=scene.device)
+    _check(load_library().ivm_triangle_groups(scene.handle, _ptr(out), _stream(stream)), "ivm_triangle_groups")
+    return out[: scene.T]
+
+
+# ---- host-side helpers (no visibility arithmetic) --------------------------------
+
+def unpack_bits(words, n: int) -> np.ndarray:
+    """[..., W] int64 words -> [..., n] bool (bit j = word j>>6, bit j&63)."""
+    w = np.ascontiguousarray(words.cpu().numpy() if hasattr(words, "cpu") else words).view(np.uint64)
+    b = np.unpackbits(w.view(np.uint8).reshape(*w.shape, 8), axis=-1, bitorder="little")
+    return b.reshape(*w.shape[:-1], w.shape[-1] * 64)[..., :n].astype(bool)
+
+
+def pack_bits(bits: np.ndarray) -> np.ndarray:
+    """[..., n] bool -> [..., ceil(n/64)] int64 words."""
+    bits = np.asarray(bits, bool)
+    n = bits.shape[-1]
+    W = (n + 63) // 64
+    pad = np.zeros((*bits.shape[:-1], W * 64), bool)
+    pad[..., :n] = bits
+    by = np.packbits(pad.reshape(*bits.shape[:-1], W * 8, 8), axis=-1, bitorder="little")
+    return by.reshape(*bits.shape[:-1], W * 8).view(np.uint64).view(np.int64).reshape(*bits.shape[:-1], W)

@@ -1,0 +1,226 @@
+// abi.hip -- the extern "C" entry points of libivm (declared in include/ivm.h).
+// Host code only: argument checks, workspace layout, option defaults, launches.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "ivm_internal.h"
+
+using namespace ivm;
+
+struct ivm_scene {
+    Scene s;
+};
+
+namespace {
+
+ivm_status status_from_bits(int bits) {
+    if (bits & kStInvalid) return IVM_ERR_INVALID_ARGUMENT;
+    if (bits & kStGrid) return IVM_ERR_GRID;
+    if (bits & kStDegenerate) return IVM_ERR_DEGENERATE;
+    return IVM_OK;
+}
+
+bool desc_sizes_ok(const ivm_scene_desc *d) {
+    if (!d) return false;
+    if (d->n_vertices < 0 || d->n_triangles < 0 || d->n_facets < 0 || d->n_samples < 0) return false;
+    if (d->n_facets > 65535 || d->n_triangles > (1 << 27)) return false;
+    if (d->grid_vertex_log2 < -30 || d->grid_vertex_log2 > 30) return false;
+    if (d->grid_sample_log2 < d->grid_vertex_log2 || d->grid_sample_log2 > 30) return false;
+    if (d->n_facets > 0 && !d->sample_offsets) return false;
+    if (d->n_triangles > 0 && (!d->tri_vertices || !d->tri_facet || !d->vertices || d->n_vertices == 0)) return false;
+    if (d->n_samples > 0 && !d->samples) return false;
+    return true;
+}
+
+TraverseOpts make_opts(const ivm_matrix_opts *o) {
+    TraverseOpts t{};
+    t.order_mode = o ? o->order_mode : IVM_ORDER_PLAIN;
+    t.fp64_only = o ? o->fp64_only : 0;
+    int depth = (o && o->stack_depth > 0) ? o->stack_depth : kDefaultStack;
+    if (depth < 2) depth = 2;
+    if (depth > IVM_MAX_STACK) depth = IVM_MAX_STACK;
+    t.stack_depth = depth;
+    float eps = (o && o->eps > 0.f) ? o->eps : kDefaultEps;
+    if (!(eps >= kDefaultEps)) eps = kDefaultEps;  // never below the sound margin (NaN -> default)
+    t.eps6 = std::isinf(eps) ? INFINITY : 6.0f * eps;
+    int wpc = (o && o->waves_per_cu > 0) ? o->waves_per_cu : 16;
+    if (wpc > 64) wpc = 64;
+    long long blocks = (long long)device_cu_count() * wpc / 4;
+    if (blocks < 1) blocks = 1;
+    t.grid_blocks = (int)blocks;
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ivm_status_string(ivm_status s) {
+    switch (s) {
+        case IVM_OK: return "IVM_OK";
+        case IVM_ERR_INVALID_ARGUMENT: return "IVM_ERR_INVALID_ARGUMENT";
+        case IVM_ERR_WORKSPACE: return "IVM_ERR_WORKSPACE";
+        case IVM_ERR_GRID: return "IVM_ERR_GRID";
+        case IVM_ERR_DEGENERATE: return "IVM_ERR_DEGENERATE";
+        case IVM_ERR_HIP: return "IVM_ERR_HIP";
+        case IVM_ERR_CAPACITY: return "IVM_ERR_CAPACITY";
+        case IVM_ERR_MODEL: return "IVM_ERR_MODEL";
+        default: return "IVM_ERR_UNKNOWN";
+    }
+}
+
+ivm_status ivm_scene_workspace_size(const ivm_scene_desc *desc, size_t *bytes) {
+    if (!desc || !bytes || !desc_sizes_ok(desc)) return IVM_ERR_INVALID_ARGUMENT;
+    *bytes = make_layout(desc->n_facets, desc->n_triangles, desc->n_samples,
+                         (desc->flags & IVM_SCENE_LEARNED) != 0)
+                 .total;
+    return IVM_OK;
+}
+
+ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t workspace_bytes, hipStream_t stream,
+                           ivm_scene **out) {
+    if (!out) return IVM_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (!desc || !desc_sizes_ok(desc) || !d_workspace) return IVM_ERR_INVALID_ARGUMENT;
+    if (((uintptr_t)d_workspace & 255u) != 0) return IVM_ERR_INVALID_ARGUMENT;
+    Layout L = make_layout(desc->n_facets, desc->n_triangles, desc->n_samples, (desc->flags & IVM_SCENE_LEARNED) != 0);
+    if (workspace_bytes < L.total) return IVM_ERR_WORKSPACE;
+    ivm_scene *h = new (std::nothrow) ivm_scene();
+    if (!h) return IVM_ERR_INVALID_ARGUMENT;
+    Scene &sc = h->s;
+    sc.desc = *desc;
+    sc.ws = d_workspace;
+    sc.ws_bytes = workspace_bytes;
+    sc.lay = L;
+    sc.build_stream = stream;
+    sc.model = nullptr;
+    const int F = desc->n_facets;
+    SceneDev &d = sc.dev;
+    char *ws = (char *)d_workspace;
+    d.F = F;
+    d.T = desc->n_triangles;
+    d.S = desc->n_samples;
+    d.W = (F + 63) / 64;
+    d.n_treelets = desc->n_triangles < kTreelets ? desc->n_triangles : kTreelets;
+    d.max_spf = kMaxSamplesPerFacet;
+    d.g = desc->grid_vertex_log2;
+    d.gs = desc->grid_sample_log2;
+    d.tri = (const float4 *)(ws + L.tri);
+    d.tri_orig = (const int *)(ws + L.tri_orig);
+    d.tri_group = (const int *)(ws + L.tri_group);
+    d.nodes = (const Node *)(ws + L.nodes);
+    d.tl_box = (const float *)(ws + L.tl_box);
+    d.tl_root = (const int *)(ws + L.tl_root);
+    d.fplane = (const double *)(ws + L.fplane);
+    d.fbox = (const float *)(ws + L.fbox);
+    d.soff = (const int *)(ws + L.soff);
+    d.smp = (const float4 *)(ws + L.smp);
+    d.sfacet = (const int *)(ws + L.sfacet);
+    d.status = (int *)(ws + L.status);
+    d.extent = (const double *)(ws + L.extent);
+    sc.n_items = F * d.W;
+    if (launch_build(sc, stream) != hipSuccess) {
+        delete h;
+        return IVM_ERR_HIP;
+    }
+    *out = h;
+    return IVM_OK;
+}
+
+ivm_status ivm_scene_status(ivm_scene *scene) {
+    if (!scene) return IVM_ERR_INVALID_ARGUMENT;
+    int bits = 0;
+    if (hipStreamSynchronize(scene->s.build_stream) != hipSuccess) return IVM_ERR_HIP;
+    if (hipMemcpy(&bits, scene->s.dev.status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return IVM_ERR_HIP;
+    return status_from_bits(bits);
+}
+
+ivm_status ivm_scene_info(const ivm_scene *scene, ivm_scene_info_t *info) {
+    if (!scene || !info) return IVM_ERR_INVALID_ARGUMENT;
+    const SceneDev &d = scene->s.dev;
+    info->n_facets = d.F;
+    info->n_triangles = d.T;
+    info->n_samples = d.S;
+    info->words_per_row = d.W;
+    info->n_treelets = d.n_treelets;
+    info->max_samples_per_facet = d.max_spf;
+    info->n_nodes = d.T;
+    info->workspace_bytes = scene->s.lay.total;
+    return IVM_OK;
+}
+
+ivm_status ivm_destroy_scene(ivm_scene *scene) {
+    if (!scene) return IVM_ERR_INVALID_ARGUMENT;
+    delete scene;
+    return IVM_OK;
+}
+
+ivm_status ivm_intervisibility_matrix(ivm_scene *scene, const ivm_matrix_opts *opts, uint64_t *d_M,
+                                      ivm_stats *d_stats, hipStream_t stream) {
+    if (!scene || !d_M) return IVM_ERR_INVALID_ARGUMENT;
+    if (opts && (opts->order_mode < IVM_ORDER_PLAIN || opts->order_mode > IVM_ORDER_REVERSED))
+        return IVM_ERR_INVALID_ARGUMENT;
+    TraverseOpts o = make_opts(opts);
+    ivm_status ret = IVM_OK;
+    if (o.order_mode == IVM_ORDER_LEARNED && (!scene->s.model || scene->s.lay.learned_bytes == 0)) {
+        o.order_mode = IVM_ORDER_PLAIN;
+        ret = IVM_ERR_MODEL;
+        // stats flag bit 0: learned order requested but unavailable
+        if (d_stats && launch_fill_u64(&d_stats->flags, 1ull, 1, stream) != hipSuccess) return IVM_ERR_HIP;
+    }
+    if (launch_matrix(scene->s, o, d_M, d_stats, nullptr, stream) != hipSuccess) return IVM_ERR_HIP;
+    return ret;
+}
+
+ivm_status ivm_txrx_visibility_table(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_snap,
+                                     const float *d_tx, const float *d_rx, uint64_t *d_tx_vis, uint64_t *d_rx_vis,
+                                     uint8_t *d_los, ivm_stats *d_stats, hipStream_t stream) {
+    if (!scene || n_snap < 0) return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap > 0 && (!d_tx || !d_rx || !d_tx_vis || !d_rx_vis || !d_los)) return IVM_ERR_INVALID_ARGUMENT;
+    if (opts && (opts->order_mode < IVM_ORDER_PLAIN || opts->order_mode > IVM_ORDER_REVERSED))
+        return IVM_ERR_INVALID_ARGUMENT;
+    TraverseOpts o = make_opts(opts);
+    if (n_snap == 0) return IVM_OK;
+    if (launch_points(scene->s, o, n_snap, d_tx, d_rx, d_tx_vis, d_rx_vis, d_los, d_stats, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int32_t n_snap,
+                                     const uint64_t *d_tx_vis, const uint64_t *d_rx_vis, const uint8_t *d_los,
+                                     int32_t max_order, int64_t *d_counts, int64_t *d_offsets, int32_t *d_paths,
+                                     size_t paths_cap, hipStream_t stream) {
+    if (!scene || n_snap < 0 || max_order < 1 || max_order > 2) return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap > 0 && (!d_M || !d_tx_vis || !d_rx_vis || !d_los || !d_counts)) return IVM_ERR_INVALID_ARGUMENT;
+    if (d_paths && !d_offsets) return IVM_ERR_INVALID_ARGUMENT;
+    const SceneDev &d = scene->s.dev;
+    if (n_snap == 0) return IVM_OK;
+    if (launch_candidates_count(d, d_M, n_snap, d_tx_vis, d_rx_vis, d_los, max_order, d_counts, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    if (!d_paths) {
+        if (d_offsets && launch_candidates_offsets(n_snap, max_order, d_counts, d_offsets, stream) != hipSuccess)
+            return IVM_ERR_HIP;
+        return IVM_OK;
+    }
+    if (launch_candidates_offsets(n_snap, max_order, d_counts, d_offsets, stream) != hipSuccess) return IVM_ERR_HIP;
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, d_offsets + (size_t)n_snap * max_order, sizeof(total), hipMemcpyDeviceToHost,
+                       stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return IVM_ERR_HIP;
+    if ((size_t)total > paths_cap) return IVM_ERR_CAPACITY;
+    if (launch_candidates_fill(d, d_M, n_snap, d_tx_vis, d_rx_vis, max_order, d_offsets, d_paths, stream) !=
+        hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_triangle_groups(const ivm_scene *scene, int32_t *d_group, hipStream_t stream) {
+    if (!scene || (!d_group && scene->s.dev.T > 0)) return IVM_ERR_INVALID_ARGUMENT;
+    if (launch_triangle_groups(scene->s.dev, d_group, stream) != hipSuccess) return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// ivm_internal.h -- device data layout and launchers shared by the libivm
+// translation units.  Not part of the public interface (see include/ivm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ivm.h"
+
+namespace ivm {
+
+constexpr int kWave = 64;
+constexpr int kTreelets = 32;      // top-level subtrees: contiguous equal-count Morton ranges
+constexpr int kLeafMax = 4;        // subtrees of <= kLeafMax triangles become leaves
+constexpr int kDefaultStack = 24;
+constexpr int kMaxSamplesPerFacet = 64;
+constexpr float kDefaultEps = 1e-5f;
+
+// Status bits raised on the device, mapped to ivm_status by the host.
+constexpr int kStGrid = 1;
+constexpr int kStDegenerate = 2;
+constexpr int kStInvalid = 4;
+
+// Node of a binary BVH whose boxes live in the parent (one 64-byte record):
+//   a = (lo0.x, lo0.y, lo0.z, hi0.x), b = (hi0.y, hi0.z, lo1.x, lo1.y),
+//   c = (lo1.z, hi1.x, hi1.y, hi1.z), d = (ref0, ref1, first, last).
+// ref >= 0 is an internal node; ref < 0 is a leaf holding the sorted triangle
+// ranks [first, first + count) encoded as ~((first << 3) | (count - 1)).
+// first/last is the node's own sorted-rank range (used by the overflow scan).
+struct __align__(16) Node {
+    float4 a, b, c;
+    int4 d;
+};
+
+__host__ __device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }
+__host__ __device__ inline int leaf_first(int ref) { return (~ref) >> 3; }
+__host__ __device__ inline int leaf_count(int ref) { return ((~ref) & 7) + 1; }
+
+// Triangle record in sorted (Morton) order, three float4:
+//   [0] = (a.x, a.y, a.z, facet id as int bits)
+//   [1] = (e1 = b - a, max |e1_k|)
+//   [2] = (e2 = c - a, max |e2_k|)
+// All components are exact: vertices sit on a dyadic grid.
+
+// Device view of a built scene (passed by value to kernels).
+struct SceneDev {
+    int F, T, S, W, n_treelets, max_spf;
+    int g, gs;                 // grid exponents (vertex, sample)
+    const float4 *tri;         // 3 * T
+    const int *tri_orig;       // sorted rank -> caller's triangle index
+    const int *tri_group;      // caller's triangle index -> treelet
+    const Node *nodes;         // T (internal nodes at global slots)
+    const float *tl_box;       // kTreelets * 6 (lo.xyz, hi.xyz)
+    const int *tl_root;        // kTreelets root refs (0x7fffffff = empty)
+    const double *fplane;      // F * 6: a.xyz, n.xyz
+    const float *fbox;         // F * 6
+    const int *soff;           // F + 1
+    const float4 *smp;         // S
+    const int *sfacet;         // S
+    int *status;               // device status bits
+    const double *extent;      // [0..5] = sample-unit integer box of vertices+samples as doubles; [6] = E
+};
+
+// Workspace layout of one scene.
+struct Layout {
+    size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
+    size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
+    size_t ffirst, cand, prefix, queue, learned, scan_tmp;
+    size_t learned_bytes;
+    size_t total;
+};
+Layout make_layout(int F, int T, int S, bool learned);
+
+// Opaque handle behind ivm_scene.
+struct Scene {
+    ivm_scene_desc desc;
+    void *ws;
+    size_t ws_bytes;
+    Layout lay;
+    SceneDev dev;
+    hipStream_t build_stream;
+    int n_items;               // F * W pair-cull items
+    struct Model *model;       // optional occluder-ordering network
+};
+
+struct TraverseOpts {
+    int order_mode;
+    int fp64_only;
+    int stack_depth;
+    float eps6;                // 6 * eps: margin factor of the FP32 filter
+    int grid_blocks;
+};
+
+// Launchers (each returns hipSuccess or the launch error).
+hipError_t launch_build(Scene &sc, hipStream_t s);
+hipError_t launch_matrix(Scene &sc, const TraverseOpts &o, uint64_t *M, ivm_stats *stats,
+                         const uint8_t *learned_order, hipStream_t s);
+hipError_t launch_points(Scene &sc, const TraverseOpts &o, int N, const float *tx, const float *rx,
+                         uint64_t *txv, uint64_t *rxv, uint8_t *los, ivm_stats *stats, hipStream_t s);
+hipError_t launch_candidates_count(const SceneDev &d, const uint64_t *M, int N, const uint64_t *txv,
+                                   const uint64_t *rxv, const uint8_t *los, int K, int64_t *counts,
+                                   hipStream_t s);
+hipError_t launch_candidates_offsets(int N, int K, const int64_t *counts, int64_t *offsets,
+                                     hipStream_t s);
+hipError_t launch_candidates_fill(const SceneDev &d, const uint64_t *M, int N, const uint64_t *txv,
+                                  const uint64_t *rxv, int K, const int64_t *offsets, int32_t *paths,
+                                  hipStream_t s);
+hipError_t launch_triangle_groups(const SceneDev &d, int32_t *group, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace ivm

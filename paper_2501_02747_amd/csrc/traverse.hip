@@ -1,0 +1,708 @@
+// traverse.hip -- the inter-visibility hot path on gfx950.
+//
+//   k_cull     exact orientation cull of every unordered facet pair (Section II-B,
+//              eq. 2): a pair is a candidate iff some sample of i lies on j's
+//              visible side and some sample of j on i's.  One wave per 64
+//              pairs of a row; the ballot is the 64-bit candidate word.
+//   scan       exclusive prefix over per-word candidate counts: a dense index
+//              for the persistent queue.
+//   k_pairs    persistent any-hit kernel: each wave takes one candidate pair
+//              from an atomic queue, compacts the admissible samples into LDS,
+//              and tests the segments 64 at a time (one per lane) against the
+//              LBVH until one is clear (Section II-B: no other obstacle between
+//              the faces) or all are blocked.  Per-lane DFS with an LDS stack;
+//              leaf tests in FP32 with a semi-static error filter, undecided
+//              tests redone in FP64 (exact on the dyadic grid).
+//   k_points   the same any-hit core for Tx/Rx -> facet-sample segments
+//              (Section III-B, Table II), plus line of sight.
+#include <cmath>
+
+#include "ivm_internal.h"
+
+namespace ivm {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ inline float wave_min(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline float wave_max(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// orient(f, x) = (x - a_f) . n_f in FP64 (exact on the grid).
+__device__ inline double orient(const double *pl, float x, float y, float z) {
+    return ((double)x - pl[0]) * pl[3] + ((double)y - pl[1]) * pl[4] + ((double)z - pl[2]) * pl[5];
+}
+
+// ---------------------------------------------------------------------------
+// segment, box and triangle predicates
+// ---------------------------------------------------------------------------
+
+struct Seg {
+    float px, py, pz;   // origin
+    float dx, dy, dz;   // q - p (exact on the grid)
+    float ix, iy, iz;   // 1 / d (0 where d = 0)
+    float dm;           // max |d_k|
+};
+
+__device__ inline Seg make_seg(float px, float py, float pz, float qx, float qy, float qz) {
+    Seg s;
+    s.px = px; s.py = py; s.pz = pz;
+    s.dx = qx - px; s.dy = qy - py; s.dz = qz - pz;
+    s.ix = s.dx != 0.f ? 1.0f / s.dx : 0.f;
+    s.iy = s.dy != 0.f ? 1.0f / s.dy : 0.f;
+    s.iz = s.dz != 0.f ? 1.0f / s.dz : 0.f;
+    s.dm = fmaxf(fabsf(s.dx), fmaxf(fabsf(s.dy), fabsf(s.dz)));
+    return s;
+}
+
+// Conservative slab test of the segment p + t d, t in [0, 1], against a closed
+// box.  Box minus origin is exact; each slab parameter carries <= ~3 ulp of
+// relative error, so widening the exit by 2^-20 never rejects a box the exact
+// segment meets.  Axes with d = 0 are decided exactly by containment.
+constexpr float kWiden = 1.00000095367431640625f;  // 1 + 2^-20
+
+__device__ inline bool seg_box(const Seg &s, float lx, float ly, float lz, float hx, float hy, float hz,
+                               float &tentry) {
+    float t0 = 0.0f, t1 = 1.0f;
+    bool out = false;
+    if (s.dx != 0.f) {
+        float a = (lx - s.px) * s.ix, b = (hx - s.px) * s.ix;
+        t0 = fmaxf(t0, fminf(a, b));
+        t1 = fminf(t1, fmaxf(a, b));
+    } else {
+        out |= (s.px < lx) | (s.px > hx);
+    }
+    if (s.dy != 0.f) {
+        float a = (ly - s.py) * s.iy, b = (hy - s.py) * s.iy;
+        t0 = fmaxf(t0, fminf(a, b));
+        t1 = fminf(t1, fmaxf(a, b));
+    } else {
+        out |= (s.py < ly) | (s.py > hy);
+    }
+    if (s.dz != 0.f) {
+        float a = (lz - s.pz) * s.iz, b = (hz - s.pz) * s.iz;
+        t0 = fmaxf(t0, fminf(a, b));
+        t1 = fminf(t1, fmaxf(a, b));
+    } else {
+        out |= (s.pz < lz) | (s.pz > hz);
+    }
+    tentry = t0;
+    return !out && (t0 <= t1 * kWiden);
+}
+
+// Exact test in FP64 (division-free Moller-Trumbore, closed triangle, open
+// segment; a segment parallel to the plane never hits).
+__device__ __noinline__ bool tri_hit_f64(const Seg &s, float4 A, float4 B, float4 C) {
+    const double dx = s.dx, dy = s.dy, dz = s.dz;
+    const double ex = B.x, ey = B.y, ez = B.z;   // e1
+    const double fx = C.x, fy = C.y, fz = C.z;   // e2
+    const double sx = (double)s.px - (double)A.x, sy = (double)s.py - (double)A.y, sz = (double)s.pz - (double)A.z;
+    const double hx = dy * fz - dz * fy, hy = dz * fx - dx * fz, hz = dx * fy - dy * fx;
+    const double det = ex * hx + ey * hy + ez * hz;
+    if (det == 0.0) return false;
+    const double u = sx * hx + sy * hy + sz * hz;
+    const double gx = sy * ez - sz * ey, gy = sz * ex - sx * ez, gz = sx * ey - sy * ex;
+    const double v = dx * gx + dy * gy + dz * gz;
+    const double t = fx * gx + fy * gy + fz * gz;
+    if (det > 0.0) return u >= 0.0 && v >= 0.0 && u + v <= det && t > 0.0 && t < det;
+    return u <= 0.0 && v <= 0.0 && u + v >= det && t < 0.0 && t > det;
+}
+
+// FP32 test with a semi-static filter.  With D = max|d_k|, S = max|s_k|,
+// E1 = max|e1_k|, E2 = max|e2_k|, the magnitudes of det, u, v, t are bounded
+// by 6 D E1 E2, 6 S D E2, 6 D S E1, 6 E2 S E1 and the FP32 rounding error of
+// each quantity (and of det-u-v, det-t) stays below 8 * 2^-24 of its bound.
+// A comparison is trusted when its value clears eps6/6 (>= 1e-5, i.e. >= 20x
+// the error) times that bound; otherwise the whole test is redone in FP64.
+// Returns 1 hit, 0 miss; counts rechecks.
+__device__ inline bool tri_hit(const Seg &s, float4 A, float4 B, float4 C, float eps6, bool f64only,
+                               unsigned &rechecks) {
+    if (f64only) return tri_hit_f64(s, A, B, C);
+    const float sx = s.px - A.x, sy = s.py - A.y, sz = s.pz - A.z;  // exact
+    const float hx = s.dy * C.z - s.dz * C.y;
+    const float hy = s.dz * C.x - s.dx * C.z;
+    const float hz = s.dx * C.y - s.dy * C.x;
+    const float det = B.x * hx + B.y * hy + B.z * hz;
+    const float mdet = eps6 * s.dm * B.w * C.w;
+    if (!(fabsf(det) > mdet)) {
+        ++rechecks;
+        return tri_hit_f64(s, A, B, C);
+    }
+    const float sg = det > 0.f ? 1.f : -1.f;
+    const float S = fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz)));
+    const float u = (sx * hx + sy * hy + sz * hz) * sg;
+    const float mu = eps6 * S * s.dm * C.w;
+    if (u < -mu) return false;
+    const float gx = sy * B.z - sz * B.y;
+    const float gy = sz * B.x - sx * B.z;
+    const float gz = sx * B.y - sy * B.x;
+    const float v = (s.dx * gx + s.dy * gy + s.dz * gz) * sg;
+    const float mv = eps6 * s.dm * S * B.w;
+    if (v < -mv) return false;
+    const float adet = fabsf(det);
+    const float w = adet - u - v;
+    const float mw = mdet + mu + mv;
+    if (w < -mw) return false;
+    const float t = (C.x * gx + C.y * gy + C.z * gz) * sg;
+    const float mt = eps6 * C.w * S * B.w;
+    if (t < -mt) return false;
+    const float x = adet - t;
+    const float mx = mdet + mt;
+    if (x < -mx) return false;
+    if (u > mu && v > mv && w > mw && t > mt && x > mx) return true;
+    ++rechecks;
+    return tri_hit_f64(s, A, B, C);
+}
+
+struct Cnt {
+    unsigned visits = 0, tests = 0, rechecks = 0, fallbacks = 0;
+};
+
+__device__ inline bool test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
+                                  float eps6, bool f64, Cnt &c) {
+    for (int r = first; r < first + count; ++r) {
+        const float4 A = sc.tri[3 * r];
+        const int f = __float_as_int(A.w);
+        if (f == exA || f == exB) continue;
+        ++c.tests;
+        if (tri_hit(s, A, sc.tri[3 * r + 1], sc.tri[3 * r + 2], eps6, f64, c.rechecks)) return true;
+    }
+    return false;
+}
+
+constexpr int kNone = 0x7fffffff;
+
+// Any-hit traversal of one segment.  `order` lists treelets to visit (LDS or
+// constant memory); `stk` is this lane's LDS stack with a stride of one wave.
+// When the stack is full the far child's whole subtree is scanned linearly
+// (its triangles are a contiguous sorted range), so no node is ever dropped.
+template <typename OrderPtr>
+__device__ bool any_hit(const SceneDev &sc, const Seg &s, int exA, int exB, OrderPtr order, int n_order, int *stk,
+                        int depth, float eps6, bool f64, Cnt &c) {
+    int r = 0, sp = 0;
+    int ref = kNone;
+    while (true) {
+        if (ref == kNone) {
+            if (sp > 0) {
+                ref = stk[(--sp) * kWave];
+            } else {
+                while (r < n_order) {
+                    const int k = order[r++];
+                    const int root = sc.tl_root[k];
+                    if (root == kNone) continue;  // empty treelet: its inverted box must never be entered
+                    const float *b = sc.tl_box + 6 * k;
+                    float te;
+                    if (seg_box(s, b[0], b[1], b[2], b[3], b[4], b[5], te)) {
+                        ref = root;
+                        break;
+                    }
+                }
+                if (ref == kNone) return false;
+            }
+        }
+        if (ref >= 0) {
+            ++c.visits;
+            const Node nd = sc.nodes[ref];
+            float t0, t1;
+            const bool h0 = seg_box(s, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, t0);
+            const bool h1 = seg_box(s, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, t1);
+            if (h0 && h1) {
+                const int nearc = t0 <= t1 ? nd.d.x : nd.d.y;
+                const int farc = t0 <= t1 ? nd.d.y : nd.d.x;
+                if (sp < depth) {
+                    stk[(sp++) * kWave] = farc;
+                } else {
+                    ++c.fallbacks;
+                    int first, count;
+                    if (farc < 0) {
+                        first = leaf_first(farc);
+                        count = leaf_count(farc);
+                    } else {
+                        const int4 rg = sc.nodes[farc].d;
+                        first = rg.z;
+                        count = rg.w - rg.z + 1;
+                    }
+                    if (test_range(sc, s, first, count, exA, exB, eps6, f64, c)) return true;
+                }
+                ref = nearc;
+            } else if (h0) {
+                ref = nd.d.x;
+            } else if (h1) {
+                ref = nd.d.y;
+            } else {
+                ref = kNone;
+            }
+        } else {
+            if (test_range(sc, s, leaf_first(ref), leaf_count(ref), exA, exB, eps6, f64, c)) return true;
+            ref = kNone;
+        }
+    }
+}
+
+// Per-wave treelet order.  Lane k < 32 holds a 64-bit key for treelet k
+// (UINT64_MAX = skip); the wave ranks the keys (index breaks ties) into
+// order[0..n).  Returns n.
+__device__ inline int wave_rank_order(unsigned long long key, unsigned long long *skey, uint8_t *order) {
+    const int lane = lane_id();
+    if (lane < kTreelets) skey[lane] = key;
+    wave_sync();
+    const bool valid = lane < kTreelets && key != ~0ull;
+    if (valid) {
+        int rank = 0;
+        for (int m = 0; m < kTreelets; ++m) {
+            const unsigned long long km = skey[m];
+            rank += (km < key) || (km == key && m < lane);
+        }
+        order[rank] = (uint8_t)lane;
+    }
+    const int n = __popcll(__ballot(valid));
+    wave_sync();
+    return n;
+}
+
+// Key of treelet `lane` for a segment bundle with box [lo, hi]: treelets whose
+// box misses the bundle box cannot hold a hit and are skipped.
+__device__ inline unsigned long long treelet_key(const SceneDev &sc, int lane, const float lo[3], const float hi[3],
+                                                 int mode, unsigned long long learned_code) {
+    if (lane >= kTreelets || sc.tl_root[lane] == kNone) return ~0ull;
+    const float *b = sc.tl_box + 6 * lane;
+    if (b[0] > hi[0] || b[3] < lo[0] || b[1] > hi[1] || b[4] < lo[1] || b[2] > hi[2] || b[5] < lo[2]) return ~0ull;
+    float d2 = 0.f;
+    for (int k = 0; k < 3; ++k) {
+        const float c = 0.5f * (b[k] + b[3 + k]) - 0.5f * (lo[k] + hi[k]);
+        d2 += c * c;
+    }
+    const unsigned dk = __float_as_uint(d2);  // non-negative: bit order = value order
+    if (mode == IVM_ORDER_INDEX) return (unsigned long long)lane;
+    if (mode == IVM_ORDER_REVERSED) return (unsigned long long)(0xffffffffu - dk);
+    if (mode == IVM_ORDER_LEARNED) {
+        // learned_code: up to 12 treelet ids, 5 bits each, best first (31 = unused slot
+        // only when fewer than 12 are listed, since 31 is also a valid id, a count in
+        // the top 4 bits says how many are listed).
+        const int listed = (int)(learned_code >> 60);
+        for (int m = 0; m < listed && m < 12; ++m)
+            if ((int)((learned_code >> (5 * m)) & 31) == lane) return (unsigned long long)m << 32;
+        return (1ull << 40) | dk;
+    }
+    return dk;
+}
+
+// ---------------------------------------------------------------------------
+// pair cull and scan
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_cull(SceneDev sc, uint64_t *cand, uint32_t *counts, int n_items) {
+    const int lane = lane_id();
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int item = wave; item < n_items; item += nwaves) {
+        const int i = item / sc.W, w = item - (item / sc.W) * sc.W;
+        const int j = w * 64 + lane;
+        bool ok = false;
+        if (w * 64 + 63 > i && j > i && j < sc.F) {
+            const double *pi = sc.fplane + 6 * i, *pj = sc.fplane + 6 * j;
+            bool a = false;
+            for (int s = sc.soff[i]; s < sc.soff[i + 1] && !a; ++s) {
+                const float4 p = sc.smp[s];
+                a = orient(pj, p.x, p.y, p.z) > 0.0;
+            }
+            if (a) {
+                for (int s = sc.soff[j]; s < sc.soff[j + 1] && !ok; ++s) {
+                    const float4 q = sc.smp[s];
+                    ok = orient(pi, q.x, q.y, q.z) > 0.0;
+                }
+            }
+        }
+        const unsigned long long m = __ballot(ok);
+        if (lane == 0) {
+            cand[item] = m;
+            counts[item] = (uint32_t)__popcll(m);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[n_items] = 0;
+}
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kScanThreads * kScanPer;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        uint32_t x = tid >= off ? sh[tid - off] : 0u;
+        __syncthreads();
+        sh[tid] += x;
+        __syncthreads();
+    }
+    uint32_t incl = sh[tid];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(uint32_t *a, int n, uint32_t *bsum) {
+    __shared__ uint32_t sh[kScanThreads];
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    uint32_t v[kScanPer], s = 0;
+    for (int m = 0; m < kScanPer; ++m) {
+        v[m] = base + m < n ? a[base + m] : 0u;
+        s += v[m];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(s, sh, &tot);
+    for (int m = 0; m < kScanPer; ++m) {
+        if (base + m < n) a[base + m] = ex;
+        ex += v[m];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t *bsum, int nb) {
+    __shared__ uint32_t sh[kScanThreads];
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kScanThreads) {
+        const int i = base + threadIdx.x;
+        uint32_t v = i < nb ? bsum[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(v, sh, &tot);
+        if (i < nb) bsum[i] = ex + carry;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_add(uint32_t *a, int n, const uint32_t *bsum) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += bsum[i / kScanBlock];
+}
+
+static hipError_t exclusive_scan_u32(uint32_t *a, int n, uint32_t *tmp, hipStream_t s) {
+    const int nb = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kScanThreads), 0, s, a, n, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, s, a, n, (const uint32_t *)tmp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// persistent pair kernel
+// ---------------------------------------------------------------------------
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+__device__ inline void flush_counters(ivm_stats *st, const Cnt &c, unsigned long long segs,
+                                      unsigned long long visible, unsigned long long items) {
+    if (!st) return;
+    const unsigned long long v = wave_sum_u64(c.visits), t = wave_sum_u64(c.tests);
+    const unsigned long long r = wave_sum_u64(c.rechecks), f = wave_sum_u64(c.fallbacks);
+    const unsigned long long sg = wave_sum_u64(segs);
+    if (lane_id() == 0) {
+        atomicAdd((unsigned long long *)&st->node_visits, v);
+        atomicAdd((unsigned long long *)&st->tri_tests, t);
+        atomicAdd((unsigned long long *)&st->rechecks, r);
+        atomicAdd((unsigned long long *)&st->fallbacks, f);
+        atomicAdd((unsigned long long *)&st->segments, sg);
+        if (visible) atomicAdd((unsigned long long *)&st->pairs_visible, visible);
+        if (items) atomicAdd((unsigned long long *)&st->point_items, items);
+    }
+}
+
+__device__ inline int find_item(const uint32_t *prefix, int n_items, uint32_t g) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, const uint32_t *prefix, int n_items,
+                                   uint32_t g, int &i, int &j) {
+    const int item = find_item(prefix, n_items, g);
+    unsigned long long m = cand[item];
+    for (uint32_t q = prefix[item]; q < g; ++q) m &= m - 1;
+    const int bit = __ffsll((long long)m) - 1;
+    i = item / sc.W;
+    j = (item - i * sc.W) * 64 + bit;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *cand, const uint32_t *prefix,
+                                                  int n_items, uint32_t *queue, uint64_t *M, TraverseOpts o,
+                                                  ivm_stats *st, const uint64_t *learned) {
+    __shared__ float4 sP[kWavesPerBlock][kWave];
+    __shared__ float4 sQ[kWavesPerBlock][kWave];
+    __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
+    __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
+    __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t total = prefix[n_items];
+    int *stk = &sStack[wv][lane];
+    const bool f64 = o.fp64_only != 0;
+    Cnt c;
+    unsigned long long segs = 0, nvis = 0;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    while (true) {
+        uint32_t g = 0;
+        if (lane == 0) g = atomicAdd(queue, 1u);
+        g = __shfl(g, 0);
+        if (g >= total) break;
+        int i, j;
+        decode_pair(sc, cand, prefix, n_items, g, i, j);
+        const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
+        const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
+        const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
+        const float4 p = lane < ni ? sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
+        const float4 q = lane < nj ? sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
+        const bool okp = lane < ni && orient(plj, p.x, p.y, p.z) > 0.0;
+        const bool okq = lane < nj && orient(pli, q.x, q.y, q.z) > 0.0;
+        const unsigned long long mp = __ballot(okp), mq = __ballot(okq);
+        const int np = __popcll(mp), nq = __popcll(mq);
+        if (okp) sP[wv][__popcll(mp & lt)] = p;
+        if (okq) sQ[wv][__popcll(mq & lt)] = q;
+        // bounding box of every admissible segment
+        float lo[3], hi[3];
+        {
+            const float big = INFINITY;
+            float l0 = big, l1 = big, l2 = big, h0 = -big, h1 = -big, h2 = -big;
+            if (okp) { l0 = p.x; l1 = p.y; l2 = p.z; h0 = p.x; h1 = p.y; h2 = p.z; }
+            if (okq) {
+                l0 = fminf(l0, q.x); l1 = fminf(l1, q.y); l2 = fminf(l2, q.z);
+                h0 = fmaxf(h0, q.x); h1 = fmaxf(h1, q.y); h2 = fmaxf(h2, q.z);
+            }
+            lo[0] = wave_min(l0); lo[1] = wave_min(l1); lo[2] = wave_min(l2);
+            hi[0] = wave_max(h0); hi[1] = wave_max(h1); hi[2] = wave_max(h2);
+        }
+        unsigned long long lcode = 0;
+        if (o.order_mode == IVM_ORDER_LEARNED && learned) lcode = learned[g];
+        const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
+        const int nseg = np * nq;
+        bool vis = false;
+        for (int base = 0; base < nseg; base += kWave) {
+            const int sidx = base + lane;
+            bool clear = false;
+            if (sidx < nseg) {
+                const int a = sidx / nq, b = sidx - (sidx / nq) * nq;
+                const float4 P = sP[wv][a], Q = sQ[wv][b];
+                const Seg s = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+                ++segs;
+                clear = !any_hit(sc, s, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+            }
+            if (__ballot(clear)) {
+                vis = true;
+                break;
+            }
+        }
+        if (vis && lane == 0) {
+            atomicOr((unsigned long long *)&M[(size_t)i * sc.W + (j >> 6)], 1ull << (j & 63));
+            atomicOr((unsigned long long *)&M[(size_t)j * sc.W + (i >> 6)], 1ull << (i & 63));
+            ++nvis;
+        }
+        wave_sync();
+    }
+    flush_counters(st, c, segs, nvis, 0);
+}
+
+__global__ void k_pair_stats(ivm_stats *st, const uint32_t *prefix, int n_items, int F) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && st) {
+        atomicAdd((unsigned long long *)&st->pairs_candidate, (unsigned long long)prefix[n_items]);
+        atomicAdd((unsigned long long *)&st->pairs_total, (unsigned long long)F * (F - 1) / 2);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    unsigned b = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u32, dim3(b > 4096 ? 4096 : b), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    unsigned b = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u64, dim3(b > 4096 ? 4096 : b), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+int device_cu_count() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_stats *stats,
+                         const uint8_t * /*unused*/, hipStream_t s) {
+    const SceneDev &sc = scn.dev;
+    char *ws = (char *)scn.ws;
+    const Layout &L = scn.lay;
+    uint64_t *cand = (uint64_t *)(ws + L.cand);
+    uint32_t *prefix = (uint32_t *)(ws + L.prefix);
+    uint32_t *queue = (uint32_t *)(ws + L.queue);
+    const int n_items = scn.n_items;
+    hipError_t e;
+    if ((e = launch_fill_u64(M, 0ull, (size_t)sc.F * sc.W, s)) != hipSuccess) return e;
+    if (sc.F < 2) return hipSuccess;
+    if ((e = launch_fill_u32(queue, 0u, 64, s)) != hipSuccess) return e;
+    {
+        const int waves = n_items;
+        const unsigned blocks = (unsigned)((waves + 3) / 4);
+        hipLaunchKernelGGL(k_cull, dim3(blocks > 65535u ? 65535u : blocks), dim3(256), 0, s, sc, cand, prefix, n_items);
+    }
+    if ((e = exclusive_scan_u32(prefix, n_items + 1, (uint32_t *)(ws + L.scan_tmp), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_stats, dim3(1), dim3(64), 0, s, stats, (const uint32_t *)prefix, n_items, sc.F);
+    const uint64_t *learned = (o.order_mode == IVM_ORDER_LEARNED && L.learned_bytes) ? (const uint64_t *)(ws + L.learned)
+                                                                                      : nullptr;
+    hipLaunchKernelGGL(k_pairs, dim3(o.grid_blocks), dim3(kBlock), 0, s, sc, (const uint64_t *)cand,
+                       (const uint32_t *)prefix, n_items, queue, M, o, stats, learned);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tx/Rx points and line of sight
+// ---------------------------------------------------------------------------
+
+__constant__ uint8_t kIdentOrder[kTreelets] = {0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13, 14, 15,
+                                               16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
+
+// Items are (snapshot, side, chunk of 64 consecutive samples); lane = sample.
+__global__ __launch_bounds__(kBlock) void k_points(SceneDev sc, int N, const float *tx, const float *rx, uint64_t *txv,
+                                                   uint64_t *rxv, TraverseOpts o, ivm_stats *st) {
+    __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
+    __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
+    __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    int *stk = &sStack[wv][lane];
+    const bool f64 = o.fp64_only != 0;
+    const int nch = (sc.S + kWave - 1) / kWave;
+    const long long n_items = (long long)N * 2 * nch;
+    const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    Cnt c;
+    unsigned long long segs = 0, items = 0;
+    for (long long it = wave; it < n_items; it += nwaves) {
+        const int n = (int)(it / (2 * nch));
+        const int rem = (int)(it - (long long)n * 2 * nch);
+        const int side = rem / nch, chunk = rem - side * nch;
+        const float *X = (side ? rx : tx) + 3 * n;
+        uint64_t *out = (side ? rxv : txv) + (size_t)n * sc.W;
+        const float xx = X[0], xy = X[1], xz = X[2];
+        const int sidx = chunk * kWave + lane;
+        bool act = sidx < sc.S;
+        int f = 0;
+        float4 P = make_float4(0, 0, 0, 0);
+        if (act) {
+            f = sc.sfacet[sidx];
+            P = sc.smp[sidx];
+            act = orient(sc.fplane + 6 * f, xx, xy, xz) > 0.0;
+        }
+        if (!__ballot(act)) continue;
+        ++items;
+        float lo[3], hi[3];
+        {
+            const float big = INFINITY;
+            lo[0] = fminf(xx, wave_min(act ? P.x : big));
+            lo[1] = fminf(xy, wave_min(act ? P.y : big));
+            lo[2] = fminf(xz, wave_min(act ? P.z : big));
+            hi[0] = fmaxf(xx, wave_max(act ? P.x : -big));
+            hi[1] = fmaxf(xy, wave_max(act ? P.y : -big));
+            hi[2] = fmaxf(xz, wave_max(act ? P.z : -big));
+        }
+        const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode == IVM_ORDER_LEARNED
+                                                                                ? IVM_ORDER_PLAIN
+                                                                                : o.order_mode, 0ull),
+                                            sKey[wv], sOrder[wv]);
+        bool clear = false;
+        if (act) {
+            const Seg s = make_seg(xx, xy, xz, P.x, P.y, P.z);
+            ++segs;
+            clear = !any_hit(sc, s, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+        }
+        if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+        wave_sync();
+    }
+    flush_counters(st, c, segs, 0, items);
+}
+
+__global__ __launch_bounds__(kBlock) void k_los(SceneDev sc, int N, const float *tx, const float *rx, uint8_t *los,
+                                                TraverseOpts o) {
+    __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    Cnt c;
+    if (n < N) {
+        const Seg s = make_seg(tx[3 * n], tx[3 * n + 1], tx[3 * n + 2], rx[3 * n], rx[3 * n + 1], rx[3 * n + 2]);
+        const bool hit = any_hit(sc, s, -1, -1, kIdentOrder, kTreelets, &sStack[wv][lane], o.stack_depth, o.eps6,
+                                 o.fp64_only != 0, c);
+        los[n] = hit ? 0 : 1;
+    }
+}
+
+// On-grid and exactness-budget check of Tx/Rx positions (see ivm.h).
+__global__ void k_check_points(SceneDev sc, int N, const float *tx, const float *rx) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= 2 * N) return;
+    const float *X = (id < N ? tx + 3 * id : rx + 3 * (id - N));
+    const double sscale = ldexp(1.0, sc.gs);
+    double D = 0.0;
+    int bad = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double y = (double)X[k] * sscale;
+        if (!(fabs(y) < 16777216.0) || y != floor(y)) bad |= kStGrid;
+        const double lo = fmin(sc.extent[k], y), hi = fmax(sc.extent[3 + k], y);
+        D = fmax(D, (hi - lo) / sscale);
+    }
+    const double E = sc.extent[6];
+    const int g = sc.g, kk = sc.gs - sc.g;
+    const double bound = (6.0 * D * E * E + 12.0 * D * D * E) * ldexp(1.0, 3 * g + 2 * kk);
+    if (!(bound < 9007199254740992.0) || !(D * sscale < 16777216.0)) bad |= kStGrid;
+    if (bad) atomicOr(sc.status, bad);
+}
+
+hipError_t launch_points(Scene &scn, const TraverseOpts &o, int N, const float *tx, const float *rx, uint64_t *txv,
+                         uint64_t *rxv, uint8_t *los, ivm_stats *stats, hipStream_t s) {
+    const SceneDev &sc = scn.dev;
+    hipError_t e;
+    if ((e = launch_fill_u64(txv, 0ull, (size_t)N * sc.W, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(rxv, 0ull, (size_t)N * sc.W, s)) != hipSuccess) return e;
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_points, dim3((2 * N + 255) / 256), dim3(256), 0, s, sc, N, tx, rx);
+    if (sc.S > 0 && sc.F > 0)
+        hipLaunchKernelGGL(k_points, dim3(o.grid_blocks), dim3(kBlock), 0, s, sc, N, tx, rx, txv, rxv, o, stats);
+    hipLaunchKernelGGL(k_los, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, N, tx, rx, los, o);
+    return hipGetLastError();
+}
+
+}  // namespace ivm

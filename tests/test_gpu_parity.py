@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, bit for bit.
+
+Every result here is integer (visibility bits, counts, index lists), so the bar
+is exact equality.  Inputs are seeded synthetic scenes from scenegen; expected
+values come only from oracle/.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ivm():
+    import torch
+    import paper_2501_02747_amd as ivm
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    ivm.load_library()
+    return ivm
+
+
+def _run_all(ivm, scene, opts=None, K=2, lists=True):
+    import torch
+    g = ivm.GpuScene.from_scene(scene).check()
+    M = ivm.ivm_intervisibility_matrix(g, opts)
+    tx = torch.as_tensor(scene.tx).cuda()
+    rx = torch.as_tensor(scene.rx).cuda()
+    tv, rv, los = ivm.ivm_txrx_visibility_table(g, tx, rx, opts)
+    out = {"scene": g, "M": M, "tv": tv, "rv": rv, "los": los}
+    if lists:
+        out["counts"], out["offsets"], out["paths"] = ivm.ivm_image_tree_candidates(g, M, tv, rv, los, K, lists=True)
+    else:
+        out["counts"] = ivm.ivm_image_tree_candidates(g, M, tv, rv, los, K)
+    torch.cuda.synchronize()
+    assert g.status() == 0
+    return out
+
+
+def _assert_matrix(ivm, Mg, Mo, F):
+    got = ivm.unpack_bits(Mg, F)
+    if not (got == Mo).all():
+        bad = np.argwhere(got != Mo)
+        raise AssertionError(f"{len(bad)} matrix bits differ, first {bad[:5].tolist()} "
+                             f"gpu={got[tuple(bad[0])]} oracle={Mo[tuple(bad[0])]}")
+    words = Mg.cpu().numpy().view(np.uint64)
+    if F % 64:
+        assert not (words[:, -1] >> np.uint64(F % 64)).any(), "padding bits must be zero"
+
+
+def _check_lists(out, lists, N, K):
+    off = out["offsets"].cpu().numpy()
+    paths = out["paths"].cpu().numpy()
+    for n in range(N):
+        for k in range(1, K + 1):
+            a, b = off[n * K + k - 1], off[n * K + k]
+            got = [tuple(int(x) for x in paths[p:p + k]) for p in range(a, b, k)]
+            assert got == lists[n][k - 1], (n, k)
+
+
+@pytest.mark.parametrize("seed", list(range(1, 33)))
+def test_c1_full_parity(oracle_mod, ivm, seed):
+    """Tiny urban scene (42 facets, 84 triangles, 4x4 samples, 10 snapshots): matrix,
+    Tx/Rx tables, LoS, candidate counts and lists up to order 2, all bit-exact."""
+    _log(f"[c1 parity] seed={seed}")
+    s = sg.gen_c1(seed)
+    orc = oracle_mod.Oracle(s)
+    Mo, mism = orc.matrix(audit=True)
+    assert mism == 0
+    tvo, rvo, loso = orc.txrx(s.tx, s.rx)
+    co, lists = oracle_mod.candidates_enum(Mo, tvo, rvo, loso, 2)
+    for fp64 in (False, True):
+        out = _run_all(ivm, s, ivm.make_opts(fp64_only=fp64))
+        _assert_matrix(ivm, out["M"], Mo, s.n_facets)
+        assert (ivm.unpack_bits(out["tv"], s.n_facets) == tvo).all()
+        assert (ivm.unpack_bits(out["rv"], s.n_facets) == rvo).all()
+        assert (out["los"].cpu().numpy().astype(bool) == loso).all()
+        assert (out["counts"].cpu().numpy() == co).all()
+        _check_lists(out, lists, s.n_snapshots, 2)
+
+
+@pytest.mark.parametrize("nx,ny", [(4, 5), (5, 6)])
+def test_urban_grid_medium_full_parity(oracle_mod, ivm, nx, ny):
+    """Manhattan-grid generator at 200 and 300 facets (8x8 samples: 4096 segments per
+    pair, several 64-facet row words with a ragged tail): everything bit-exact."""
+    _log(f"[medium parity] {nx}x{ny}")
+    s = sg.gen_c2(2, n_snap=40, nx=nx, ny=ny)
+    orc = oracle_mod.Oracle(s)
+    Mo, _ = orc.matrix()
+    tvo, rvo, loso = orc.txrx(s.tx, s.rx)
+    co = oracle_mod.candidates_matmul(Mo, tvo, rvo, loso, 2)
+    out = _run_all(ivm, s, lists=False)
+    _assert_matrix(ivm, out["M"], Mo, s.n_facets)
+    assert (ivm.unpack_bits(out["tv"], s.n_facets) == tvo).all()
+    assert (ivm.unpack_bits(out["rv"], s.n_facets) == rvo).all()
+    assert (out["los"].cpu().numpy().astype(bool) == loso).all()
+    assert (out["counts"].cpu().numpy() == co).all()
+
+
+@pytest.mark.parametrize("mode,fp64,stack,eps", [
+    ("index", False, 0, 0.0), ("reversed", False, 0, 0.0), ("plain", False, 2, 0.0),
+    ("plain", False, 3, 0.0), ("plain", False, 0, float("inf")), ("plain", True, 2, 0.0),
+    ("plain", False, 0, 1e-2),
+])
+def test_result_independent_of_options(oracle_mod, ivm, mode, fp64, stack, eps):
+    """Treelet order, FP64-only mode, a tiny stack (forces the linear-scan fallback),
+    and the filter margin (inf sends every test to FP64) never change a bit."""
+    import torch
+    _log(f"[options] {mode} fp64={fp64} stack={stack} eps={eps}")
+    s = sg.gen_c2(5, n_snap=8, nx=4, ny=3)
+    orc = oracle_mod.Oracle(s)
+    Mo, _ = orc.matrix()
+    tvo, rvo, loso = orc.txrx(s.tx, s.rx)
+    m = {"plain": ivm.IVM_ORDER_PLAIN, "index": ivm.IVM_ORDER_INDEX, "reversed": ivm.IVM_ORDER_REVERSED}[mode]
+    opts = ivm.make_opts(order_mode=m, fp64_only=fp64, stack_depth=stack, eps=eps)
+    st = ivm.new_stats()
+    g = ivm.GpuScene.from_scene(s).check()
+    M = ivm.ivm_intervisibility_matrix(g, opts, stats=st)
+    tv, rv, los = ivm.ivm_txrx_visibility_table(g, torch.as_tensor(s.tx).cuda(), torch.as_tensor(s.rx).cuda(), opts)
+    torch.cuda.synchronize()
+    _assert_matrix(ivm, M, Mo, s.n_facets)
+    assert (ivm.unpack_bits(tv, s.n_facets) == tvo).all()
+    assert (ivm.unpack_bits(rv, s.n_facets) == rvo).all()
+    assert (los.cpu().numpy().astype(bool) == loso).all()
+    d = ivm.stats_dict(st)
+    assert d["pairs_visible"] == Mo.sum() // 2
+    assert d["pairs_total"] == s.n_facets * (s.n_facets - 1) // 2
+    if stack == 2:
+        assert d["fallbacks"] > 0, "a 2-deep stack must overflow and take the linear-scan path"
+    if eps == float("inf") and not fp64:
+        assert d["rechecks"] == d["tri_tests"], "eps=inf sends every test to FP64"
+
+
+def test_triangle_groups_match_oracle_partition(oracle_mod, ivm):
+    """The LBVH's 32 treelets are the Morton partition the oracle defines."""
+    import torch
+    for s in (sg.gen_c1(1), sg.gen_c2(2, n_snap=1, nx=3, ny=4), sg.gen_plates([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]])):
+        _log(f"[groups] T={s.n_triangles}")
+        g = ivm.GpuScene.from_scene(s).check()
+        got = ivm.ivm_triangle_groups(g)
+        torch.cuda.synchronize()
+        _, expect = oracle_mod.morton_treelets(s, 32)
+        assert (got.cpu().numpy() == expect).all()
+
+
+def test_degenerate_and_tiny_scenes(oracle_mod, ivm):
+    """One facet (no pairs), two facets, fewer triangles than treelets."""
+    import torch
+    for rects in ([[[0, 0, 0], [4, 0, 0], [0, 4, 0]]],
+                  [[[0, 0, 0], [4, 0, 0], [0, 4, 0]], [[0, 0, 10], [0, 4, 0], [4, 0, 0]]],
+                  [[[0, 0, 0], [4, 0, 0], [0, 4, 0]], [[0, 0, 10], [0, 4, 0], [4, 0, 0]],
+                   [[-4, -4, 5], [12, 0, 0], [0, 12, 0]]]):
+        s = sg.gen_plates(rects, tx=[[1, 1, 3], [50, 50, 50]], rx=[[2, 2, 7], [1, 1, -3]])
+        _log(f"[tiny] F={s.n_facets}")
+        orc = oracle_mod.Oracle(s)
+        Mo, _ = orc.matrix()
+        tvo, rvo, loso = orc.txrx(s.tx, s.rx)
+        out = _run_all(ivm, s, lists=False)
+        _assert_matrix(ivm, out["M"], Mo, s.n_facets)
+        assert (ivm.unpack_bits(out["tv"], s.n_facets) == tvo).all()
+        assert (ivm.unpack_bits(out["rv"], s.n_facets) == rvo).all()
+        assert (out["los"].cpu().numpy().astype(bool) == loso).all()
+
+
+def test_invalid_scenes_report_status(ivm):
+    """Device-side validation: off-grid vertex, zero-area facet, unsorted facet ids,
+    too small a workspace.  Each is reported, and nothing faults."""
+    import ctypes
+    import torch
+    base = sg.gen_plates([[[0, 0, 0], [4, 0, 0], [0, 4, 0]], [[0, 0, 10], [0, 4, 0], [4, 0, 0]]])
+    # off-grid vertex (1/32 m on a 1/16 m vertex grid)
+    v = base.vertices.copy()
+    v[0, 0] = np.float32(1.0 / 32)
+    g = ivm.GpuScene(v, base.tri_vertices, base.tri_facet, base.sample_offsets, base.samples, base.g, base.g + base.k)
+    assert g.status() == ivm.IVM_ERR_GRID
+    # zero-area first triangle
+    v = base.vertices.copy()
+    v[1] = v[0]
+    g = ivm.GpuScene(v, base.tri_vertices, base.tri_facet, base.sample_offsets, base.samples, base.g, base.g + base.k)
+    assert g.status() == ivm.IVM_ERR_DEGENERATE
+    # facet ids out of order
+    tf = base.tri_facet[::-1].copy()
+    g = ivm.GpuScene(base.vertices, base.tri_vertices, tf, base.sample_offsets, base.samples, base.g, base.g + base.k)
+    assert g.status() == ivm.IVM_ERR_INVALID_ARGUMENT
+    # workspace too small
+    lib = ivm.load_library()
+    g = ivm.GpuScene.from_scene(base).check()
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    st = lib.ivm_build_scene(ctypes.byref(g.desc), (int(ws.data_ptr()) + 255) & ~255, 256, None, ctypes.byref(h))
+    assert st == ivm.IVM_ERR_WORKSPACE
+    # off-grid Tx is reported by the table call's position check
+    tx = torch.tensor([[0.001, 0.0, 1.0]], dtype=torch.float32, device="cuda")
+    ivm.ivm_txrx_visibility_table(g, tx, tx.clone())
+    torch.cuda.synchronize()
+    assert g.status() == ivm.IVM_ERR_GRID
+
+
+def _plate_row_scene(ivm, F):
+    """F small plates on a line: a valid scene with exactly F facets (W = ceil(F/64))."""
+    x = np.arange(F, dtype=np.float32)
+    V = np.stack([np.stack([x, 0 * x, 0 * x], 1), np.stack([x + 0.5, 0 * x, 0 * x], 1),
+                  np.stack([x + 0.5, 0 * x + 0.5, 0 * x], 1), np.stack([x, 0 * x + 0.5, 0 * x], 1)], 1)
+    base = 4 * np.arange(F, dtype=np.int32)[:, None]
+    T = np.stack([np.concatenate([base, base + 1, base + 2], 1), np.concatenate([base, base + 2, base + 3], 1)], 1)
+    TF = np.repeat(np.arange(F, dtype=np.int32), 2)
+    SM = np.stack([x + 0.25, 0 * x + 0.25, 0 * x], 1)
+    OFF = np.arange(F + 1, dtype=np.int32)
+    return ivm.GpuScene(V.reshape(-1, 3), T.reshape(-1, 3), TF, OFF, SM, 2, 2).check()
+
+
+def test_candidates_random_tables_full_size(oracle_mod, ivm):
+    """Candidate counts (and lists) at full size, 2000 and 20000 facets, on seeded random
+    bit tables with realistic densities, against the oracle's integer products."""
+    import torch
+    for F, N, dens, lists in ((2000, 200, 0.02, True), (20000, 64, 0.002, False)):
+        _log(f"[candidates] F={F} N={N}")
+        rng = np.random.default_rng(F)
+        M = rng.random((F, F)) < dens
+        M = M | M.T
+        np.fill_diagonal(M, False)
+        tv = rng.random((N, F)) < 0.03
+        rv = rng.random((N, F)) < 0.03
+        los = rng.random(N) < 0.3
+        g = _plate_row_scene(ivm, F)
+        dM = torch.as_tensor(ivm.pack_bits(M)).cuda()
+        dtv = torch.as_tensor(ivm.pack_bits(tv)).cuda()
+        drv = torch.as_tensor(ivm.pack_bits(rv)).cuda()
+        dlos = torch.as_tensor(los.astype(np.uint8)).cuda()
+        co = oracle_mod.candidates_matmul(M, tv, rv, los, 2)
+        if lists:
+            counts, off, paths = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 2, lists=True)
+            torch.cuda.synchronize()
+            assert (counts.cpu().numpy() == co).all()
+            _, L = oracle_mod.candidates_enum(M, tv[:5], rv[:5], los[:5], 2)
+            _check_lists({"offsets": off, "paths": paths}, L, 5, 2)
+        else:
+            counts = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 2)
+            torch.cuda.synchronize()
+            assert (counts.cpu().numpy() == co).all()
