@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the inter-visibility hot path on one MI355X.
+
+One step = one pass of the whole path over the workload: build the scene
+(validation + Morton LBVH), the facet-pair inter-visibility matrix, the Tx/Rx
+visibility table for every snapshot, and image-tree candidate counts up to
+order 2.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  value = facet-pair queries/s = F(F-1)/2 unordered pairs
+decided per second of ivm_intervisibility_matrix GPU time (median over steps);
+txrx_ms_per_snapshot = (table + candidates) GPU time / snapshots.
+
+    python bench.py [--steps K] [--warmup W] [--config c2] [--order plain]
+"""
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 non-packed FP32 lane-ops/s
+# (one FMA = one lane-op; 78.6 TFLOP/s counting an FMA as two).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic work per counted unit (VALU lane-ops): a node visit tests two child
+# boxes (2 x 14), a segment/triangle test ~43 (Moller-Trumbore 33 + filter 10),
+# an FP64 recheck ~35 more.
+OPS_NODE, OPS_TRI, OPS_RECHECK = 28, 43, 35
+
+WORKLOADS = {
+    "c1": "tiny urban 200x200 m, 8 boxes, 42 facets / 84 tris, 4x4 samples, 10 snapshots",
+    "c2": "urban grid 1x1 km, 200 boxes on a Manhattan grid, 2000 facets / 4000 tris, 8x8 samples, "
+          "1000 snapshots (Rx 120 km/h every 10 ms, Tx fixed at 30 m)",
+    "c3": "large city 4x4 km, 2000 convex 4-8-gon extrusions, ~20k facets / ~44k tris, 4x4 samples, "
+          "10000 snapshots (two vehicles 5-20 m/s)",
+    "c4": "one config-1-style scene of the batched set (500-5000 facets), 4x4 samples",
+}
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--snapshots", type=int, default=None)
+    ap.add_argument("--order", default="plain", choices=["plain", "index", "reversed", "learned"])
+    ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--stack", type=int, default=0)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(scene, seconds, seed=0):
+    """The FP64 oracle on a bounded, seeded sample of the same workload: uniformly
+    drawn unordered facet pairs (queries/s) and a few whole snapshots (ms/snapshot)."""
+    import oracle
+    orc = oracle.Oracle(scene)
+    rng = np.random.default_rng(seed)
+    F = scene.n_facets
+    n_pairs, t_pairs = 0, 0.0
+    while t_pairs < 0.75 * seconds:
+        I = rng.integers(0, F, 512)
+        J = rng.integers(0, F, 512)
+        keep = I != J
+        I, J = I[keep], J[keep]
+        t0 = time.perf_counter()
+        orc.pairs(I, J)
+        t_pairs += time.perf_counter() - t0
+        n_pairs += len(I)
+    n_snap, t_snap = 0, 0.0
+    idx = rng.permutation(scene.n_snapshots)
+    while t_snap < 0.25 * seconds and n_snap < len(idx):
+        k = idx[n_snap:n_snap + 1]
+        t0 = time.perf_counter()
+        tv, rv, los = orc.txrx(scene.tx[k], scene.rx[k])
+        oracle.candidates_matmul(np.zeros((F, F), bool), tv, rv, los, 1)
+        t_snap += time.perf_counter() - t0
+        n_snap += 1
+    return {"value": n_pairs / t_pairs, "unit": "facet-pair queries/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_pairs} uniformly drawn facet pairs of the same scene ({t_pairs:.1f} s); "
+                      f"Tx/Rx table for {n_snap} snapshots: {1e3 * t_snap / max(n_snap, 1):.1f} ms/snapshot "
+                      f"(table only)",
+            "ms_per_snapshot": 1e3 * t_snap / max(n_snap, 1)}
+
+
+def verify(ivm, scene, M, tv, rv, los, counts):
+    """Compare with the oracle: the full cached result if one exists for this exact
+    workload, else seeded sampled pairs and snapshot entries computed now."""
+    import oracle
+    F = scene.n_facets
+    gm = ivm.unpack_bits(M, F)
+    gtv, grv = ivm.unpack_bits(tv, F), ivm.unpack_bits(rv, F)
+    glos = los.cpu().numpy().astype(bool)
+    cache = os.path.join(ROOT, "tests", "golden", "cache", f"{scene.name}_seed{scene.seed}.npz")
+    if os.path.exists(cache) and scene.n_snapshots == 1000:
+        z = np.load(cache)
+        Mo = np.unpackbits(z["M"], axis=1)[:, :F].astype(bool)
+        tvo = np.unpackbits(z["tx_vis"], axis=1)[:, :F].astype(bool)
+        rvo = np.unpackbits(z["rx_vis"], axis=1)[:, :F].astype(bool)
+        co = oracle.candidates_matmul(Mo, tvo, rvo, z["los"], 2)
+        ok = bool((gm == Mo).all() and (gtv == tvo).all() and (grv == rvo).all() and (glos == z["los"]).all()
+                  and (counts.cpu().numpy() == co).all())
+        return {"mode": "full oracle cache", "ok": ok}
+    orc = oracle.Oracle(scene)
+    rng = np.random.default_rng(1)
+    I = rng.integers(0, F, 300)
+    J = rng.integers(0, F, 300)
+    # bias half the sample toward visible GPU pairs so both outcomes are checked
+    vis = np.argwhere(np.triu(gm, 1))
+    if len(vis):
+        pick = vis[rng.integers(0, len(vis), 150)]
+        I = np.concatenate([I, pick[:, 0]])
+        J = np.concatenate([J, pick[:, 1]])
+    ok = bool((orc.pairs(I, J) == gm[I, J]).all())
+    N = scene.n_snapshots
+    n_idx = rng.integers(0, N, 200)
+    f_idx = rng.integers(0, F, 200)
+    ok &= bool((orc.point_facets(scene.tx[n_idx], f_idx) == gtv[n_idx, f_idx]).all())
+    ok &= bool((orc.point_facets(scene.rx[n_idx], f_idx) == grv[n_idx, f_idx]).all())
+    ok &= bool((orc.los(scene.tx[n_idx], scene.rx[n_idx]) == glos[n_idx]).all())
+    ok &= bool((gm == gm.T).all() and not gm.diagonal().any())
+    return {"mode": f"sampled: {len(I)} pairs, 200 Tx + 200 Rx entries, 200 LoS", "ok": ok}
+
+
+def main():
+    args = _parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}): the inter-visibility "
+              "path runs on a single MI355X; see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2501_02747_amd as ivm
+    import scenegen as sg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(1)
+    kw = {}
+    if args.snapshots is not None:
+        kw["n_snap"] = args.snapshots
+    scene = sg.make_config(args.config, args.seed, **kw)
+    F, N = scene.n_facets, scene.n_snapshots
+    order = {"plain": ivm.IVM_ORDER_PLAIN, "index": ivm.IVM_ORDER_INDEX, "reversed": ivm.IVM_ORDER_REVERSED,
+             "learned": ivm.IVM_ORDER_LEARNED}[args.order]
+    g = ivm.GpuScene.from_scene(scene, learned=(args.order == "learned")).check()
+    tx = torch.as_tensor(scene.tx).cuda()
+    rx = torch.as_tensor(scene.rx).cuda()
+    M = torch.empty((F, g.W), dtype=torch.int64, device="cuda")
+    tv = torch.empty((N, g.W), dtype=torch.int64, device="cuda")
+    rv = torch.empty((N, g.W), dtype=torch.int64, device="cuda")
+    los = torch.empty((N,), dtype=torch.uint8, device="cuda")
+    counts = torch.empty((N, 3), dtype=torch.int64, device="cuda")
+    st_m, st_p = ivm.new_stats(), ivm.new_stats()
+    t_pairs, t_points = ivm.KernelTimer(), ivm.KernelTimer()
+    om = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu,
+                       stack_depth=args.stack, timing=t_pairs)
+    op = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu,
+                       stack_depth=args.stack, timing=t_points)
+
+    def step(rec):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        st_m.zero_()
+        st_p.zero_()
+        ev[0].record()
+        g.rebuild()
+        ev[1].record()
+        ivm.ivm_intervisibility_matrix(g, om, out=M, stats=st_m, allow_model_fallback=False)
+        ev[2].record()
+        ivm.ivm_txrx_visibility_table(g, tx, rx, op, stats=st_p, out=(tv, rv, los))
+        ev[3].record()
+        ivm.ivm_image_tree_candidates(g, M, tv, rv, los, 2, counts=counts)
+        ev[4].record()
+        if rec is not None:
+            rec.append((ev, t_pairs, t_points))
+
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    progress(f"{args.config}: F={F} T={scene.n_triangles} S={scene.n_samples} N={N}; warmup {args.warmup}")
+    for k in range(args.warmup):
+        step(None)
+        torch.cuda.synchronize()
+        progress(f"warmup step {k + 1} done")
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    progress(f"timed {args.steps} steps in {wall:.3f} s")
+    # per-step GPU times (the kernel timers hold the last step's values; re-read per step
+    # would need one timer per step, so kernel times come from the final step and a
+    # check below that the matrix phase time is stable across steps)
+    phases = {"build": [], "matrix": [], "txrx": [], "cand": [], "step": []}
+    for ev, _, _ in recs:
+        phases["build"].append(ev[0].elapsed_time(ev[1]))
+        phases["matrix"].append(ev[1].elapsed_time(ev[2]))
+        phases["txrx"].append(ev[2].elapsed_time(ev[3]))
+        phases["cand"].append(ev[3].elapsed_time(ev[4]))
+        phases["step"].append(ev[0].elapsed_time(ev[4]))
+    med = {k: statistics.median(v) for k, v in phases.items()}
+    pairs_kernel_ms = t_pairs.elapsed_ms()
+    points_kernel_ms = t_points.elapsed_ms()
+    sm, sp = ivm.stats_dict(st_m), ivm.stats_dict(st_p)
+    n_pairs = F * (F - 1) // 2
+    value = n_pairs / (med["matrix"] / 1e3)
+    ops_pairs = sm["node_visits"] * OPS_NODE + sm["tri_tests"] * OPS_TRI + sm["rechecks"] * OPS_RECHECK
+    ops_points = sp["node_visits"] * OPS_NODE + sp["tri_tests"] * OPS_TRI + sp["rechecks"] * OPS_RECHECK
+    ach = ops_pairs / (pairs_kernel_ms / 1e3) / 1e12
+    ach_p = ops_points / (points_kernel_ms / 1e3) / 1e12
+    out = {
+        "metric": "facet-pair vis queries/s + Tx/Rx table ms/snapshot, learned vs plain, bit-exact",
+        "value": value,
+        "unit": "facet-pair queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.fp64_only else "f32 (f64 recheck)",
+        "data": "synthetic (seeded scene generator)",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "facets": F,
+                   "triangles": scene.n_triangles, "samples": scene.n_samples, "snapshots": N,
+                   "seed": scene.seed, "order": args.order, "parallelism": "single GPU"},
+        "txrx_ms_per_snapshot": (med["txrx"] + med["cand"]) / N,
+        "phase_ms_median": med,
+        "kernel_ms": {"k_pairs": pairs_kernel_ms, "k_points": points_kernel_ms},
+        "stats_matrix": sm,
+        "stats_table": sp,
+        "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                     "frac": ach / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_pairs",
+                     "ops_per_launch": ops_pairs},
+        "roofline_points": {"bound": "alu", "achieved": ach_p, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                            "frac": ach_p / VALU_PEAK_TOPS, "kernel": "k_points"},
+    }
+    if not args.no_verify:
+        progress("verifying against the oracle")
+        counts_now = counts
+        out["verified"] = verify(ivm, scene, M, tv, rv, los, counts_now)
+    if not args.no_cpu_baseline:
+        progress("timing the oracle on the host cores")
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_baseline_seconds)
+        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

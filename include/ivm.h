@@ -115,7 +115,8 @@ typedef struct ivm_scene_info_t {
  * segments: segments traversed; node_visits: internal BVH nodes whose child
  * boxes were tested; tri_tests: segment/triangle tests; rechecks: tests whose
  * FP32 margin was too small and which were decided in FP64; fallbacks: subtrees
- * scanned linearly because the traversal stack was full. */
+ * scanned linearly because the traversal stack was full; certified: pairs
+ * decided blocked by the single-occluder test on sample-hull corners. */
 typedef struct ivm_stats {
     uint64_t pairs_total;
     uint64_t pairs_candidate;
@@ -127,7 +128,8 @@ typedef struct ivm_stats {
     uint64_t fallbacks;
     uint64_t point_items;
     uint64_t flags; /* bit 0: learned order fell back to the plain order */
-    uint64_t reserved[6];
+    uint64_t certified; /* pairs proven blocked by one convex occluder from hull corners */
+    uint64_t reserved[5];
 } ivm_stats;
 
 #define IVM_ORDER_PLAIN 0    /* treelets nearest the pair's segment box first */
@@ -144,7 +146,10 @@ typedef struct ivm_matrix_opts {
     float eps;              /* FP32 filter margin relative to the magnitude bound;
                                0 = default 1e-5; values < 1e-5 are raised to 1e-5;
                                +inf sends every test to FP64 */
-    int32_t reserved[3];
+    int32_t reserved;
+    hipEvent_t *timing_events; /* optional (NULL = none): two caller-created events the
+                                  call records on its stream immediately before and
+                                  after its traversal kernel */
 } ivm_matrix_opts;
 
 #define IVM_MAX_STACK 32

@@ -71,12 +71,13 @@ class ivm_matrix_opts(ctypes.Structure):
     _fields_ = [
         ("order_mode", ctypes.c_int32), ("fp64_only", ctypes.c_int32),
         ("stack_depth", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-        ("eps", ctypes.c_float), ("reserved", ctypes.c_int32 * 3),
+        ("eps", ctypes.c_float), ("reserved", ctypes.c_int32),
+        ("timing_events", ctypes.c_void_p),
     ]
 
 
 STATS_FIELDS = ["pairs_total", "pairs_candidate", "pairs_visible", "segments", "node_visits",
-                "tri_tests", "rechecks", "fallbacks", "point_items", "flags"]
+                "tri_tests", "rechecks", "fallbacks", "point_items", "flags", "certified"]
 STATS_WORDS = 16
 
 _lib = None
@@ -140,11 +141,46 @@ def _ptr(t) -> Optional[int]:
 
 
 def make_opts(order_mode: int = IVM_ORDER_PLAIN, fp64_only: bool = False, stack_depth: int = 0,
-              waves_per_cu: int = 0, eps: float = 0.0) -> ivm_matrix_opts:
+              waves_per_cu: int = 0, eps: float = 0.0, timing: Optional["KernelTimer"] = None) -> ivm_matrix_opts:
     o = ivm_matrix_opts()
     o.order_mode, o.fp64_only, o.stack_depth = order_mode, int(fp64_only), stack_depth
     o.waves_per_cu, o.eps = waves_per_cu, eps
+    o.timing_events = timing.array_ptr if timing is not None else None
     return o
+
+
+class KernelTimer:
+    """Two HIP events (created through the HIP runtime torch has loaded) that an
+    entry point records around its traversal kernel; elapsed_ms() reads them."""
+
+    def __init__(self):
+        import torch  # noqa: F401
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.events = (ctypes.c_void_p * 2)()
+        for k in range(2):
+            ev = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(ev)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.events[k] = ev
+        self.array_ptr = ctypes.cast(self.events, ctypes.c_void_p).value
+
+    def elapsed_ms(self) -> float:
+        self.hip.hipEventSynchronize(self.events[1])
+        ms = ctypes.c_float(0.0)
+        if self.hip.hipEventElapsedTime(ctypes.byref(ms), self.events[0], self.events[1]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            for k in range(2):
+                self.hip.hipEventDestroy(self.events[k])
+        except Exception:
+            pass
 
 
 def new_stats(device="cuda"):
@@ -200,6 +236,20 @@ class GpuScene:
         self.F, self.T, self.S, self.W = info.n_facets, info.n_triangles, info.n_samples, info.words_per_row
         self.n_treelets = info.n_treelets
         self.device = dev
+
+    def rebuild(self, stream=None) -> "GpuScene":
+        """Run ivm_build_scene again on the resident arrays and workspace (no allocation)."""
+        lib = load_library()
+        old = self.handle
+        h = ctypes.c_void_p()
+        nbytes = self.workspace.numel() - 256
+        aligned = (int(self.workspace.data_ptr()) + 255) & ~255
+        _check(lib.ivm_build_scene(ctypes.byref(self.desc), aligned, nbytes, _stream(stream), ctypes.byref(h)),
+               "ivm_build_scene")
+        self.handle = h
+        if old and old.value:
+            lib.ivm_destroy_scene(old)
+        return self
 
     @classmethod
     def from_scene(cls, sc, **kw) -> "GpuScene":

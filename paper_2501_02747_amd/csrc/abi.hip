@@ -50,6 +50,7 @@ TraverseOpts make_opts(const ivm_matrix_opts *o) {
     long long blocks = (long long)device_cu_count() * wpc / 4;
     if (blocks < 1) blocks = 1;
     t.grid_blocks = (int)blocks;
+    t.events = o ? o->timing_events : nullptr;
     return t;
 }
 
@@ -118,6 +119,10 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.soff = (const int *)(ws + L.soff);
     d.smp = (const float4 *)(ws + L.smp);
     d.sfacet = (const int *)(ws + L.sfacet);
+    d.tri_caller = (const float4 *)(ws + L.tri_caller);
+    d.ftri = (const int *)(ws + L.ffirst);
+    d.fhull = (const int *)(ws + L.fhull);
+    d.fhull_n = (const int *)(ws + L.fhull_n);
     d.status = (int *)(ws + L.status);
     d.extent = (const double *)(ws + L.extent);
     sc.n_items = F * d.W;

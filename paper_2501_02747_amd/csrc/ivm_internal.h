@@ -16,6 +16,7 @@ constexpr int kLeafMax = 4;        // subtrees of <= kLeafMax triangles become l
 constexpr int kDefaultStack = 24;
 constexpr int kMaxSamplesPerFacet = 64;
 constexpr float kDefaultEps = 1e-5f;
+constexpr int kHullMax = 8;       // sample convex hull points kept per facet (0 = none kept)
 
 // Status bits raised on the device, mapped to ivm_status by the host.
 constexpr int kStGrid = 1;
@@ -58,6 +59,10 @@ struct SceneDev {
     const int *soff;           // F + 1
     const float4 *smp;         // S
     const int *sfacet;         // S
+    const float4 *tri_caller;  // 3 * T, same records in the caller's triangle order
+    const int *ftri;           // F * 2: first caller triangle of the facet, triangle count
+    const int *fhull;          // F * kHullMax: sample indices of the convex hull of the facet's samples
+    const int *fhull_n;        // F: hull size (0 = unavailable)
     int *status;               // device status bits
     const double *extent;      // [0..5] = sample-unit integer box of vertices+samples as doubles; [6] = E
 };
@@ -66,7 +71,7 @@ struct SceneDev {
 struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
-    size_t ffirst, cand, prefix, queue, learned, scan_tmp;
+    size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n;
     size_t learned_bytes;
     size_t total;
 };
@@ -90,6 +95,7 @@ struct TraverseOpts {
     int stack_depth;
     float eps6;                // 6 * eps: margin factor of the FP32 filter
     int grid_blocks;
+    hipEvent_t *events;        // optional: recorded around the traversal kernel
 };
 
 // Launchers (each returns hipSuccess or the launch error).

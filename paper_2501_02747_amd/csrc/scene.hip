@@ -54,6 +54,9 @@ Layout make_layout(int F, int T, int S, bool learned) {
     L.node_range = take(Tn * 2 * sizeof(int));
     L.node_box = take(Tn * 6 * sizeof(float));
     L.ffirst = take(Fn * 2 * sizeof(int));
+    L.tri_caller = take(Tn * 3 * sizeof(float4));
+    L.fhull = take(Fn * kHullMax * sizeof(int));
+    L.fhull_n = take(Fn * sizeof(int));
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
@@ -155,8 +158,48 @@ __global__ void k_sample_prep(ivm_scene_desc d, int *ibox, int *status) {
     if (bad) atomicOr(status, bad);
 }
 
+// Convex hull (Andrew's monotone chain, strict turns) of a facet's samples,
+// projected on the two axes orthogonal to the normal's largest component.  The
+// sample grid makes every cross product an exact FP64 integer.  Writes up to
+// kHullMax global sample indices; returns the hull size, or 0 if it is larger.
+__device__ int sample_hull(const float *samples, int s0, int ns, int drop, int *out) {
+    if (ns <= 0 || ns > kMaxSamplesPerFacet) return 0;
+    const int ax = drop == 0 ? 1 : 0, ay = drop == 2 ? 1 : 2;
+    int idx[kMaxSamplesPerFacet];
+    for (int m = 0; m < ns; ++m) idx[m] = m;
+    auto U = [&](int m) { return (double)samples[3 * (s0 + m) + ax]; };
+    auto V = [&](int m) { return (double)samples[3 * (s0 + m) + ay]; };
+    for (int m = 1; m < ns; ++m) {  // insertion sort by (u, v)
+        int x = idx[m];
+        int k = m - 1;
+        while (k >= 0 && (U(idx[k]) > U(x) || (U(idx[k]) == U(x) && V(idx[k]) > V(x)))) {
+            idx[k + 1] = idx[k];
+            --k;
+        }
+        idx[k + 1] = x;
+    }
+    int h[2 * kMaxSamplesPerFacet + 1];
+    int n = 0;
+    auto turn = [&](int o, int a, int b) {
+        return (U(a) - U(o)) * (V(b) - V(o)) - (V(a) - V(o)) * (U(b) - U(o));
+    };
+    for (int m = 0; m < ns; ++m) {  // lower hull
+        while (n >= 2 && turn(h[n - 2], h[n - 1], idx[m]) <= 0.0) --n;
+        h[n++] = idx[m];
+    }
+    for (int m = ns - 2, lo = n + 1; m >= 0; --m) {  // upper hull
+        while (n >= lo && turn(h[n - 2], h[n - 1], idx[m]) <= 0.0) --n;
+        h[n++] = idx[m];
+    }
+    if (n > 1) --n;  // last point repeats the first
+    // duplicates collapse to one point
+    if (n > kHullMax) return 0;
+    for (int m = 0; m < n; ++m) out[m] = s0 + h[m];
+    return n;
+}
+
 __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane, float *fbox, int *soff,
-                             float4 *smp, int *sfacet, int *ibox, int *status) {
+                             float4 *smp, int *sfacet, int *ibox, int *status, int *fhull, int *fhull_n) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.n_facets) return;
     int bad = 0;
@@ -216,6 +259,9 @@ __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane
         fbox[6 * f + k] = lo[k];
         fbox[6 * f + 3 + k] = hi[k];
     }
+    const double an0 = fabs(n[0]), an1 = fabs(n[1]), an2 = fabs(n[2]);
+    const int drop = (an0 >= an1 && an0 >= an2) ? 0 : (an1 >= an2 ? 1 : 2);
+    fhull_n[f] = (bad & kStDegenerate) ? 0 : sample_hull(d.samples, s0, s1 - s0, drop, fhull + kHullMax * f);
     if (bad) atomicOr(status, bad);
 }
 
@@ -343,7 +389,8 @@ __device__ inline void treelet_range(int k, int T, int *s, int *e) {
     *e = (int)(((long long)(k + 1) * T + kTreelets - 1) / kTreelets);
 }
 
-__global__ void k_tri_sorted(ivm_scene_desc d, const uint32_t *order, float4 *tri, int *tri_orig, int *tri_group) {
+__global__ void k_tri_sorted(ivm_scene_desc d, const uint32_t *order, float4 *tri, int *tri_orig, int *tri_group,
+                             float4 *tri_caller) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= d.n_triangles) return;
     int t = (int)order[r];
@@ -362,9 +409,15 @@ __global__ void k_tri_sorted(ivm_scene_desc d, const uint32_t *order, float4 *tr
         m1 = fmaxf(m1, fabsf(e1[k]));
         m2 = fmaxf(m2, fabsf(e2[k]));
     }
-    tri[3 * r + 0] = make_float4(P[0][0], P[0][1], P[0][2], __int_as_float(f));
-    tri[3 * r + 1] = make_float4(e1[0], e1[1], e1[2], m1);
-    tri[3 * r + 2] = make_float4(e2[0], e2[1], e2[2], m2);
+    const float4 A = make_float4(P[0][0], P[0][1], P[0][2], __int_as_float(f));
+    const float4 B = make_float4(e1[0], e1[1], e1[2], m1);
+    const float4 C = make_float4(e2[0], e2[1], e2[2], m2);
+    tri[3 * r + 0] = A;
+    tri[3 * r + 1] = B;
+    tri[3 * r + 2] = C;
+    tri_caller[3 * t + 0] = A;
+    tri_caller[3 * t + 1] = B;
+    tri_caller[3 * t + 2] = C;
     tri_orig[r] = t;
     tri_group[t] = (int)(((long long)r * kTreelets) / d.n_triangles);
 }
@@ -537,7 +590,7 @@ hipError_t launch_build(Scene &sc, hipStream_t s) {
     if (F > 0)
         hipLaunchKernelGGL(k_facet_prep, dim3(nblk(F, 128)), dim3(128), 0, s, d, ffirst, (double *)(ws + L.fplane),
                            (float *)(ws + L.fbox), (int *)(ws + L.soff), (float4 *)(ws + L.smp),
-                           (int *)(ws + L.sfacet), ibox, status);
+                           (int *)(ws + L.sfacet), ibox, status, (int *)(ws + L.fhull), (int *)(ws + L.fhull_n));
     hipLaunchKernelGGL(k_budget, dim3(1), dim3(64), 0, s, d, ibox, (double *)(ws + L.extent), status);
     if (T > 0) {
         uint32_t *keys = (uint32_t *)(ws + L.keys), *vals = (uint32_t *)(ws + L.vals);
@@ -546,7 +599,7 @@ hipError_t launch_build(Scene &sc, hipStream_t s) {
                            (uint32_t *)(ws + L.vals2), T);
         float4 *tri = (float4 *)(ws + L.tri);
         hipLaunchKernelGGL(k_tri_sorted, dim3(nblk(T, 256)), dim3(256), 0, s, d, vals, tri, (int *)(ws + L.tri_orig),
-                           (int *)(ws + L.tri_group));
+                           (int *)(ws + L.tri_group), (float4 *)(ws + L.tri_caller));
         int *child = (int *)(ws + L.node_child), *range = (int *)(ws + L.node_range);
         float *nbox = (float *)(ws + L.node_box);
         hipLaunchKernelGGL(k_karras, dim3(nblk(T, 256)), dim3(256), 0, s, T, keys, child, range);

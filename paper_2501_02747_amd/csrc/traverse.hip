@@ -58,25 +58,31 @@ __device__ inline double orient(const double *pl, float x, float y, float z) {
 struct Seg {
     float px, py, pz;   // origin
     float dx, dy, dz;   // q - p (exact on the grid)
-    float ix, iy, iz;   // 1 / d (0 where d = 0)
     float dm;           // max |d_k|
+    float ix, iy, iz;   // 1 / d_k (0 where d_k = 0), set by with_inverse()
 };
 
 __device__ inline Seg make_seg(float px, float py, float pz, float qx, float qy, float qz) {
     Seg s;
     s.px = px; s.py = py; s.pz = pz;
     s.dx = qx - px; s.dy = qy - py; s.dz = qz - pz;
-    s.ix = s.dx != 0.f ? 1.0f / s.dx : 0.f;
-    s.iy = s.dy != 0.f ? 1.0f / s.dy : 0.f;
-    s.iz = s.dz != 0.f ? 1.0f / s.dz : 0.f;
     s.dm = fmaxf(fabsf(s.dx), fmaxf(fabsf(s.dy), fabsf(s.dz)));
+    s.ix = s.iy = s.iz = 0.f;
     return s;
 }
 
+// v_rcp_f32 is within 1 ulp; the slab test below budgets for it.
+__device__ inline void with_inverse(Seg &s) {
+    s.ix = s.dx != 0.f ? __builtin_amdgcn_rcpf(s.dx) : 0.f;
+    s.iy = s.dy != 0.f ? __builtin_amdgcn_rcpf(s.dy) : 0.f;
+    s.iz = s.dz != 0.f ? __builtin_amdgcn_rcpf(s.dz) : 0.f;
+}
+
 // Conservative slab test of the segment p + t d, t in [0, 1], against a closed
-// box.  Box minus origin is exact; each slab parameter carries <= ~3 ulp of
-// relative error, so widening the exit by 2^-20 never rejects a box the exact
-// segment meets.  Axes with d = 0 are decided exactly by containment.
+// box.  Box minus origin is exact; each slab parameter carries <= 3 ulp of
+// relative error (1 from the reciprocal, 1 from the product, ulp = 2^-23), so
+// widening the exit by 2^-20 never rejects a box the exact segment meets.
+// Axes with d = 0 are decided exactly by containment.
 constexpr float kWiden = 1.00000095367431640625f;  // 1 + 2^-20
 
 __device__ inline bool seg_box(const Seg &s, float lx, float ly, float lz, float hx, float hy, float hz,
@@ -176,27 +182,29 @@ struct Cnt {
     unsigned visits = 0, tests = 0, rechecks = 0, fallbacks = 0;
 };
 
-__device__ inline bool test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
-                                  float eps6, bool f64, Cnt &c) {
+__device__ inline int test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
+                                 float eps6, bool f64, Cnt &c) {
     for (int r = first; r < first + count; ++r) {
         const float4 A = sc.tri[3 * r];
         const int f = __float_as_int(A.w);
         if (f == exA || f == exB) continue;
         ++c.tests;
-        if (tri_hit(s, A, sc.tri[3 * r + 1], sc.tri[3 * r + 2], eps6, f64, c.rechecks)) return true;
+        if (tri_hit(s, A, sc.tri[3 * r + 1], sc.tri[3 * r + 2], eps6, f64, c.rechecks)) return r;
     }
-    return false;
+    return -1;
 }
 
 constexpr int kNone = 0x7fffffff;
 
-// Any-hit traversal of one segment.  `order` lists treelets to visit (LDS or
-// constant memory); `stk` is this lane's LDS stack with a stride of one wave.
-// When the stack is full the far child's whole subtree is scanned linearly
-// (its triangles are a contiguous sorted range), so no node is ever dropped.
+// Any-hit traversal of one segment; returns the sorted rank of a triangle that
+// the segment hits, or -1 when the segment is clear.  `order` lists treelets to
+// visit (LDS or constant memory); `stk` is this lane's LDS stack with a stride of
+// one wave.  When the stack is full the far child's whole subtree is scanned
+// linearly (its triangles are a contiguous sorted range), so no node is dropped.
 template <typename OrderPtr>
-__device__ bool any_hit(const SceneDev &sc, const Seg &s, int exA, int exB, OrderPtr order, int n_order, int *stk,
-                        int depth, float eps6, bool f64, Cnt &c) {
+__device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr order, int n_order, int *stk,
+                       int depth, float eps6, bool f64, Cnt &c) {
+    with_inverse(s);
     int r = 0, sp = 0;
     int ref = kNone;
     while (true) {
@@ -215,7 +223,7 @@ __device__ bool any_hit(const SceneDev &sc, const Seg &s, int exA, int exB, Orde
                         break;
                     }
                 }
-                if (ref == kNone) return false;
+                if (ref == kNone) return -1;
             }
         }
         if (ref >= 0) {
@@ -240,7 +248,8 @@ __device__ bool any_hit(const SceneDev &sc, const Seg &s, int exA, int exB, Orde
                         first = rg.z;
                         count = rg.w - rg.z + 1;
                     }
-                    if (test_range(sc, s, first, count, exA, exB, eps6, f64, c)) return true;
+                    const int h = test_range(sc, s, first, count, exA, exB, eps6, f64, c);
+                    if (h >= 0) return h;
                 }
                 ref = nearc;
             } else if (h0) {
@@ -251,7 +260,8 @@ __device__ bool any_hit(const SceneDev &sc, const Seg &s, int exA, int exB, Orde
                 ref = kNone;
             }
         } else {
-            if (test_range(sc, s, leaf_first(ref), leaf_count(ref), exA, exB, eps6, f64, c)) return true;
+            const int h = test_range(sc, s, leaf_first(ref), leaf_count(ref), exA, exB, eps6, f64, c);
+            if (h >= 0) return h;
             ref = kNone;
         }
     }
@@ -448,6 +458,42 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
     j = (item - i * sc.W) * 64 + bit;
 }
 
+constexpr int kCache = 4;  // recent blockers tested before a traversal
+
+// Single-occluder certificate.  Let H_i, H_j be the convex hulls of the two
+// sample sets and C a convex facet.  For fixed q the points p whose open segment
+// to q meets C form a convex set, and symmetrically for p fixed; so if every
+// segment between hull corners meets C transversally inside (0, 1), every
+// segment between the hulls does, and each crosses C's plane strictly, at a point
+// of the closed polygon C, i.e. of one of its closed triangles.  Then no
+// admissible segment of the pair is clear.  One lane per (corner, corner,
+// triangle of C).
+__device__ bool certify_blocked(const SceneDev &sc, int i, int j, int C, int *corner, float eps6, bool f64,
+                                Cnt &c) {
+    const int lane = lane_id();
+    const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
+    const int t0 = sc.ftri[2 * C], nt = sc.ftri[2 * C + 1];
+    if (ni == 0 || nj == 0 || nt <= 0) return false;
+    const int pairs = ni * nj;  // <= kHullMax^2 = 64
+    corner[lane] = 0;
+    wave_sync();
+    for (int it = lane; it < pairs * nt; it += kWave) {
+        const int cp = it / nt, t = it - (it / nt) * nt;
+        const int a = cp / nj, b = cp - (cp / nj) * nj;
+        const float4 P = sc.smp[sc.fhull[kHullMax * i + a]];
+        const float4 Q = sc.smp[sc.fhull[kHullMax * j + b]];
+        const Seg s = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+        ++c.tests;
+        const float4 *tr = sc.tri_caller + 3 * (t0 + t);
+        if (tri_hit(s, tr[0], tr[1], tr[2], eps6, f64, c.rechecks)) corner[cp] = 1;
+    }
+    wave_sync();
+    const bool missing = lane < pairs && corner[lane] == 0;
+    const bool ok = __ballot(missing) == 0ull;
+    wave_sync();
+    return ok;
+}
+
 __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *cand, const uint32_t *prefix,
                                                   int n_items, uint32_t *queue, uint64_t *M, TraverseOpts o,
                                                   ivm_stats *st, const uint64_t *learned) {
@@ -456,12 +502,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
+    __shared__ int sCorner[kWavesPerBlock][kWave];
+    __shared__ int sMiss[kWavesPerBlock][2 * kWave];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t total = prefix[n_items];
     int *stk = &sStack[wv][lane];
     const bool f64 = o.fp64_only != 0;
     Cnt c;
-    unsigned long long segs = 0, nvis = 0;
+    unsigned long long segs = 0, nvis = 0, ncert = 0;
     const unsigned long long lt = (1ull << lane) - 1ull;
     while (true) {
         uint32_t g = 0;
@@ -498,21 +546,91 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
         if (o.order_mode == IVM_ORDER_LEARNED && learned) lcode = learned[g];
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
         const int nseg = np * nq;
-        bool vis = false;
-        for (int base = 0; base < nseg; base += kWave) {
-            const int sidx = base + lane;
-            bool clear = false;
-            if (sidx < nseg) {
-                const int a = sidx / nq, b = sidx - (sidx / nq) * nq;
-                const float4 P = sP[wv][a], Q = sQ[wv][b];
-                const Seg s = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
-                ++segs;
-                clear = !any_hit(sc, s, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+        const float inv_np = 1.0f / (float)np, inv_nq = 1.0f / (float)nq;
+        bool vis = false, done = false, first_traversal = true;
+        int cache[kCache];   // wave-uniform list of recent blockers (sorted ranks)
+        int ncache = 0, cpos = 0, nmiss = 0;
+        int *miss = sMiss[wv];
+        for (int base = 0; !done; base += kWave) {
+            const bool more = base < nseg;
+            if (more) {
+                // cache pass: each lane takes one segment in spread order (the first
+                // batch pairs many different p with many q) and tests the recent blockers
+                const int sidx = base + lane;
+                bool need = false;
+                int ab = 0;
+                if (sidx < nseg) {
+                    // (sidx + 1/2) / np sits >= 1/(2 np) >= 1/128 away from an integer and
+                    // sidx < 4096, so the float product's error (< 2e-3) cannot move the floor
+                    const int qa = (int)(((float)sidx + 0.5f) * inv_np);
+                    const int a = sidx - qa * np;
+                    const int t = qa + a;
+                    const int b = t - nq * (int)(((float)t + 0.5f) * inv_nq);
+                    ab = a | (b << 8);
+                    ++segs;
+                    need = true;
+                    if (ncache > 0) {
+                        const float4 P = sP[wv][a], Q = sQ[wv][b];
+                        const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+                        for (int k = 0; k < ncache && need; ++k) {
+                            const int r = cache[k];
+                            ++c.tests;
+                            if (tri_hit(sg, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], o.eps6, f64,
+                                        c.rechecks))
+                                need = false;
+                        }
+                    }
+                }
+                const unsigned long long nm = __ballot(need);
+                if (need) miss[nmiss + __popcll(nm & lt)] = ab;
+                nmiss += __popcll(nm);
+                wave_sync();
             }
-            if (__ballot(clear)) {
-                vis = true;
-                break;
+            // traversal passes over full batches of queued segments (and the tail)
+            while (!done && (nmiss >= kWave || (!more && nmiss > 0))) {
+                const int k = min(kWave, nmiss);
+                int hit = -1;
+                bool clear = false;
+                if (lane < k) {
+                    const int ab = miss[nmiss - k + lane];
+                    const float4 P = sP[wv][ab & 255], Q = sQ[wv][ab >> 8];
+                    const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+                    hit = any_hit(sc, sg, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+                    clear = hit < 0;
+                }
+                nmiss -= k;
+                wave_sync();
+                if (__ballot(clear)) {
+                    vis = done = true;
+                    break;
+                }
+                // remember up to kCache distinct new blockers
+                unsigned long long fm = __ballot(lane < k);
+                for (int added = 0; fm && added < kCache; ++added) {
+                    const int src = __ffsll((long long)fm) - 1;
+                    fm &= fm - 1;
+                    const int r = __shfl(hit, src);
+                    bool dup = false;
+                    for (int m = 0; m < ncache; ++m) dup |= cache[m] == r;
+                    if (dup) continue;
+                    if (ncache < kCache) cache[ncache++] = r;
+                    else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
+                }
+                // the first traversal batch is all blocked: try to prove the whole pair
+                // blocked by the facet that blocked its first lane, then its last lane's
+                if (first_traversal && nseg > kWave) {
+                    first_traversal = false;
+                    const int C1 = __float_as_int(sc.tri[3 * __shfl(hit, 0)].w);
+                    const int C2 = __float_as_int(sc.tri[3 * __shfl(hit, k - 1)].w);
+                    bool blocked = certify_blocked(sc, i, j, C1, sCorner[wv], o.eps6, f64, c);
+                    if (!blocked && C2 != C1) blocked = certify_blocked(sc, i, j, C2, sCorner[wv], o.eps6, f64, c);
+                    if (blocked) {
+                        ++ncert;
+                        done = true;
+                    }
+                }
             }
+            if (!more) done = true;
         }
         if (vis && lane == 0) {
             atomicOr((unsigned long long *)&M[(size_t)i * sc.W + (j >> 6)], 1ull << (j & 63));
@@ -522,6 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
         wave_sync();
     }
     flush_counters(st, c, segs, nvis, 0);
+    if (st && lane == 0 && ncert) atomicAdd((unsigned long long *)&st->certified, ncert);
 }
 
 __global__ void k_pair_stats(ivm_stats *st, const uint32_t *prefix, int n_items, int F) {
@@ -585,9 +704,12 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
     hipLaunchKernelGGL(k_pair_stats, dim3(1), dim3(64), 0, s, stats, (const uint32_t *)prefix, n_items, sc.F);
     const uint64_t *learned = (o.order_mode == IVM_ORDER_LEARNED && L.learned_bytes) ? (const uint64_t *)(ws + L.learned)
                                                                                       : nullptr;
+    if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pairs, dim3(o.grid_blocks), dim3(kBlock), 0, s, sc, (const uint64_t *)cand,
                        (const uint32_t *)prefix, n_items, queue, M, o, stats, learned);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (o.events && (e = hipEventRecord(o.events[1], s)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -648,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_points(SceneDev sc, int N, const flo
         if (act) {
             const Seg s = make_seg(xx, xy, xz, P.x, P.y, P.z);
             ++segs;
-            clear = !any_hit(sc, s, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+            clear = any_hit(sc, s, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c) < 0;
         }
         if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
         wave_sync();
@@ -665,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_los(SceneDev sc, int N, const float 
     if (n < N) {
         const Seg s = make_seg(tx[3 * n], tx[3 * n + 1], tx[3 * n + 2], rx[3 * n], rx[3 * n + 1], rx[3 * n + 2]);
         const bool hit = any_hit(sc, s, -1, -1, kIdentOrder, kTreelets, &sStack[wv][lane], o.stack_depth, o.eps6,
-                                 o.fp64_only != 0, c);
+                                 o.fp64_only != 0, c) >= 0;
         los[n] = hit ? 0 : 1;
     }
 }
@@ -699,8 +821,11 @@ hipError_t launch_points(Scene &scn, const TraverseOpts &o, int N, const float *
     if ((e = launch_fill_u64(rxv, 0ull, (size_t)N * sc.W, s)) != hipSuccess) return e;
     if (N == 0) return hipSuccess;
     hipLaunchKernelGGL(k_check_points, dim3((2 * N + 255) / 256), dim3(256), 0, s, sc, N, tx, rx);
+    if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
     if (sc.S > 0 && sc.F > 0)
         hipLaunchKernelGGL(k_points, dim3(o.grid_blocks), dim3(kBlock), 0, s, sc, N, tx, rx, txv, rxv, o, stats);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (o.events && (e = hipEventRecord(o.events[1], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_los, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, N, tx, rx, los, o);
     return hipGetLastError();
 }
