@@ -123,6 +123,9 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.ftri = (const int *)(ws + L.ffirst);
     d.fhull = (const int *)(ws + L.fhull);
     d.fhull_n = (const int *)(ws + L.fhull_n);
+    d.scluster = (const int *)(ws + L.scluster);
+    d.fchull = (const int *)(ws + L.fchull);
+    d.fchull_n = (const int *)(ws + L.fchull_n);
     d.status = (int *)(ws + L.status);
     d.extent = (const double *)(ws + L.extent);
     sc.n_items = F * d.W;

@@ -63,6 +63,9 @@ struct SceneDev {
     const int *ftri;           // F * 2: first caller triangle of the facet, triangle count
     const int *fhull;          // F * kHullMax: sample indices of the convex hull of the facet's samples
     const int *fhull_n;        // F: hull size (0 = unavailable)
+    const int *scluster;       // S: quadrant cluster (0..3) of each sample within its facet
+    const int *fchull;         // F * 4 * kHullMax: hull sample indices per cluster
+    const int *fchull_n;       // F * 4: cluster hull sizes (0 = unavailable or empty)
     int *status;               // device status bits
     const double *extent;      // [0..5] = sample-unit integer box of vertices+samples as doubles; [6] = E
 };
@@ -71,7 +74,7 @@ struct SceneDev {
 struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
-    size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n;
+    size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n;
     size_t learned_bytes;
     size_t total;
 };

@@ -57,6 +57,9 @@ Layout make_layout(int F, int T, int S, bool learned) {
     L.tri_caller = take(Tn * 3 * sizeof(float4));
     L.fhull = take(Fn * kHullMax * sizeof(int));
     L.fhull_n = take(Fn * sizeof(int));
+    L.scluster = take(Sn * sizeof(int));
+    L.fchull = take(Fn * 4 * kHullMax * sizeof(int));
+    L.fchull_n = take(Fn * 4 * sizeof(int));
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
@@ -158,17 +161,18 @@ __global__ void k_sample_prep(ivm_scene_desc d, int *ibox, int *status) {
     if (bad) atomicOr(status, bad);
 }
 
-// Convex hull (Andrew's monotone chain, strict turns) of a facet's samples,
-// projected on the two axes orthogonal to the normal's largest component.  The
-// sample grid makes every cross product an exact FP64 integer.  Writes up to
-// kHullMax global sample indices; returns the hull size, or 0 if it is larger.
-__device__ int sample_hull(const float *samples, int s0, int ns, int drop, int *out) {
+// Convex hull (Andrew's monotone chain, strict turns) of the samples listed in
+// `list` (global indices), projected on the two axes orthogonal to the normal's
+// largest component.  The sample grid makes every cross product an exact FP64
+// integer.  Writes up to kHullMax global sample indices; returns the hull size,
+// or 0 if it is larger (or the list is empty or too long).
+__device__ int sample_hull(const float *samples, const int *list, int ns, int drop, int *out) {
     if (ns <= 0 || ns > kMaxSamplesPerFacet) return 0;
     const int ax = drop == 0 ? 1 : 0, ay = drop == 2 ? 1 : 2;
     int idx[kMaxSamplesPerFacet];
-    for (int m = 0; m < ns; ++m) idx[m] = m;
-    auto U = [&](int m) { return (double)samples[3 * (s0 + m) + ax]; };
-    auto V = [&](int m) { return (double)samples[3 * (s0 + m) + ay]; };
+    for (int m = 0; m < ns; ++m) idx[m] = list[m];
+    auto U = [&](int g) { return (double)samples[3 * g + ax]; };
+    auto V = [&](int g) { return (double)samples[3 * g + ay]; };
     for (int m = 1; m < ns; ++m) {  // insertion sort by (u, v)
         int x = idx[m];
         int k = m - 1;
@@ -191,15 +195,15 @@ __device__ int sample_hull(const float *samples, int s0, int ns, int drop, int *
         while (n >= lo && turn(h[n - 2], h[n - 1], idx[m]) <= 0.0) --n;
         h[n++] = idx[m];
     }
-    if (n > 1) --n;  // last point repeats the first
-    // duplicates collapse to one point
+    if (n > 1) --n;  // the last point repeats the first; duplicates collapse
     if (n > kHullMax) return 0;
-    for (int m = 0; m < n; ++m) out[m] = s0 + h[m];
+    for (int m = 0; m < n; ++m) out[m] = h[m];
     return n;
 }
 
 __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane, float *fbox, int *soff,
-                             float4 *smp, int *sfacet, int *ibox, int *status, int *fhull, int *fhull_n) {
+                             float4 *smp, int *sfacet, int *ibox, int *status, int *fhull, int *fhull_n,
+                             int *scluster, int *fchull, int *fchull_n) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.n_facets) return;
     int bad = 0;
@@ -261,7 +265,28 @@ __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane
     }
     const double an0 = fabs(n[0]), an1 = fabs(n[1]), an2 = fabs(n[2]);
     const int drop = (an0 >= an1 && an0 >= an2) ? 0 : (an1 >= an2 ? 1 : 2);
-    fhull_n[f] = (bad & kStDegenerate) ? 0 : sample_hull(d.samples, s0, s1 - s0, drop, fhull + kHullMax * f);
+    const int ns = s1 - s0;
+    const bool hull_ok = !(bad & kStDegenerate) && ns > 0 && ns <= kMaxSamplesPerFacet;
+    int list[kMaxSamplesPerFacet];
+    for (int m = 0; m < ns && m < kMaxSamplesPerFacet; ++m) list[m] = s0 + m;
+    fhull_n[f] = hull_ok ? sample_hull(d.samples, list, ns, drop, fhull + kHullMax * f) : 0;
+    // quadrant clusters: split the samples at their centroid along both in-plane axes
+    // (exact: u * ns and the sum of u are FP64 integers on the sample grid)
+    const int ax = drop == 0 ? 1 : 0, ay = drop == 2 ? 1 : 2;
+    double su = 0.0, sv = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        su += (double)d.samples[3 * s + ax];
+        sv += (double)d.samples[3 * s + ay];
+    }
+    for (int cl = 0; cl < 4; ++cl) {
+        int nc = 0;
+        for (int s = s0; s < s1; ++s) {
+            const int c = ((double)d.samples[3 * s + ax] * ns > su ? 1 : 0) + ((double)d.samples[3 * s + ay] * ns > sv ? 2 : 0);
+            if (cl == 0) scluster[s] = c;
+            if (c == cl && nc < kMaxSamplesPerFacet) list[nc++] = s;
+        }
+        fchull_n[4 * f + cl] = hull_ok ? sample_hull(d.samples, list, nc, drop, fchull + (4 * f + cl) * kHullMax) : 0;
+    }
     if (bad) atomicOr(status, bad);
 }
 
@@ -590,7 +615,8 @@ hipError_t launch_build(Scene &sc, hipStream_t s) {
     if (F > 0)
         hipLaunchKernelGGL(k_facet_prep, dim3(nblk(F, 128)), dim3(128), 0, s, d, ffirst, (double *)(ws + L.fplane),
                            (float *)(ws + L.fbox), (int *)(ws + L.soff), (float4 *)(ws + L.smp),
-                           (int *)(ws + L.sfacet), ibox, status, (int *)(ws + L.fhull), (int *)(ws + L.fhull_n));
+                           (int *)(ws + L.sfacet), ibox, status, (int *)(ws + L.fhull), (int *)(ws + L.fhull_n),
+                           (int *)(ws + L.scluster), (int *)(ws + L.fchull), (int *)(ws + L.fchull_n));
     hipLaunchKernelGGL(k_budget, dim3(1), dim3(64), 0, s, d, ibox, (double *)(ws + L.extent), status);
     if (T > 0) {
         uint32_t *keys = (uint32_t *)(ws + L.keys), *vals = (uint32_t *)(ws + L.vals);

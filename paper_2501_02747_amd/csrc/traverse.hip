@@ -494,6 +494,63 @@ __device__ bool certify_blocked(const SceneDev &sc, int i, int j, int C, int *co
     return ok;
 }
 
+// Certificate per sub-pair: the samples of each facet are split into 4
+// quadrant clusters (scene build) and sub-pair (ci, cj) is certified blocked by
+// facet C when every segment between the corners of the two cluster hulls
+// meets C (same convexity argument as above).  Lanes run over the flattened
+// (sub-pair, corner, corner, triangle) items; returns the certified sub-pairs
+// among `todo` (bit 4 ci + cj).
+__device__ unsigned certify_subpairs(const SceneDev &sc, int i, int j, int C, unsigned todo,
+                                     unsigned long long *bits, float eps6, bool f64, Cnt &c) {
+    const int lane = lane_id();
+    const int t0 = sc.ftri[2 * C], nt = sc.ftri[2 * C + 1];
+    if (nt <= 0 || !todo) return 0u;
+    if (lane < 16) bits[lane] = 0ull;
+    wave_sync();
+    int total = 0;
+    for (int sp = 0; sp < 16; ++sp) {
+        if (!((todo >> sp) & 1u)) continue;
+        total += sc.fchull_n[4 * i + (sp >> 2)] * sc.fchull_n[4 * j + (sp & 3)] * nt;
+    }
+    for (int it = lane; it < total; it += kWave) {
+        int run = 0, sp = 0, hi = 0, hj = 0;
+        for (sp = 0; sp < 16; ++sp) {
+            if (!((todo >> sp) & 1u)) continue;
+            hi = sc.fchull_n[4 * i + (sp >> 2)];
+            hj = sc.fchull_n[4 * j + (sp & 3)];
+            const int cnt = hi * hj * nt;
+            if (it < run + cnt) break;
+            run += cnt;
+        }
+        const int local = it - run;
+        const int cp = local / nt, t = local - (local / nt) * nt;
+        const int a = cp / hj, b = cp - (cp / hj) * hj;
+        const float4 P = sc.smp[sc.fchull[(4 * i + (sp >> 2)) * kHullMax + a]];
+        const float4 Q = sc.smp[sc.fchull[(4 * j + (sp & 3)) * kHullMax + b]];
+        const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+        ++c.tests;
+        const float4 *tr = sc.tri_caller + 3 * (t0 + t);
+        if (tri_hit(sg, tr[0], tr[1], tr[2], eps6, f64, c.rechecks)) atomicOr(&bits[sp], 1ull << cp);
+    }
+    wave_sync();
+    bool ok = false;
+    if (lane < 16 && ((todo >> lane) & 1u)) {
+        const int n = sc.fchull_n[4 * i + (lane >> 2)] * sc.fchull_n[4 * j + (lane & 3)];
+        const unsigned long long full = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+        ok = n > 0 && bits[lane] == full;
+    }
+    const unsigned res = (unsigned)(__ballot(ok) & 0xffffull);
+    wave_sync();
+    return res;
+}
+
+// A segment space is a list of rectangles of (admissible p index, admissible q
+// index): rect k covers p in [pa, pa + pn) and q in [qb, qb + qn).
+struct Rects {
+    int n;
+    int pa[16], pn[16], qb[16], qn[16], pre[17];
+};
+
 __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *cand, const uint32_t *prefix,
                                                   int n_items, uint32_t *queue, uint64_t *M, TraverseOpts o,
                                                   ivm_stats *st, const uint64_t *learned) {
@@ -504,12 +561,16 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
     __shared__ int sCorner[kWavesPerBlock][kWave];
     __shared__ int sMiss[kWavesPerBlock][2 * kWave];
+    __shared__ unsigned long long sBits[kWavesPerBlock][16];
+    __shared__ Rects sR[kWavesPerBlock];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t total = prefix[n_items];
     int *stk = &sStack[wv][lane];
+    int *miss = sMiss[wv];
+    Rects &R = sR[wv];
     const bool f64 = o.fp64_only != 0;
     Cnt c;
-    unsigned long long segs = 0, nvis = 0, ncert = 0;
+    unsigned long long segs = 0, nvis = 0, ncert = 0, nsub = 0;
     const unsigned long long lt = (1ull << lane) - 1ull;
     while (true) {
         uint32_t g = 0;
@@ -525,10 +586,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
         const float4 q = lane < nj ? sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
         const bool okp = lane < ni && orient(plj, p.x, p.y, p.z) > 0.0;
         const bool okq = lane < nj && orient(pli, q.x, q.y, q.z) > 0.0;
-        const unsigned long long mp = __ballot(okp), mq = __ballot(okq);
-        const int np = __popcll(mp), nq = __popcll(mq);
-        if (okp) sP[wv][__popcll(mp & lt)] = p;
-        if (okq) sQ[wv][__popcll(mq & lt)] = q;
+        const int clp = lane < ni ? sc.scluster[si0 + lane] : 0;
+        const int clq = lane < nj ? sc.scluster[sj0 + lane] : 0;
+        // compact admissible samples grouped by cluster: cluster c of i occupies
+        // [pco[c], pco[c + 1]) of sP
+        int pco[5], qco[5];
+        pco[0] = qco[0] = 0;
+        for (int cl = 0; cl < 4; ++cl) {
+            const unsigned long long mpc = __ballot(okp && clp == cl), mqc = __ballot(okq && clq == cl);
+            if (okp && clp == cl) sP[wv][pco[cl] + __popcll(mpc & lt)] = p;
+            if (okq && clq == cl) sQ[wv][qco[cl] + __popcll(mqc & lt)] = q;
+            pco[cl + 1] = pco[cl] + __popcll(mpc);
+            qco[cl + 1] = qco[cl] + __popcll(mqc);
+        }
+        const int np = pco[4], nq = qco[4];
         // bounding box of every admissible segment
         float lo[3], hi[3];
         {
@@ -545,12 +616,17 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
         unsigned long long lcode = 0;
         if (o.order_mode == IVM_ORDER_LEARNED && learned) lcode = learned[g];
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
-        const int nseg = np * nq;
-        const float inv_np = 1.0f / (float)np, inv_nq = 1.0f / (float)nq;
+        // phase 0: the whole product space, until the first traversal batch
+        if (lane == 0) {
+            R.n = 1;
+            R.pa[0] = 0; R.pn[0] = np; R.qb[0] = 0; R.qn[0] = nq;
+            R.pre[0] = 0; R.pre[1] = np * nq;
+        }
+        wave_sync();
+        int nseg = np * nq;
         bool vis = false, done = false, first_traversal = true;
         int cache[kCache];   // wave-uniform list of recent blockers (sorted ranks)
         int ncache = 0, cpos = 0, nmiss = 0;
-        int *miss = sMiss[wv];
         for (int base = 0; !done; base += kWave) {
             const bool more = base < nseg;
             if (more) {
@@ -560,20 +636,24 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
                 bool need = false;
                 int ab = 0;
                 if (sidx < nseg) {
-                    // (sidx + 1/2) / np sits >= 1/(2 np) >= 1/128 away from an integer and
-                    // sidx < 4096, so the float product's error (< 2e-3) cannot move the floor
-                    const int qa = (int)(((float)sidx + 0.5f) * inv_np);
-                    const int a = sidx - qa * np;
-                    const int t = qa + a;
-                    const int b = t - nq * (int)(((float)t + 0.5f) * inv_nq);
+                    int k = 0;
+                    while (k + 1 < R.n && sidx >= R.pre[k + 1]) ++k;
+                    const int local = sidx - R.pre[k], pn = R.pn[k], qn = R.qn[k];
+                    // (local + 1/2) / pn sits >= 1/(2 pn) >= 1/128 away from an integer and
+                    // local < 4096, so the float product's error (< 2e-3) cannot move the floor
+                    const int qa = (int)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)pn));
+                    const int al = local - qa * pn;
+                    const int t = qa + al;
+                    const int bl = t - qn * (int)(((float)t + 0.5f) * __builtin_amdgcn_rcpf((float)qn));
+                    const int a = R.pa[k] + al, b = R.qb[k] + bl;
                     ab = a | (b << 8);
                     ++segs;
                     need = true;
                     if (ncache > 0) {
                         const float4 P = sP[wv][a], Q = sQ[wv][b];
                         const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
-                        for (int k = 0; k < ncache && need; ++k) {
-                            const int r = cache[k];
+                        for (int m = 0; m < ncache && need; ++m) {
+                            const int r = cache[m];
                             ++c.tests;
                             if (tri_hit(sg, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], o.eps6, f64,
                                         c.rechecks))
@@ -616,10 +696,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
                     if (ncache < kCache) cache[ncache++] = r;
                     else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
                 }
-                // the first traversal batch is all blocked: try to prove the whole pair
-                // blocked by the facet that blocked its first lane, then its last lane's
                 if (first_traversal && nseg > kWave) {
                     first_traversal = false;
+                    // the first traversal batch is all blocked: try to prove the whole pair
+                    // blocked by the facet that blocked its first lane, then its last lane's
                     const int C1 = __float_as_int(sc.tri[3 * __shfl(hit, 0)].w);
                     const int C2 = __float_as_int(sc.tri[3 * __shfl(hit, k - 1)].w);
                     bool blocked = certify_blocked(sc, i, j, C1, sCorner[wv], o.eps6, f64, c);
@@ -627,10 +707,59 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
                     if (blocked) {
                         ++ncert;
                         done = true;
+                        break;
+                    }
+                    // then sub-pair by sub-pair with every facet seen blocking so far; the
+                    // uncertified sub-pairs become the new segment space
+                    unsigned todo = 0u;
+                    int biggest = 0;
+                    for (int sp = 0; sp < 16; ++sp) {
+                        const int pn = pco[(sp >> 2) + 1] - pco[sp >> 2], qn = qco[(sp & 3) + 1] - qco[sp & 3];
+                        if (pn > 0 && qn > 0) todo |= 1u << sp;
+                        biggest = max(biggest, pn * qn);
+                    }
+                    if (biggest >= 2 * kWave) {
+                        int tried[kCache];
+                        int ntried = 0;
+                        for (int m = 0; m < ncache && todo; ++m) {
+                            const int C = __float_as_int(sc.tri[3 * cache[m]].w);
+                            bool seen = false;
+                            for (int u = 0; u < ntried; ++u) seen |= tried[u] == C;
+                            if (seen) continue;
+                            tried[ntried++] = C;
+                            todo &= ~certify_subpairs(sc, i, j, C, todo, sBits[wv], o.eps6, f64, c);
+                        }
+                        if (!todo) {
+                            ++ncert;
+                            done = true;
+                            break;
+                        }
+                        ++nsub;
+                        if (lane == 0) {
+                            int nr = 0, run = 0;
+                            for (int sp = 0; sp < 16; ++sp) {
+                                if (!((todo >> sp) & 1u)) continue;
+                                const int ci = sp >> 2, cj = sp & 3;
+                                R.pa[nr] = pco[ci];
+                                R.pn[nr] = pco[ci + 1] - pco[ci];
+                                R.qb[nr] = qco[cj];
+                                R.qn[nr] = qco[cj + 1] - qco[cj];
+                                R.pre[nr] = run;
+                                run += R.pn[nr] * R.qn[nr];
+                                ++nr;
+                            }
+                            R.pre[nr] = run;
+                            R.n = nr;
+                        }
+                        wave_sync();
+                        nseg = R.pre[R.n];
+                        base = -kWave;  // restart the cache passes over the new space
+                        nmiss = 0;
+                        break;
                     }
                 }
             }
-            if (!more) done = true;
+            if (!more && nmiss == 0) done = true;
         }
         if (vis && lane == 0) {
             atomicOr((unsigned long long *)&M[(size_t)i * sc.W + (j >> 6)], 1ull << (j & 63));
@@ -641,6 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
     }
     flush_counters(st, c, segs, nvis, 0);
     if (st && lane == 0 && ncert) atomicAdd((unsigned long long *)&st->certified, ncert);
+    if (st && lane == 0 && nsub) atomicAdd((unsigned long long *)&st->reserved[0], nsub);
 }
 
 __global__ void k_pair_stats(ivm_stats *st, const uint32_t *prefix, int n_items, int F) {
@@ -719,61 +849,154 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
 __constant__ uint8_t kIdentOrder[kTreelets] = {0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13, 14, 15,
                                                16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
 
-// Items are (snapshot, side, chunk of 64 consecutive samples); lane = sample.
+// Items are (snapshot, side, chunk of 64 consecutive samples); each wave walks a
+// contiguous range of items so consecutive items share the Tx or Rx point.  A
+// lane first tests its sample's segment against the wave's recent blockers;
+// the misses are queued in LDS and traversed in full 64-lane batches.  The
+// queue is drained whenever the point changes.  Samples of facets already
+// known visible are skipped (a set bit is never cleared, so a stale read only
+// costs work).
 __global__ __launch_bounds__(kBlock) void k_points(SceneDev sc, int N, const float *tx, const float *rx, uint64_t *txv,
                                                    uint64_t *rxv, TraverseOpts o, ivm_stats *st) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
+    __shared__ int sMiss[kWavesPerBlock][2 * kWave];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     int *stk = &sStack[wv][lane];
+    int *miss = sMiss[wv];
     const bool f64 = o.fp64_only != 0;
     const int nch = (sc.S + kWave - 1) / kWave;
     const long long n_items = (long long)N * 2 * nch;
     const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
     const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    const long long per = (n_items + nwaves - 1) / nwaves;
+    const long long it0 = wave * per, it1 = min(n_items, it0 + per);
+    const unsigned long long lt = (1ull << lane) - 1ull;
     Cnt c;
     unsigned long long segs = 0, items = 0;
-    for (long long it = wave; it < n_items; it += nwaves) {
-        const int n = (int)(it / (2 * nch));
-        const int rem = (int)(it - (long long)n * 2 * nch);
-        const int side = rem / nch, chunk = rem - side * nch;
-        const float *X = (side ? rx : tx) + 3 * n;
-        uint64_t *out = (side ? rxv : txv) + (size_t)n * sc.W;
-        const float xx = X[0], xy = X[1], xz = X[2];
+    int cache[kCache];
+    int ncache = 0, cpos = 0, nmiss = 0, n_order = 0;
+    int cur = -1;  // current (snapshot, side) = 2 n + side
+    float xx = 0.f, xy = 0.f, xz = 0.f;
+    uint64_t *out = nullptr;
+    for (long long it = it0; it <= it1; ++it) {
+        const bool more = it < it1;
+        int key = -1, chunk = 0;
+        if (more) {
+            const int n = (int)(it / (2 * nch));
+            const int rem = (int)(it - (long long)n * 2 * nch);
+            const int side = rem / nch;
+            chunk = rem - side * nch;
+            key = 2 * n + side;
+        }
+        // drain the queue when the point changes (or at the end)
+        while (nmiss > 0 && key != cur) {
+            const int k = min(kWave, nmiss);
+            bool clear = false;
+            int hit = -1, f = -1;
+            if (lane < k) {
+                const int s = miss[nmiss - k + lane];
+                f = sc.sfacet[s];
+                const float4 P = sc.smp[s];
+                const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+                hit = any_hit(sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+                clear = hit < 0;
+            }
+            nmiss -= k;
+            wave_sync();
+            if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+            unsigned long long fm = __ballot(lane < k && !clear);
+            for (int added = 0; fm && added < kCache; ++added) {
+                const int src = __ffsll((long long)fm) - 1;
+                fm &= fm - 1;
+                const int r = __shfl(hit, src);
+                bool dup = false;
+                for (int m = 0; m < ncache; ++m) dup |= cache[m] == r;
+                if (dup) continue;
+                if (ncache < kCache) cache[ncache++] = r;
+                else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
+            }
+        }
+        if (!more) break;
+        if (key != cur) {
+            cur = key;
+            const int n = key >> 1, side = key & 1;
+            const float *X = (side ? rx : tx) + 3 * n;
+            xx = X[0]; xy = X[1]; xz = X[2];
+            out = (side ? rxv : txv) + (size_t)n * sc.W;
+            ncache = 0;
+            cpos = 0;
+            // treelet order for this point: nearest treelet box first (a heuristic only)
+            const float xp[3] = {xx, xy, xz};
+            const int mode = o.order_mode == IVM_ORDER_LEARNED ? IVM_ORDER_PLAIN : o.order_mode;
+            unsigned long long tk = ~0ull;
+            if (lane < kTreelets && sc.tl_root[lane] != kNone) {
+                const float *b = sc.tl_box + 6 * lane;
+                float d2 = 0.f;
+                for (int q = 0; q < 3; ++q) {
+                    const float cq = fmaxf(fmaxf(b[q] - xp[q], xp[q] - b[3 + q]), 0.f);
+                    d2 += cq * cq;
+                }
+                const unsigned dk = __float_as_uint(d2);
+                tk = mode == IVM_ORDER_INDEX ? (unsigned long long)lane
+                     : (mode == IVM_ORDER_REVERSED ? (unsigned long long)(0xffffffffu - dk) : dk);
+            }
+            n_order = wave_rank_order(tk, sKey[wv], sOrder[wv]);
+        }
         const int sidx = chunk * kWave + lane;
-        bool act = sidx < sc.S;
-        int f = 0;
-        float4 P = make_float4(0, 0, 0, 0);
-        if (act) {
-            f = sc.sfacet[sidx];
-            P = sc.smp[sidx];
-            act = orient(sc.fplane + 6 * f, xx, xy, xz) > 0.0;
+        bool need = false;
+        if (sidx < sc.S) {
+            const int f = sc.sfacet[sidx];
+            need = orient(sc.fplane + 6 * f, xx, xy, xz) > 0.0 && !((out[f >> 6] >> (f & 63)) & 1ull);
+            if (need) {
+                ++segs;
+                if (ncache > 0) {
+                    const float4 P = sc.smp[sidx];
+                    const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+                    for (int k = 0; k < ncache && need; ++k) {
+                        const int r = cache[k];
+                        if (__float_as_int(sc.tri[3 * r].w) == f) continue;
+                        ++c.tests;
+                        if (tri_hit(sg, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], o.eps6, f64, c.rechecks))
+                            need = false;
+                    }
+                }
+            }
         }
-        if (!__ballot(act)) continue;
-        ++items;
-        float lo[3], hi[3];
-        {
-            const float big = INFINITY;
-            lo[0] = fminf(xx, wave_min(act ? P.x : big));
-            lo[1] = fminf(xy, wave_min(act ? P.y : big));
-            lo[2] = fminf(xz, wave_min(act ? P.z : big));
-            hi[0] = fmaxf(xx, wave_max(act ? P.x : -big));
-            hi[1] = fmaxf(xy, wave_max(act ? P.y : -big));
-            hi[2] = fmaxf(xz, wave_max(act ? P.z : -big));
-        }
-        const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode == IVM_ORDER_LEARNED
-                                                                                ? IVM_ORDER_PLAIN
-                                                                                : o.order_mode, 0ull),
-                                            sKey[wv], sOrder[wv]);
-        bool clear = false;
-        if (act) {
-            const Seg s = make_seg(xx, xy, xz, P.x, P.y, P.z);
-            ++segs;
-            clear = any_hit(sc, s, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c) < 0;
-        }
-        if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+        const unsigned long long nm = __ballot(need);
+        if (nm) ++items;
+        if (need) miss[nmiss + __popcll(nm & lt)] = sidx;
+        nmiss += __popcll(nm);
         wave_sync();
+        // full traversal batches
+        while (nmiss >= kWave) {
+            const int k = kWave;
+            bool clear = false;
+            int hit = -1, f = -1;
+            {
+                const int s = miss[nmiss - k + lane];
+                f = sc.sfacet[s];
+                const float4 P = sc.smp[s];
+                const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+                hit = any_hit(sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+                clear = hit < 0;
+            }
+            nmiss -= k;
+            wave_sync();
+            if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+            unsigned long long fm = __ballot(!clear);
+            for (int added = 0; fm && added < kCache; ++added) {
+                const int src = __ffsll((long long)fm) - 1;
+                fm &= fm - 1;
+                const int r = __shfl(hit, src);
+                bool dup = false;
+                for (int m = 0; m < ncache; ++m) dup |= cache[m] == r;
+                if (dup) continue;
+                if (ncache < kCache) cache[ncache++] = r;
+                else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
+            }
+        }
     }
     flush_counters(st, c, segs, 0, items);
 }
