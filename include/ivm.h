@@ -213,6 +213,62 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
                                      int64_t *d_offsets, int32_t *d_paths, size_t paths_cap,
                                      hipStream_t stream);
 
+/* ---- learned occluder ordering ---------------------------------------------
+ * A small network scores, for a facet pair, how likely each of the 32 treelets is
+ * to hold an occluder; IVM_ORDER_LEARNED visits the treelets in that order.  The
+ * exact tests still decide every bit, so the order never changes a result.
+ * Network: 24 -> 128 -> 128 -> 128 -> 32, ReLU on hidden layers, linear scores;
+ * loss: mean binary cross-entropy with logits; optimiser: Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected).  Parameters are one FP32 array of
+ * IVM_MLP_PARAMS values laid out W0[128][24], b0[128], W1[128][128], b1[128],
+ * W2[128][128], b2[128], W3[32][128], b3[32].
+ * Features of pair (i, j), with the scene box centre c0 and half-size s (largest
+ * axis) of all vertices: centroid of i's samples and of j's, (x - c0) / s (3 + 3);
+ * unit normals of i and j (3 + 3); areas / s^2 (1 + 1); distance between the
+ * centroids (1); the AABB of both facets, min then max, (x - c0) / s (3 + 3);
+ * unit direction from i's centroid to j's (3, zero if they coincide). */
+#define IVM_MLP_FEATURES 24
+#define IVM_MLP_HIDDEN 128
+#define IVM_MLP_OUTPUTS 32
+#define IVM_MLP_PARAMS 40352
+
+#define IVM_MODEL_BF16 0 /* GEMMs on BF16 MFMA with FP32 accumulation */
+#define IVM_MODEL_FP32 1 /* GEMMs in FP32 on the vector ALUs (reference mode) */
+
+typedef struct ivm_model ivm_model; /* opaque host handle */
+
+/* Device workspace for a model that trains or evaluates batches of up to max_batch rows. */
+ivm_status ivm_model_workspace_size(int32_t max_batch, size_t *bytes);
+/* d_workspace (caller-owned, 256-byte aligned) holds parameters, gradients, Adam
+ * state and activations.  Parameters start at zero: set them before use. */
+ivm_status ivm_model_create(void *d_workspace, size_t workspace_bytes, int32_t max_batch, int32_t precision,
+                            ivm_model **out);
+ivm_status ivm_model_destroy(ivm_model *model);
+/* Copy IVM_MLP_PARAMS FP32 values (device) into the model and reset Adam. */
+ivm_status ivm_model_set_params(ivm_model *model, const float *d_params, hipStream_t stream);
+ivm_status ivm_model_get_params(const ivm_model *model, float *d_params, hipStream_t stream);
+/* Scores (logits) float[n][32] for features float[n][24], n <= max_batch. */
+ivm_status ivm_model_forward(ivm_model *model, int32_t n, const float *d_x, float *d_logits, hipStream_t stream);
+/* Mean BCE-with-logits loss (float[1]) and its gradient (float[IVM_MLP_PARAMS])
+ * for labels float[n][32] in {0, 1}; parameters are not changed. */
+ivm_status ivm_model_loss_grad(ivm_model *model, int32_t n, const float *d_x, const float *d_y, float *d_loss,
+                               float *d_grad, hipStream_t stream);
+/* One Adam step with learning rate lr on the batch; d_loss (may be NULL) gets the
+ * loss before the step. */
+ivm_status ivm_model_train_step(ivm_model *model, int32_t n, const float *d_x, const float *d_y, float lr,
+                                float *d_loss, hipStream_t stream);
+/* Features float[n][24] of the pairs (d_i[k], d_j[k]) (see above). */
+ivm_status ivm_pair_features(const ivm_scene *scene, int32_t n, const int32_t *d_i, const int32_t *d_j, float *d_x,
+                             hipStream_t stream);
+/* Hit records: for each pair, bit k of d_labels[k] is set iff some triangle of
+ * treelet k (see ivm_triangle_groups) meets an admissible segment of the pair
+ * (all hits, not the first).  Pairs with no admissible segment get 0. */
+ivm_status ivm_pair_occluder_labels(ivm_scene *scene, int32_t n, const int32_t *d_i, const int32_t *d_j,
+                                    uint32_t *d_labels, hipStream_t stream);
+/* Attach (or, with NULL, detach) the model used by IVM_ORDER_LEARNED.  The scene
+ * must have been built with IVM_SCENE_LEARNED. */
+ivm_status ivm_scene_set_model(ivm_scene *scene, const ivm_model *model);
+
 /* Treelet (Morton group) index of every triangle in the caller's triangle order:
  * d_group is int32[T].  Treelet k holds sorted ranks [ceil(k T / 32), ceil((k+1) T / 32)). */
 ivm_status ivm_triangle_groups(const ivm_scene *scene, int32_t *d_group, hipStream_t stream);

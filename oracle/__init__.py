@@ -383,6 +383,54 @@ def image_paths(scene, orc: Oracle, T, R, K: int) -> List[Tuple[int, ...]]:
 MLP_SIZES = (24, 128, 128, 128, 32)
 
 
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    u = np.ascontiguousarray(np.asarray(x, np.float64).astype(np.float32)).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def pair_features(scene, I, J) -> np.ndarray:
+    """The 24 features of facet pairs (i, j), in FP64, from their definition:
+    with the box of all triangle vertices (centre c0, half-size s of its largest
+    axis): centroids of the two facets' samples, (x - c0) / s; unit normals of the
+    first triangles; areas / s^2; distance between the normalised centroids; the
+    AABB of both facets' vertices, min then max, (x - c0) / s; unit direction from
+    the first centroid to the second (zero when they coincide)."""
+    V = scene.vertices.astype(np.float64)
+    tv = V[scene.tri_vertices]
+    lo, hi = tv.reshape(-1, 3).min(0), tv.reshape(-1, 3).max(0)
+    c0 = (lo + hi) / 2
+    hs = float(((hi - lo) / 2).max())
+    hs = hs if hs > 0 else 1.0
+    F = scene.n_facets
+    smp = scene.samples.astype(np.float64)
+    off = scene.sample_offsets
+    cent = np.array([smp[off[f]:off[f + 1]].mean(0) for f in range(F)])
+    first = np.full(F, -1)
+    for t in range(scene.n_triangles - 1, -1, -1):
+        first[scene.tri_facet[t]] = t
+    e1 = tv[:, 1] - tv[:, 0]
+    e2 = tv[:, 2] - tv[:, 0]
+    cr = np.cross(e1, e2)
+    nrm = cr[first] / np.linalg.norm(cr[first], axis=1, keepdims=True)
+    area = np.zeros(F)
+    np.add.at(area, scene.tri_facet, 0.5 * np.linalg.norm(cr, axis=1))
+    blo = np.full((F, 3), np.inf)
+    bhi = np.full((F, 3), -np.inf)
+    np.minimum.at(blo, scene.tri_facet, tv.min(1))
+    np.maximum.at(bhi, scene.tri_facet, tv.max(1))
+    I = np.asarray(I)
+    J = np.asarray(J)
+    ci, cj = (cent[I] - c0) / hs, (cent[J] - c0) / hs
+    d = cj - ci
+    dist = np.linalg.norm(d, axis=1)
+    safe = np.where(dist > 0, dist, 1.0)
+    direc = np.where(dist[:, None] > 0, d / safe[:, None], 0.0)
+    return np.concatenate([ci, cj, nrm[I], nrm[J], area[I, None] / hs ** 2, area[J, None] / hs ** 2, dist[:, None],
+                           (np.minimum(blo[I], blo[J]) - c0) / hs, (np.maximum(bhi[I], bhi[J]) - c0) / hs, direc], 1)
+
+
 def mlp_init(seed: int = 0, sizes=MLP_SIZES) -> Dict[str, np.ndarray]:
     """Deterministic He-uniform initialisation (numpy PCG64 with the given seed)."""
     rng = np.random.default_rng(seed)
@@ -395,13 +443,16 @@ def mlp_init(seed: int = 0, sizes=MLP_SIZES) -> Dict[str, np.ndarray]:
     return p
 
 
-def mlp_forward(p: Dict[str, np.ndarray], X: np.ndarray):
-    """ReLU hidden layers, linear output.  Returns (logits, activations)."""
+def mlp_forward(p: Dict[str, np.ndarray], X: np.ndarray, bf16: bool = False):
+    """ReLU hidden layers, linear output.  Returns (logits, activations).  With
+    bf16=True both operands of every product are first rounded to BF16 (the
+    arithmetic of a BF16 matrix unit with wide accumulation)."""
+    r = bf16_round if bf16 else (lambda a: a)
     acts = [np.asarray(X, np.float64)]
     L = len([k for k in p if k.startswith("W")])
     h = acts[0]
     for l in range(L):
-        z = h @ p[f"W{l}"].T + p[f"b{l}"]
+        z = r(h) @ r(p[f"W{l}"]).T + p[f"b{l}"]
         h = np.maximum(z, 0.0) if l < L - 1 else z
         acts.append(h)
     return h, acts
@@ -412,20 +463,39 @@ def bce_with_logits(z: np.ndarray, y: np.ndarray) -> float:
     return float(np.mean(np.maximum(z, 0.0) - z * y + np.log1p(np.exp(-np.abs(z)))))
 
 
-def mlp_loss_grad(p: Dict[str, np.ndarray], X: np.ndarray, Y: np.ndarray):
-    """Loss and gradients of the mean BCE-with-logits loss."""
-    z, acts = mlp_forward(p, X)
+def mlp_loss_grad(p: Dict[str, np.ndarray], X: np.ndarray, Y: np.ndarray, bf16: bool = False):
+    """Loss and gradients of the mean BCE-with-logits loss (operands of every
+    product rounded to BF16 when bf16=True, as in mlp_forward)."""
+    r = bf16_round if bf16 else (lambda a: a)
+    z, acts = mlp_forward(p, X, bf16)
     loss = bce_with_logits(z, Y)
     L = len([k for k in p if k.startswith("W")])
     dz = (1.0 / (1.0 + np.exp(-z)) - Y) / z.size
     g = {}
     for l in range(L - 1, -1, -1):
-        g[f"W{l}"] = dz.T @ acts[l]
+        g[f"W{l}"] = r(dz).T @ r(acts[l])
         g[f"b{l}"] = dz.sum(0)
         if l > 0:
-            dh = dz @ p[f"W{l}"]
+            dh = r(dz) @ r(p[f"W{l}"])
             dz = dh * (acts[l] > 0.0)
     return loss, g
+
+
+def mlp_flatten(p: Dict[str, np.ndarray]) -> np.ndarray:
+    """Parameters as one array: W0, b0, W1, b1, W2, b2, W3, b3 (row-major)."""
+    L = len([k for k in p if k.startswith("W")])
+    return np.concatenate([np.concatenate([p[f"W{l}"].ravel(), p[f"b{l}"].ravel()]) for l in range(L)])
+
+
+def mlp_unflatten(v: np.ndarray, sizes=MLP_SIZES) -> Dict[str, np.ndarray]:
+    p, o = {}, 0
+    for l in range(len(sizes) - 1):
+        n, k = sizes[l + 1], sizes[l]
+        p[f"W{l}"] = np.asarray(v[o:o + n * k], np.float64).reshape(n, k)
+        o += n * k
+        p[f"b{l}"] = np.asarray(v[o:o + n], np.float64).copy()
+        o += n
+    return p
 
 
 def adam_step(p, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -37,7 +37,13 @@ EXPORTED = [
     "ivm_status_string", "ivm_scene_workspace_size", "ivm_build_scene", "ivm_scene_status",
     "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
     "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups",
+    "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
+    "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
+    "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
 ]
+
+IVM_MLP_FEATURES, IVM_MLP_HIDDEN, IVM_MLP_OUTPUTS, IVM_MLP_PARAMS = 24, 128, 32, 40352
+IVM_MODEL_BF16, IVM_MODEL_FP32 = 0, 1
 
 
 class IvmError(RuntimeError):
@@ -113,6 +119,27 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_image_tree_candidates.argtypes = [P, P, i32, P, P, P, i32, P, P, P, sz, P]
     lib.ivm_triangle_groups.restype = i32
     lib.ivm_triangle_groups.argtypes = [P, P, P]
+    lib.ivm_model_workspace_size.restype = i32
+    lib.ivm_model_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
+    lib.ivm_model_create.restype = i32
+    lib.ivm_model_create.argtypes = [P, sz, i32, i32, ctypes.POINTER(P)]
+    lib.ivm_model_destroy.restype = i32
+    lib.ivm_model_destroy.argtypes = [P]
+    for name in ("ivm_model_set_params", "ivm_model_get_params"):
+        getattr(lib, name).restype = i32
+        getattr(lib, name).argtypes = [P, P, P]
+    lib.ivm_model_forward.restype = i32
+    lib.ivm_model_forward.argtypes = [P, i32, P, P, P]
+    lib.ivm_model_loss_grad.restype = i32
+    lib.ivm_model_loss_grad.argtypes = [P, i32, P, P, P, P, P]
+    lib.ivm_model_train_step.restype = i32
+    lib.ivm_model_train_step.argtypes = [P, i32, P, P, ctypes.c_float, P, P]
+    lib.ivm_pair_features.restype = i32
+    lib.ivm_pair_features.argtypes = [P, i32, P, P, P, P]
+    lib.ivm_pair_occluder_labels.restype = i32
+    lib.ivm_pair_occluder_labels.argtypes = [P, i32, P, P, P, P]
+    lib.ivm_scene_set_model.restype = i32
+    lib.ivm_scene_set_model.argtypes = [P, P]
     _lib = lib
     return lib
 
@@ -342,6 +369,94 @@ def ivm_triangle_groups(scene: GpuScene, stream=None):
     out = torch.empty((max(scene.T, 1),), dtype=torch.int32, device=scene.device)
     _check(load_library().ivm_triangle_groups(scene.handle, _ptr(out), _stream(stream)), "ivm_triangle_groups")
     return out[: scene.T]
+
+
+# ---- learned occluder ordering ------------------------------------------------------
+
+class Model:
+    """The occluder-ordering network (parameters, gradients, Adam state in one
+    device workspace).  precision: IVM_MODEL_BF16 (MFMA) or IVM_MODEL_FP32."""
+
+    def __init__(self, max_batch: int = 1024, precision: int = IVM_MODEL_BF16, device: str = "cuda"):
+        import torch
+        lib = load_library()
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.ivm_model_workspace_size(max_batch, ctypes.byref(nbytes)), "ivm_model_workspace_size")
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=device)
+        aligned = (int(self.workspace.data_ptr()) + 255) & ~255
+        self.handle = ctypes.c_void_p()
+        _check(lib.ivm_model_create(aligned, int(nbytes.value), max_batch, precision, ctypes.byref(self.handle)),
+               "ivm_model_create")
+        self.max_batch, self.precision, self.device = max_batch, precision, torch.device(device)
+
+    def set_params(self, params, stream=None):
+        import torch
+        t = torch.as_tensor(np.ascontiguousarray(params, np.float32) if isinstance(params, np.ndarray) else params,
+                            dtype=torch.float32).to(self.device).contiguous()
+        assert t.numel() == IVM_MLP_PARAMS
+        _check(load_library().ivm_model_set_params(self.handle, _ptr(t), _stream(stream)), "ivm_model_set_params")
+        torch.cuda.current_stream().synchronize()
+
+    def get_params(self, stream=None):
+        import torch
+        out = torch.empty(IVM_MLP_PARAMS, dtype=torch.float32, device=self.device)
+        _check(load_library().ivm_model_get_params(self.handle, _ptr(out), _stream(stream)), "ivm_model_get_params")
+        return out
+
+    def forward(self, x, stream=None):
+        import torch
+        n = int(x.shape[0])
+        out = torch.empty((n, IVM_MLP_OUTPUTS), dtype=torch.float32, device=self.device)
+        _check(load_library().ivm_model_forward(self.handle, n, _ptr(x), _ptr(out), _stream(stream)),
+               "ivm_model_forward")
+        return out
+
+    def loss_grad(self, x, y, stream=None):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty(IVM_MLP_PARAMS, dtype=torch.float32, device=self.device)
+        _check(load_library().ivm_model_loss_grad(self.handle, int(x.shape[0]), _ptr(x), _ptr(y), _ptr(loss),
+                                                  _ptr(grad), _stream(stream)), "ivm_model_loss_grad")
+        return loss, grad
+
+    def train_step(self, x, y, lr: float = 1e-3, loss=None, stream=None):
+        _check(load_library().ivm_model_train_step(self.handle, int(x.shape[0]), _ptr(x), _ptr(y), float(lr),
+                                                   _ptr(loss), _stream(stream)), "ivm_model_train_step")
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load_library().ivm_model_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ivm_pair_features(scene: GpuScene, I, J, stream=None):
+    import torch
+    n = int(I.shape[0])
+    out = torch.empty((n, IVM_MLP_FEATURES), dtype=torch.float32, device=scene.device)
+    _check(load_library().ivm_pair_features(scene.handle, n, _ptr(I), _ptr(J), _ptr(out), _stream(stream)),
+           "ivm_pair_features")
+    return out
+
+
+def ivm_pair_occluder_labels(scene: GpuScene, I, J, stream=None):
+    import torch
+    n = int(I.shape[0])
+    out = torch.empty((n,), dtype=torch.int32, device=scene.device)
+    _check(load_library().ivm_pair_occluder_labels(scene.handle, n, _ptr(I), _ptr(J), _ptr(out), _stream(stream)),
+           "ivm_pair_occluder_labels")
+    return out
+
+
+def ivm_scene_set_model(scene: GpuScene, model: Optional[Model]):
+    _check(load_library().ivm_scene_set_model(scene.handle, model.handle if model is not None else None),
+           "ivm_scene_set_model")
+    scene._model = model
 
 
 # ---- host-side helpers (no visibility arithmetic) --------------------------------

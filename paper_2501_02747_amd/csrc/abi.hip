@@ -13,6 +13,12 @@ struct ivm_scene {
     Scene s;
 };
 
+struct ivm_model {
+    Model m;
+    void *ws;
+    size_t bytes;
+};
+
 namespace {
 
 ivm_status status_from_bits(int bits) {
@@ -126,6 +132,8 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.scluster = (const int *)(ws + L.scluster);
     d.fchull = (const int *)(ws + L.fchull);
     d.fchull_n = (const int *)(ws + L.fchull_n);
+    d.ffeat = (const float *)(ws + L.ffeat);
+    d.fnorm = (const float *)(ws + L.fnorm);
     d.status = (int *)(ws + L.status);
     d.extent = (const double *)(ws + L.extent);
     sc.n_items = F * d.W;
@@ -222,6 +230,114 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
     if (launch_candidates_fill(d, d_M, n_snap, d_tx_vis, d_rx_vis, max_order, d_offsets, d_paths, stream) !=
         hipSuccess)
         return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_model_workspace_size(int32_t max_batch, size_t *bytes) {
+    if (!bytes || max_batch <= 0 || max_batch > (1 << 24)) return IVM_ERR_INVALID_ARGUMENT;
+    *bytes = model_workspace_bytes(max_batch);
+    return IVM_OK;
+}
+
+ivm_status ivm_model_create(void *d_workspace, size_t workspace_bytes, int32_t max_batch, int32_t precision,
+                            ivm_model **out) {
+    if (!out) return IVM_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (!d_workspace || max_batch <= 0 || max_batch > (1 << 24)) return IVM_ERR_INVALID_ARGUMENT;
+    if (precision != IVM_MODEL_BF16 && precision != IVM_MODEL_FP32) return IVM_ERR_INVALID_ARGUMENT;
+    if (((uintptr_t)d_workspace & 255u) != 0) return IVM_ERR_INVALID_ARGUMENT;
+    if (workspace_bytes < model_workspace_bytes(max_batch)) return IVM_ERR_WORKSPACE;
+    ivm_model *h = new (std::nothrow) ivm_model();
+    if (!h) return IVM_ERR_INVALID_ARGUMENT;
+    h->ws = d_workspace;
+    h->bytes = workspace_bytes;
+    model_bind(h->m, d_workspace, max_batch, precision);
+    if (launch_fill_u32((uint32_t *)h->m.params, 0u, 4 * (size_t)kParams, nullptr) != hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess) {
+        delete h;
+        return IVM_ERR_HIP;
+    }
+    *out = h;
+    return IVM_OK;
+}
+
+ivm_status ivm_model_destroy(ivm_model *model) {
+    if (!model) return IVM_ERR_INVALID_ARGUMENT;
+    delete model;
+    return IVM_OK;
+}
+
+ivm_status ivm_model_set_params(ivm_model *model, const float *d_params, hipStream_t stream) {
+    if (!model || !d_params) return IVM_ERR_INVALID_ARGUMENT;
+    Model &m = model->m;
+    if (hipMemcpyAsync(m.params, d_params, sizeof(float) * kParams, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    if (launch_fill_u32((uint32_t *)m.m, 0u, 2 * (size_t)kParams, stream) != hipSuccess) return IVM_ERR_HIP;
+    m.step = 0;
+    return IVM_OK;
+}
+
+ivm_status ivm_model_get_params(const ivm_model *model, float *d_params, hipStream_t stream) {
+    if (!model || !d_params) return IVM_ERR_INVALID_ARGUMENT;
+    if (hipMemcpyAsync(d_params, model->m.params, sizeof(float) * kParams, hipMemcpyDeviceToDevice, stream) !=
+        hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_model_forward(ivm_model *model, int32_t n, const float *d_x, float *d_logits, hipStream_t stream) {
+    if (!model || n < 0 || n > model->m.max_batch || (n > 0 && (!d_x || !d_logits))) return IVM_ERR_INVALID_ARGUMENT;
+    if (n == 0) return IVM_OK;
+    if (model_forward(model->m, n, d_x, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (hipMemcpyAsync(d_logits, model->m.logits, sizeof(float) * (size_t)n * kOut, hipMemcpyDeviceToDevice,
+                       stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_model_loss_grad(ivm_model *model, int32_t n, const float *d_x, const float *d_y, float *d_loss,
+                               float *d_grad, hipStream_t stream) {
+    if (!model || n <= 0 || n > model->m.max_batch || !d_x || !d_y || !d_loss || !d_grad)
+        return IVM_ERR_INVALID_ARGUMENT;
+    Model &m = model->m;
+    if (launch_fill_u32((uint32_t *)m.loss, 0u, 1, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (model_backward(m, n, d_x, d_y, d_grad, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (hipMemcpyAsync(d_loss, m.loss, sizeof(float), hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_model_train_step(ivm_model *model, int32_t n, const float *d_x, const float *d_y, float lr,
+                                float *d_loss, hipStream_t stream) {
+    if (!model || n <= 0 || n > model->m.max_batch || !d_x || !d_y || !(lr >= 0.f)) return IVM_ERR_INVALID_ARGUMENT;
+    Model &m = model->m;
+    if (launch_fill_u32((uint32_t *)m.loss, 0u, 1, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (model_backward(m, n, d_x, d_y, m.grad, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (model_adam(m, lr, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (d_loss && hipMemcpyAsync(d_loss, m.loss, sizeof(float), hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_pair_features(const ivm_scene *scene, int32_t n, const int32_t *d_i, const int32_t *d_j, float *d_x,
+                             hipStream_t stream) {
+    if (!scene || n < 0 || (n > 0 && (!d_i || !d_j || !d_x))) return IVM_ERR_INVALID_ARGUMENT;
+    if (launch_pair_features(scene->s.dev, n, d_i, d_j, d_x, stream) != hipSuccess) return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_pair_occluder_labels(ivm_scene *scene, int32_t n, const int32_t *d_i, const int32_t *d_j,
+                                    uint32_t *d_labels, hipStream_t stream) {
+    if (!scene || n < 0 || (n > 0 && (!d_i || !d_j || !d_labels))) return IVM_ERR_INVALID_ARGUMENT;
+    TraverseOpts o = make_opts(nullptr);
+    if (launch_pair_labels(scene->s, o, n, d_i, d_j, d_labels, stream) != hipSuccess) return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_scene_set_model(ivm_scene *scene, const ivm_model *model) {
+    if (!scene) return IVM_ERR_INVALID_ARGUMENT;
+    if (model && scene->s.lay.learned_bytes == 0) return IVM_ERR_MODEL;
+    scene->s.model = model ? const_cast<Model *>(&model->m) : nullptr;
     return IVM_OK;
 }
 

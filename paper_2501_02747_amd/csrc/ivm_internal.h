@@ -66,6 +66,8 @@ struct SceneDev {
     const int *scluster;       // S: quadrant cluster (0..3) of each sample within its facet
     const int *fchull;         // F * 4 * kHullMax: hull sample indices per cluster
     const int *fchull_n;       // F * 4: cluster hull sizes (0 = unavailable or empty)
+    const float *ffeat;        // F * 8: normalised centroid (3), unit normal (3), area (1), pad
+    const float *fnorm;        // 4: scene-box centre (3) and half-size used to normalise features
     int *status;               // device status bits
     const double *extent;      // [0..5] = sample-unit integer box of vertices+samples as doubles; [6] = E
 };
@@ -74,7 +76,7 @@ struct SceneDev {
 struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
-    size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n;
+    size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
     size_t learned_bytes;
     size_t total;
 };
@@ -91,6 +93,21 @@ struct Scene {
     int n_items;               // F * W pair-cull items
     struct Model *model;       // optional occluder-ordering network
 };
+
+// Occluder-ordering network state (device arrays inside the caller's workspace).
+struct Model {
+    int max_batch, precision;
+    float *params, *grad, *m, *v;          // IVM_MLP_PARAMS each
+    float *h0, *h1, *h2, *logits, *d0, *d1, *loss;
+    long long step;
+};
+
+// Offsets of the layers inside the flat parameter array.
+constexpr int kIn = IVM_MLP_FEATURES, kHid = IVM_MLP_HIDDEN, kOut = IVM_MLP_OUTPUTS;
+constexpr int kOffW0 = 0, kOffB0 = kOffW0 + kHid * kIn, kOffW1 = kOffB0 + kHid, kOffB1 = kOffW1 + kHid * kHid;
+constexpr int kOffW2 = kOffB1 + kHid, kOffB2 = kOffW2 + kHid * kHid, kOffW3 = kOffB2 + kHid;
+constexpr int kOffB3 = kOffW3 + kOut * kHid, kParams = kOffB3 + kOut;
+static_assert(kParams == IVM_MLP_PARAMS, "parameter layout");
 
 struct TraverseOpts {
     int order_mode;
@@ -116,6 +133,16 @@ hipError_t launch_candidates_fill(const SceneDev &d, const uint64_t *M, int N, c
                                   const uint64_t *rxv, int K, const int64_t *offsets, int32_t *paths,
                                   hipStream_t s);
 hipError_t launch_triangle_groups(const SceneDev &d, int32_t *group, hipStream_t s);
+hipError_t launch_facet_features(Scene &sc, hipStream_t s);
+hipError_t launch_pair_features(const SceneDev &d, int n, const int32_t *I, const int32_t *J, float *X, hipStream_t s);
+hipError_t launch_pair_labels(Scene &sc, const TraverseOpts &o, int n, const int32_t *I, const int32_t *J,
+                              uint32_t *labels, hipStream_t s);
+hipError_t launch_learned_order(Scene &sc, const Model &m, hipStream_t s);
+hipError_t model_forward(Model &m, int n, const float *X, hipStream_t s);
+hipError_t model_backward(Model &m, int n, const float *X, const float *Y, float *grad, hipStream_t s);
+hipError_t model_adam(Model &m, float lr, hipStream_t s);
+size_t model_workspace_bytes(int max_batch);
+void model_bind(Model &m, void *ws, int max_batch, int precision);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 

@@ -60,6 +60,8 @@ Layout make_layout(int F, int T, int S, bool learned) {
     L.scluster = take(Sn * sizeof(int));
     L.fchull = take(Fn * 4 * kHullMax * sizeof(int));
     L.fchull_n = take(Fn * 4 * sizeof(int));
+    L.ffeat = take(Fn * 8 * sizeof(float));
+    L.fnorm = take(8 * sizeof(float));
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
@@ -594,6 +596,50 @@ __global__ void k_treelets(int T, const float4 *tri, const float *nbox, float *t
     }
 }
 
+// Per-facet inputs of the pair features: centroid of the samples, unit normal and
+// area, normalised by the box of all vertices (centre c0, half-size s of the
+// largest axis).
+__global__ void k_facet_feat(int F, int g, const int *ibox, const int *soff, const float4 *smp, const double *fplane,
+                             const int *ffirst, const float4 *tri_caller, float *ffeat, float *fnorm) {
+    const float inv = ldexpf(1.0f, -g);
+    float c0[3], hs = 0.f;
+    for (int k = 0; k < 3; ++k) {
+        const float lo = (float)ibox[k] * inv, hi = (float)ibox[3 + k] * inv;
+        c0[k] = 0.5f * (lo + hi);
+        hs = fmaxf(hs, 0.5f * (hi - lo));
+    }
+    if (!(hs > 0.f)) hs = 1.f;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f == 0) {
+        fnorm[0] = c0[0]; fnorm[1] = c0[1]; fnorm[2] = c0[2]; fnorm[3] = hs;
+    }
+    if (f >= F) return;
+    float cx = 0.f, cy = 0.f, cz = 0.f;
+    const int s0 = soff[f], s1 = soff[f + 1];
+    for (int s = s0; s < s1; ++s) {
+        cx += smp[s].x; cy += smp[s].y; cz += smp[s].z;
+    }
+    const float ns = s1 > s0 ? (float)(s1 - s0) : 1.f;
+    const double *pl = fplane + 6 * f;
+    const double nl = sqrt(pl[3] * pl[3] + pl[4] * pl[4] + pl[5] * pl[5]);
+    float area = 0.f;
+    const int t0 = ffirst[2 * f], nt = ffirst[2 * f + 1];
+    for (int t = t0; t < t0 + nt; ++t) {
+        const float4 B = tri_caller[3 * t + 1], C = tri_caller[3 * t + 2];
+        const float x = B.y * C.z - B.z * C.y, y = B.z * C.x - B.x * C.z, z = B.x * C.y - B.y * C.x;
+        area += 0.5f * sqrtf(x * x + y * y + z * z);
+    }
+    float *o = ffeat + 8 * f;
+    o[0] = (cx / ns - c0[0]) / hs;
+    o[1] = (cy / ns - c0[1]) / hs;
+    o[2] = (cz / ns - c0[2]) / hs;
+    o[3] = nl > 0.0 ? (float)(pl[3] / nl) : 0.f;
+    o[4] = nl > 0.0 ? (float)(pl[4] / nl) : 0.f;
+    o[5] = nl > 0.0 ? (float)(pl[5] / nl) : 0.f;
+    o[6] = area / (hs * hs);
+    o[7] = 0.f;
+}
+
 __global__ void k_groups(int T, const int *tri_group, int32_t *out) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < T) out[t] = tri_group[t];
@@ -638,6 +684,19 @@ hipError_t launch_build(Scene &sc, hipStream_t s) {
         hipLaunchKernelGGL(k_treelets, dim3(1), dim3(64), 0, s, 0, (const float4 *)nullptr, (const float *)nullptr,
                            (float *)(ws + L.tl_box), (int *)(ws + L.tl_root));
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_facet_features(sc, s);
+}
+
+hipError_t launch_facet_features(Scene &sc, hipStream_t s) {
+    char *ws = (char *)sc.ws;
+    const Layout &L = sc.lay;
+    const int F = sc.desc.n_facets;
+    hipLaunchKernelGGL(k_facet_feat, dim3(nblk(F > 0 ? F : 1, 128)), dim3(128), 0, s, F, sc.desc.grid_vertex_log2,
+                       (const int *)(ws + L.ibox), (const int *)(ws + L.soff), (const float4 *)(ws + L.smp),
+                       (const double *)(ws + L.fplane), (const int *)(ws + L.ffirst),
+                       (const float4 *)(ws + L.tri_caller), (float *)(ws + L.ffeat), (float *)(ws + L.fnorm));
     return hipGetLastError();
 }
 

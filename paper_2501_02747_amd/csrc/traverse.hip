@@ -773,6 +773,90 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
     if (st && lane == 0 && nsub) atomicAdd((unsigned long long *)&st->reserved[0], nsub);
 }
 
+// Hit records for the occluder-ordering network: for each listed pair, the set
+// of treelets holding a triangle that meets at least one admissible segment.
+// Treelets already in the set are not searched again, so each segment runs one
+// any-hit search per treelet still open.
+__global__ __launch_bounds__(kBlock) void k_labels(SceneDev sc, int n, const int32_t *I, const int32_t *J,
+                                                   uint32_t *labels, TraverseOpts o) {
+    __shared__ float4 sP[kWavesPerBlock][kWave];
+    __shared__ float4 sQ[kWavesPerBlock][kWave];
+    __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
+    __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
+    __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
+    __shared__ uint8_t sRem[kWavesPerBlock][kTreelets];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    int *stk = &sStack[wv][lane];
+    const bool f64 = o.fp64_only != 0;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    Cnt c;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int k = wave; k < n; k += nwaves) {
+        int i = min(I[k], J[k]), j = max(I[k], J[k]);
+        if (i < 0 || j >= sc.F || i == j) {
+            if (lane == 0) labels[k] = 0u;
+            continue;
+        }
+        const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
+        const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
+        const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
+        const float4 p = lane < ni ? sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
+        const float4 q = lane < nj ? sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
+        const bool okp = lane < ni && orient(plj, p.x, p.y, p.z) > 0.0;
+        const bool okq = lane < nj && orient(pli, q.x, q.y, q.z) > 0.0;
+        const unsigned long long mp = __ballot(okp), mq = __ballot(okq);
+        const int np = __popcll(mp), nq = __popcll(mq);
+        if (okp) sP[wv][__popcll(mp & lt)] = p;
+        if (okq) sQ[wv][__popcll(mq & lt)] = q;
+        float lo[3], hi[3];
+        {
+            const float big = INFINITY;
+            float l0 = big, l1 = big, l2 = big, h0 = -big, h1 = -big, h2 = -big;
+            if (okp) { l0 = p.x; l1 = p.y; l2 = p.z; h0 = p.x; h1 = p.y; h2 = p.z; }
+            if (okq) {
+                l0 = fminf(l0, q.x); l1 = fminf(l1, q.y); l2 = fminf(l2, q.z);
+                h0 = fmaxf(h0, q.x); h1 = fmaxf(h1, q.y); h2 = fmaxf(h2, q.z);
+            }
+            lo[0] = wave_min(l0); lo[1] = wave_min(l1); lo[2] = wave_min(l2);
+            hi[0] = wave_max(h0); hi[1] = wave_max(h1); hi[2] = wave_max(h2);
+        }
+        const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, IVM_ORDER_INDEX, 0ull), sKey[wv], sOrder[wv]);
+        unsigned mask = 0u;
+        const int nseg = np * nq;
+        for (int base = 0; base < nseg; base += kWave) {
+            const bool open = lane < n_order && !((mask >> sOrder[wv][lane]) & 1u);
+            const unsigned long long om = __ballot(open);
+            if (open) sRem[wv][__popcll(om & lt)] = sOrder[wv][lane];
+            wave_sync();
+            const int nrem = __popcll(om);
+            if (nrem == 0) break;
+            const int sidx = base + lane;
+            const bool act = sidx < nseg;
+            Seg sg = make_seg(0, 0, 0, 0, 0, 0);
+            if (act) {
+                const int a = sidx / nq, b = sidx - (sidx / nq) * nq;
+                const float4 P = sP[wv][a], Q = sQ[wv][b];
+                sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+            }
+            for (int r = 0; r < nrem; ++r) {
+                bool hit = false;
+                if (act) hit = any_hit(sc, sg, i, j, &sRem[wv][r], 1, stk, o.stack_depth, o.eps6, f64, c) >= 0;
+                if (__ballot(hit)) mask |= 1u << sRem[wv][r];
+            }
+            wave_sync();
+        }
+        if (lane == 0) labels[k] = mask;
+    }
+}
+
+hipError_t launch_pair_labels(Scene &scn, const TraverseOpts &o, int n, const int32_t *I, const int32_t *J,
+                              uint32_t *labels, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_labels, dim3(o.grid_blocks), dim3(kBlock), 0, s, scn.dev, n, I, J, labels, o);
+    return hipGetLastError();
+}
+
 __global__ void k_pair_stats(ivm_stats *st, const uint32_t *prefix, int n_items, int F) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && st) {
         atomicAdd((unsigned long long *)&st->pairs_candidate, (unsigned long long)prefix[n_items]);
@@ -832,8 +916,11 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
     }
     if ((e = exclusive_scan_u32(prefix, n_items + 1, (uint32_t *)(ws + L.scan_tmp), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pair_stats, dim3(1), dim3(64), 0, s, stats, (const uint32_t *)prefix, n_items, sc.F);
-    const uint64_t *learned = (o.order_mode == IVM_ORDER_LEARNED && L.learned_bytes) ? (const uint64_t *)(ws + L.learned)
-                                                                                      : nullptr;
+    const uint64_t *learned = nullptr;
+    if (o.order_mode == IVM_ORDER_LEARNED && L.learned_bytes && scn.model) {
+        if ((e = launch_learned_order(scn, *scn.model, s)) != hipSuccess) return e;
+        learned = (const uint64_t *)(ws + L.learned);
+    }
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pairs, dim3(o.grid_blocks), dim3(kBlock), 0, s, sc, (const uint64_t *)cand,
                        (const uint32_t *)prefix, n_items, queue, M, o, stats, learned);

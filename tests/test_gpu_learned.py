@@ -1,0 +1,184 @@
+"""GPU checks of the learned occluder ordering: features, hit-record labels,
+network forward and gradients (FP32 and BF16-MFMA modes) against the FP64
+oracle, Adam, training progress, and that the learned order never changes a
+result bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ivm():
+    import torch
+    import paper_2501_02747_amd as ivm
+    assert torch.cuda.is_available()
+    ivm.load_library()
+    return ivm
+
+
+def _pairs(F, n, seed):
+    rng = np.random.default_rng(seed)
+    I = rng.integers(0, F, n)
+    J = rng.integers(0, F, n)
+    keep = I != J
+    return np.minimum(I, J)[keep].astype(np.int32), np.maximum(I, J)[keep].astype(np.int32)
+
+
+def test_features_match_oracle(oracle_mod, ivm):
+    import torch
+    for s in (sg.gen_c1(3), sg.gen_c2(4, n_snap=1, nx=4, ny=4)):
+        _log(f"[features] F={s.n_facets}")
+        g = ivm.GpuScene.from_scene(s).check()
+        I, J = _pairs(s.n_facets, 500, 1)
+        x = ivm.ivm_pair_features(g, torch.as_tensor(I).cuda(), torch.as_tensor(J).cuda()).cpu().numpy()
+        xo = oracle_mod.pair_features(s, I, J)
+        assert np.abs(x - xo).max() < 2e-5
+
+
+def test_labels_match_oracle(oracle_mod, ivm):
+    """Hit records are integer: bit-exact against the oracle's all-hit search."""
+    import torch
+    for s, n in ((sg.gen_c1(5), 861), (sg.gen_c2(6, n_snap=1, nx=4, ny=3), 300)):
+        _log(f"[labels] F={s.n_facets}")
+        g = ivm.GpuScene.from_scene(s).check()
+        if n == 861:
+            I, J = np.triu_indices(s.n_facets, 1)
+            I, J = I.astype(np.int32), J.astype(np.int32)
+        else:
+            I, J = _pairs(s.n_facets, n, 2)
+        lab = ivm.ivm_pair_occluder_labels(g, torch.as_tensor(I).cuda(), torch.as_tensor(J).cuda())
+        lab = lab.cpu().numpy().view(np.uint32)
+        _, groups = oracle_mod.morton_treelets(s, 32)
+        expect = oracle_mod.Oracle(s).occluder_groups(I, J, groups)
+        assert (lab == expect).all(), np.argwhere(lab != expect)[:5]
+        assert (lab != 0).sum() > 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_forward_and_gradients_match_oracle(oracle_mod, ivm, precision):
+    """FP32 mode against the FP64 reference; BF16 (MFMA) mode against the FP64
+    reference with every product's operands rounded to BF16."""
+    import torch
+    _log(f"[mlp] {precision}")
+    bf16 = precision == "bf16"
+    rng = np.random.default_rng(3)
+    p = oracle_mod.mlp_init(7)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.normal(scale=0.1, size=p[k].shape)
+    flat = oracle_mod.mlp_flatten(p).astype(np.float32)
+    pf = oracle_mod.mlp_unflatten(flat.astype(np.float64))       # the FP32-stored parameters
+    B = 200
+    X = rng.normal(size=(B, 24)).astype(np.float32)
+    Y = (rng.random((B, 32)) < 0.3).astype(np.float32)
+    m = ivm.Model(max_batch=256, precision=ivm.IVM_MODEL_BF16 if bf16 else ivm.IVM_MODEL_FP32)
+    m.set_params(flat)
+    dX, dY = torch.as_tensor(X).cuda(), torch.as_tensor(Y).cuda()
+    z = m.forward(dX).cpu().numpy()
+    zo, _ = oracle_mod.mlp_forward(pf, X.astype(np.float64), bf16=bf16)
+    tol = 2e-3 if bf16 else 1e-5
+    assert np.abs(z - zo).max() <= tol * max(1.0, np.abs(zo).max())
+    loss, grad = m.loss_grad(dX, dY)
+    lo, go = oracle_mod.mlp_loss_grad(pf, X.astype(np.float64), Y.astype(np.float64), bf16=bf16)
+    assert abs(float(loss.item()) - lo) <= (1e-3 if bf16 else 1e-5) * max(1.0, lo)
+    g_gpu = grad.cpu().numpy().astype(np.float64)
+    g_ref = oracle_mod.mlp_flatten(go)
+    rel = np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)
+    assert rel <= (1e-2 if bf16 else 1e-4), rel
+    # per layer as well
+    off = 0
+    for l in range(4):
+        for key in (f"W{l}", f"b{l}"):
+            n = go[key].size
+            seg_g, seg_r = g_gpu[off:off + n], g_ref[off:off + n]
+            assert np.linalg.norm(seg_g - seg_r) <= (2e-2 if bf16 else 2e-4) * np.linalg.norm(seg_r) + 1e-9, key
+            off += n
+
+
+def test_adam_step_matches_oracle(oracle_mod, ivm):
+    import torch
+    rng = np.random.default_rng(4)
+    p = oracle_mod.mlp_init(1)
+    flat = oracle_mod.mlp_flatten(p).astype(np.float32)
+    X = rng.normal(size=(64, 24)).astype(np.float32)
+    Y = (rng.random((64, 32)) < 0.3).astype(np.float32)
+    m = ivm.Model(max_batch=64, precision=ivm.IVM_MODEL_FP32)
+    m.set_params(flat)
+    dX, dY = torch.as_tensor(X).cuda(), torch.as_tensor(Y).cuda()
+    pf = oracle_mod.mlp_unflatten(flat.astype(np.float64))
+    st = {}
+    for _ in range(3):
+        _, go = oracle_mod.mlp_loss_grad(pf, X.astype(np.float64), Y.astype(np.float64))
+        oracle_mod.adam_step(pf, go, st, lr=1e-3)
+        m.train_step(dX, dY, 1e-3)
+    got = m.get_params().cpu().numpy().astype(np.float64)
+    ref = oracle_mod.mlp_flatten(pf)
+    assert np.abs(got - ref).max() < 1e-5
+
+
+def test_training_reduces_loss(ivm):
+    """Records from the GPU's own hit-record pass; BF16 training lowers the loss."""
+    from paper_2501_02747_amd import train as tr
+    s = sg.gen_c2(201, n_snap=1, nx=5, ny=5)
+    X, Y = tr.collect_records(s, 20000, 0)
+    assert len(X) > 1000
+    m = ivm.Model(max_batch=1024, precision=ivm.IVM_MODEL_BF16)
+    m.set_params(tr.he_uniform_init(0))
+    hist = tr.train(m, X, Y, epochs=4, batch=256, lr=2e-3)
+    _log(f"[train] losses {hist}")
+    assert hist[-1] < hist[0]
+
+
+@pytest.mark.parametrize("weights", ["trained", "random", "nan"])
+def test_learned_order_keeps_every_bit(oracle_mod, ivm, weights):
+    """IVM_ORDER_LEARNED with any weights (trained, random, NaN) gives the plain bits."""
+    import torch
+    from paper_2501_02747_amd import train as tr
+    s = sg.gen_c2(2, n_snap=4, nx=5, ny=4)
+    g = ivm.GpuScene.from_scene(s, learned=True).check()
+    m = ivm.Model(max_batch=1024, precision=ivm.IVM_MODEL_BF16)
+    params = tr.he_uniform_init(5)
+    if weights == "trained":
+        X, Y = tr.collect_records(s, 20000, 1)
+        m.set_params(params)
+        tr.train(m, X, Y, epochs=2, batch=256, lr=2e-3)
+    elif weights == "nan":
+        params = np.full_like(params, np.nan)
+        m.set_params(params)
+    else:
+        m.set_params(params)
+    ivm.ivm_scene_set_model(g, m)
+    st_l, st_p = ivm.new_stats(), ivm.new_stats()
+    Ml = ivm.ivm_intervisibility_matrix(g, ivm.make_opts(order_mode=ivm.IVM_ORDER_LEARNED), stats=st_l).clone()
+    Mp = ivm.ivm_intervisibility_matrix(g, ivm.make_opts(order_mode=ivm.IVM_ORDER_PLAIN), stats=st_p).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(Ml, Mp)
+    Mo, _ = oracle_mod.Oracle(s).matrix()
+    assert (ivm.unpack_bits(Ml, s.n_facets) == Mo).all()
+    dl, dp = ivm.stats_dict(st_l), ivm.stats_dict(st_p)
+    assert dl["flags"] == 0
+    _log(f"[learned {weights}] visits {dl['node_visits']} vs plain {dp['node_visits']}, "
+         f"tests {dl['tri_tests']} vs {dp['tri_tests']}")
+
+
+def test_learned_without_model_falls_back(ivm):
+    import torch
+    s = sg.gen_c1(2)
+    g = ivm.GpuScene.from_scene(s).check()
+    st = ivm.new_stats()
+    M = ivm.ivm_intervisibility_matrix(g, ivm.make_opts(order_mode=ivm.IVM_ORDER_LEARNED), stats=st,
+                                       allow_model_fallback=True)
+    Mp = ivm.ivm_intervisibility_matrix(g)
+    torch.cuda.synchronize()
+    assert torch.equal(M, Mp)
+    assert ivm.stats_dict(st)["flags"] & 1
