@@ -155,7 +155,17 @@ def main():
     F, N = scene.n_facets, scene.n_snapshots
     order = {"plain": ivm.IVM_ORDER_PLAIN, "index": ivm.IVM_ORDER_INDEX, "reversed": ivm.IVM_ORDER_REVERSED,
              "learned": ivm.IVM_ORDER_LEARNED}[args.order]
-    g = ivm.GpuScene.from_scene(scene, learned=(args.order == "learned")).check()
+    weights = os.path.join(ROOT, "paper_2501_02747_amd", "models", "occluder_mlp.npy")
+    have_model = os.path.exists(weights)
+    g = ivm.GpuScene.from_scene(scene, learned=have_model).check()
+    model = None
+    if have_model:
+        model = ivm.Model(max_batch=1024, precision=ivm.IVM_MODEL_BF16)
+        model.set_params(np.load(weights, allow_pickle=False))
+        ivm.ivm_scene_set_model(g, model)
+    elif args.order == "learned":
+        print("no trained occluder-ordering weights found", file=sys.stderr)
+        sys.exit(1)
     tx = torch.as_tensor(scene.tx).cuda()
     rx = torch.as_tensor(scene.rx).cuda()
     M = torch.empty((F, g.W), dtype=torch.int64, device="cuda")
@@ -248,6 +258,35 @@ def main():
         "roofline_points": {"bound": "alu", "achieved": ach_p, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
                             "frac": ach_p / VALU_PEAK_TOPS, "kernel": "k_points"},
     }
+    # the other traversal order on the same matrix, timed the same way, bits compared
+    if have_model:
+        other = "plain" if args.order == "learned" else "learned"
+        oo = ivm.make_opts(order_mode=ivm.IVM_ORDER_LEARNED if other == "learned" else ivm.IVM_ORDER_PLAIN,
+                           fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu, stack_depth=args.stack,
+                           timing=t_pairs)
+        M2 = torch.empty_like(M)
+        st_o = ivm.new_stats()
+        times = []
+        for k in range(args.warmup + args.steps):
+            st_o.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ivm.ivm_intervisibility_matrix(g, oo, out=M2, stats=st_o)
+            e1.record()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(e0.elapsed_time(e1))
+        so = ivm.stats_dict(st_o)
+        out["compare_order"] = {
+            "order": other, "matrix_ms": statistics.median(times),
+            "queries_per_s": n_pairs / (statistics.median(times) / 1e3),
+            "k_pairs_ms": t_pairs.elapsed_ms(), "identical_bits": bool(torch.equal(M, M2)),
+            "node_visits": so["node_visits"], "tri_tests": so["tri_tests"], "segments": so["segments"],
+            "certified": so["certified"],
+            "note": "learned = network inference (in the matrix call) + learned treelet order",
+        }
+        progress(f"{other} order: {statistics.median(times):.2f} ms, identical bits "
+                 f"{out['compare_order']['identical_bits']}")
     if not args.no_verify:
         progress("verifying against the oracle")
         counts_now = counts
