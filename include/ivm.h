@@ -269,6 +269,38 @@ ivm_status ivm_pair_occluder_labels(ivm_scene *scene, int32_t n, const int32_t *
  * must have been built with IVM_SCENE_LEARNED. */
 ivm_status ivm_scene_set_model(ivm_scene *scene, const ivm_model *model);
 
+/* ---- batched scenes ----------------------------------------------------------
+ * Many independent scenes in one run: per-scene orientation culls, then one
+ * persistent any-hit launch over the candidate pairs of all scenes, one
+ * persistent launch over all Tx/Rx items, then line of sight and candidate
+ * counts (orders 0..2) per scene.  The first ivm_batch_run captures the launch
+ * sequence in a hipGraph; later runs replay it.  Results per scene are those of
+ * ivm_intervisibility_matrix, ivm_txrx_visibility_table and
+ * ivm_image_tree_candidates (count mode). */
+typedef struct ivm_batch ivm_batch; /* opaque host handle */
+
+typedef struct ivm_batch_item {
+    ivm_scene *scene;          /* built scene, kept alive by the caller */
+    uint64_t *d_M;             /* uint64[F][W] */
+    int32_t n_snap;
+    const float *d_tx;         /* float[n_snap][3] */
+    const float *d_rx;         /* float[n_snap][3] */
+    uint64_t *d_tx_vis;        /* uint64[n_snap][W] */
+    uint64_t *d_rx_vis;        /* uint64[n_snap][W] */
+    uint8_t *d_los;            /* uint8[n_snap] */
+    int64_t *d_counts;         /* int64[n_snap][3], or NULL */
+} ivm_batch_item;
+
+/* Device bytes for the batch's job tables and queue. */
+ivm_status ivm_batch_workspace_size(int32_t n_items, size_t *bytes);
+/* Copies the job tables to d_workspace (synchronous).  Every buffer named by the
+ * items, d_stats (may be NULL; counters accumulate over runs) and the workspace
+ * must outlive the batch.  opts->timing_events is ignored. */
+ivm_status ivm_batch_create(int32_t n_items, const ivm_batch_item *items, const ivm_matrix_opts *opts,
+                            ivm_stats *d_stats, void *d_workspace, size_t workspace_bytes, ivm_batch **out);
+ivm_status ivm_batch_run(ivm_batch *batch, hipStream_t stream);
+ivm_status ivm_batch_destroy(ivm_batch *batch);
+
 /* Treelet (Morton group) index of every triangle in the caller's triangle order:
  * d_group is int32[T].  Treelet k holds sorted ranks [ceil(k T / 32), ceil((k+1) T / 32)). */
 ivm_status ivm_triangle_groups(const ivm_scene *scene, int32_t *d_group, hipStream_t stream);

@@ -40,6 +40,7 @@ EXPORTED = [
     "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
+    "ivm_batch_workspace_size", "ivm_batch_create", "ivm_batch_run", "ivm_batch_destroy",
 ]
 
 IVM_MLP_FEATURES, IVM_MLP_HIDDEN, IVM_MLP_OUTPUTS, IVM_MLP_PARAMS = 24, 128, 32, 40352
@@ -140,6 +141,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_pair_occluder_labels.argtypes = [P, i32, P, P, P, P]
     lib.ivm_scene_set_model.restype = i32
     lib.ivm_scene_set_model.argtypes = [P, P]
+    lib.ivm_batch_workspace_size.restype = i32
+    lib.ivm_batch_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
+    lib.ivm_batch_create.restype = i32
+    lib.ivm_batch_create.argtypes = [i32, P, ctypes.POINTER(ivm_matrix_opts), P, P, sz, ctypes.POINTER(P)]
+    lib.ivm_batch_run.restype = i32
+    lib.ivm_batch_run.argtypes = [P, P]
+    lib.ivm_batch_destroy.restype = i32
+    lib.ivm_batch_destroy.argtypes = [P]
     _lib = lib
     return lib
 
@@ -276,6 +285,8 @@ class GpuScene:
         self.handle = h
         if old and old.value:
             lib.ivm_destroy_scene(old)
+        if getattr(self, "_model", None) is not None:   # a new handle starts without a model
+            _check(lib.ivm_scene_set_model(self.handle, self._model.handle), "ivm_scene_set_model")
         return self
 
     @classmethod
@@ -457,6 +468,65 @@ def ivm_scene_set_model(scene: GpuScene, model: Optional[Model]):
     _check(load_library().ivm_scene_set_model(scene.handle, model.handle if model is not None else None),
            "ivm_scene_set_model")
     scene._model = model
+
+
+# ---- batched scenes ---------------------------------------------------------------
+
+class ivm_batch_item(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("d_M", ctypes.c_void_p), ("n_snap", ctypes.c_int32),
+                ("d_tx", ctypes.c_void_p), ("d_rx", ctypes.c_void_p), ("d_tx_vis", ctypes.c_void_p),
+                ("d_rx_vis", ctypes.c_void_p), ("d_los", ctypes.c_void_p), ("d_counts", ctypes.c_void_p)]
+
+
+class Batch:
+    """Many scenes run together (ivm_batch_*): outputs are allocated here, one per
+    scene; run() replays the captured graph on the given (non-default) stream."""
+
+    def __init__(self, scenes, txs, rxs, opts: Optional[ivm_matrix_opts] = None, stats=None):
+        import torch
+        lib = load_library()
+        self.scenes = list(scenes)
+        self.tx = [t.contiguous() for t in txs]
+        self.rx = [r.contiguous() for r in rxs]
+        self.M, self.tv, self.rv, self.los, self.counts = [], [], [], [], []
+        n = len(self.scenes)
+        arr = (ivm_batch_item * n)()
+        for k, g in enumerate(self.scenes):
+            N = int(self.tx[k].shape[0])
+            self.M.append(torch.zeros((g.F, g.W), dtype=torch.int64, device=g.device))
+            self.tv.append(torch.zeros((N, g.W), dtype=torch.int64, device=g.device))
+            self.rv.append(torch.zeros((N, g.W), dtype=torch.int64, device=g.device))
+            self.los.append(torch.zeros((N,), dtype=torch.uint8, device=g.device))
+            self.counts.append(torch.zeros((N, 3), dtype=torch.int64, device=g.device))
+            it = arr[k]
+            it.scene, it.d_M, it.n_snap = g.handle.value, _ptr(self.M[k]), N
+            it.d_tx, it.d_rx = _ptr(self.tx[k]), _ptr(self.rx[k])
+            it.d_tx_vis, it.d_rx_vis, it.d_los = _ptr(self.tv[k]), _ptr(self.rv[k]), _ptr(self.los[k])
+            it.d_counts = _ptr(self.counts[k])
+        self._items = arr
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.ivm_batch_workspace_size(n, ctypes.byref(nbytes)), "ivm_batch_workspace_size")
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.scenes[0].device)
+        aligned = (int(self.workspace.data_ptr()) + 255) & ~255
+        self.stats = stats
+        self.handle = ctypes.c_void_p()
+        _check(lib.ivm_batch_create(n, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(opts) if opts else None,
+                                    _ptr(stats), aligned, int(nbytes.value), ctypes.byref(self.handle)),
+               "ivm_batch_create")
+
+    def run(self, stream):
+        _check(load_library().ivm_batch_run(self.handle, int(stream.cuda_stream)), "ivm_batch_run")
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load_library().ivm_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- host-side helpers (no visibility arithmetic) --------------------------------

@@ -9,10 +9,6 @@
 
 using namespace ivm;
 
-struct ivm_scene {
-    Scene s;
-};
-
 struct ivm_model {
     Model m;
     void *ws;

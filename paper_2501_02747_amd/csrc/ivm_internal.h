@@ -118,6 +118,25 @@ struct TraverseOpts {
     hipEvent_t *events;        // optional: recorded around the traversal kernel
 };
 
+// One scene's share of a (possibly multi-scene) persistent pair launch.
+struct PairJob {
+    SceneDev sc;
+    const uint64_t *cand;     // F * W candidate words
+    const uint32_t *prefix;   // exclusive prefix of candidate counts (n_items + 1)
+    int n_items;
+    uint64_t *M;
+    const uint64_t *learned;  // per-candidate learned order, or nullptr
+};
+
+// One scene's share of a (possibly multi-scene) Tx/Rx point launch.
+struct PointJob {
+    SceneDev sc;
+    int N;
+    const float *tx, *rx;
+    uint64_t *txv, *rxv;
+    long long item_base;      // first global item of this job
+};
+
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_build(Scene &sc, hipStream_t s);
 hipError_t launch_matrix(Scene &sc, const TraverseOpts &o, uint64_t *M, ivm_stats *stats,
@@ -143,9 +162,28 @@ hipError_t model_backward(Model &m, int n, const float *X, const float *Y, float
 hipError_t model_adam(Model &m, float lr, hipStream_t s);
 size_t model_workspace_bytes(int max_batch);
 void model_bind(Model &m, void *ws, int max_batch, int precision);
+hipError_t launch_cull_scan(Scene &sc, uint64_t *M, ivm_stats *stats, hipStream_t s);
+hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue,
+                            const TraverseOpts &o, ivm_stats *stats, hipStream_t s);
+hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, hipStream_t s);
+hipError_t launch_points_prep(Scene &sc, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
+                              hipStream_t s);
+hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_items, const TraverseOpts &o,
+                             ivm_stats *stats, hipStream_t s);
+hipError_t launch_los(Scene &sc, const TraverseOpts &o, int N, const float *tx, const float *rx, uint8_t *los,
+                      hipStream_t s);
+PairJob make_pair_job(Scene &sc, uint64_t *M, bool learned);
+PointJob make_point_job(Scene &sc, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
+                        long long item_base);
+long long point_items(const Scene &sc, int N);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 
 int device_cu_count();
 
 }  // namespace ivm
+
+// The opaque handle of the C interface wraps the scene.
+struct ivm_scene {
+    ivm::Scene s;
+};

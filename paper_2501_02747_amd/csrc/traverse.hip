@@ -551,9 +551,11 @@ struct Rects {
     int pa[16], pn[16], qb[16], qn[16], pre[17];
 };
 
-__global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *cand, const uint32_t *prefix,
-                                                  int n_items, uint32_t *queue, uint64_t *M, TraverseOpts o,
-                                                  ivm_stats *st, const uint64_t *learned) {
+// MULTI: the queue index runs over the concatenated candidates of n_jobs scenes
+// (base[] = exclusive prefix of their candidate totals); otherwise over `one`.
+template <bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *many, const uint32_t *base, int n_jobs,
+                                                  uint32_t *queue, TraverseOpts o, ivm_stats *st) {
     __shared__ float4 sP[kWavesPerBlock][kWave];
     __shared__ float4 sQ[kWavesPerBlock][kWave];
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
@@ -564,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
     __shared__ unsigned long long sBits[kWavesPerBlock][16];
     __shared__ Rects sR[kWavesPerBlock];
     const int wv = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t total = prefix[n_items];
+    const uint32_t total = MULTI ? base[n_jobs] : one.prefix[one.n_items];
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
     Rects &R = sR[wv];
@@ -577,8 +579,22 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
         if (lane == 0) g = atomicAdd(queue, 1u);
         g = __shfl(g, 0);
         if (g >= total) break;
+        int js = 0;
+        uint32_t gl = g;
+        if (MULTI) {
+            int lo = 0, hi = n_jobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (base[mid] <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            js = lo;
+            gl = g - base[js];
+        }
+        const PairJob &J = MULTI ? many[js] : one;
+        const SceneDev &sc = J.sc;
         int i, j;
-        decode_pair(sc, cand, prefix, n_items, g, i, j);
+        decode_pair(sc, J.cand, J.prefix, J.n_items, gl, i, j);
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
         const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
         const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
@@ -614,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
             hi[0] = wave_max(h0); hi[1] = wave_max(h1); hi[2] = wave_max(h2);
         }
         unsigned long long lcode = 0;
-        if (o.order_mode == IVM_ORDER_LEARNED && learned) lcode = learned[g];
+        if (o.order_mode == IVM_ORDER_LEARNED && J.learned) lcode = J.learned[gl];
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
         // phase 0: the whole product space, until the first traversal batch
         if (lane == 0) {
@@ -762,8 +778,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(SceneDev sc, const uint64_t *c
             if (!more && nmiss == 0) done = true;
         }
         if (vis && lane == 0) {
-            atomicOr((unsigned long long *)&M[(size_t)i * sc.W + (j >> 6)], 1ull << (j & 63));
-            atomicOr((unsigned long long *)&M[(size_t)j * sc.W + (i >> 6)], 1ull << (i & 63));
+            atomicOr((unsigned long long *)&J.M[(size_t)i * sc.W + (j >> 6)], 1ull << (j & 63));
+            atomicOr((unsigned long long *)&J.M[(size_t)j * sc.W + (i >> 6)], 1ull << (i & 63));
             ++nvis;
         }
         wave_sync();
@@ -896,34 +912,79 @@ int device_cu_count() {
     return cus;
 }
 
-hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_stats *stats,
-                         const uint8_t * /*unused*/, hipStream_t s) {
+PairJob make_pair_job(Scene &scn, uint64_t *M, bool learned) {
+    char *ws = (char *)scn.ws;
+    const Layout &L = scn.lay;
+    PairJob j;
+    j.sc = scn.dev;
+    j.cand = (const uint64_t *)(ws + L.cand);
+    j.prefix = (const uint32_t *)(ws + L.prefix);
+    j.n_items = scn.n_items;
+    j.M = M;
+    j.learned = learned && L.learned_bytes ? (const uint64_t *)(ws + L.learned) : nullptr;
+    return j;
+}
+
+// Zero M, cull every unordered pair by orientation, scan the candidate counts
+// and reset the scene's queue counter.
+hipError_t launch_cull_scan(Scene &scn, uint64_t *M, ivm_stats *stats, hipStream_t s) {
     const SceneDev &sc = scn.dev;
     char *ws = (char *)scn.ws;
     const Layout &L = scn.lay;
     uint64_t *cand = (uint64_t *)(ws + L.cand);
     uint32_t *prefix = (uint32_t *)(ws + L.prefix);
-    uint32_t *queue = (uint32_t *)(ws + L.queue);
     const int n_items = scn.n_items;
     hipError_t e;
     if ((e = launch_fill_u64(M, 0ull, (size_t)sc.F * sc.W, s)) != hipSuccess) return e;
-    if (sc.F < 2) return hipSuccess;
-    if ((e = launch_fill_u32(queue, 0u, 64, s)) != hipSuccess) return e;
-    {
-        const int waves = n_items;
-        const unsigned blocks = (unsigned)((waves + 3) / 4);
-        hipLaunchKernelGGL(k_cull, dim3(blocks > 65535u ? 65535u : blocks), dim3(256), 0, s, sc, cand, prefix, n_items);
-    }
+    if ((e = launch_fill_u32((uint32_t *)(ws + L.queue), 0u, 64, s)) != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((n_items + 3) / 4);
+    hipLaunchKernelGGL(k_cull, dim3(blocks > 65535u ? 65535u : (blocks ? blocks : 1u)), dim3(256), 0, s, sc, cand,
+                       prefix, n_items);
     if ((e = exclusive_scan_u32(prefix, n_items + 1, (uint32_t *)(ws + L.scan_tmp), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pair_stats, dim3(1), dim3(64), 0, s, stats, (const uint32_t *)prefix, n_items, sc.F);
-    const uint64_t *learned = nullptr;
+    return hipGetLastError();
+}
+
+__global__ void k_job_base(const PairJob *jobs, int n, uint32_t *base) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int k = 0; k < n; ++k) {
+        base[k] = run;
+        run += jobs[k].sc.F >= 2 ? jobs[k].prefix[jobs[k].n_items] : 0u;
+    }
+    base[n] = run;
+}
+
+hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, hipStream_t s) {
+    hipLaunchKernelGGL(k_job_base, dim3(1), dim3(64), 0, s, d_jobs, n_jobs, d_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue,
+                            const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
+    PairJob none{};
+    hipLaunchKernelGGL(k_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base, n_jobs, d_queue, o,
+                       stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_stats *stats,
+                         const uint8_t * /*unused*/, hipStream_t s) {
+    const SceneDev &sc = scn.dev;
+    char *ws = (char *)scn.ws;
+    const Layout &L = scn.lay;
+    hipError_t e;
+    if (sc.F < 2) return launch_fill_u64(M, 0ull, (size_t)sc.F * sc.W, s);
+    if ((e = launch_cull_scan(scn, M, stats, s)) != hipSuccess) return e;
+    bool learned = false;
     if (o.order_mode == IVM_ORDER_LEARNED && L.learned_bytes && scn.model) {
         if ((e = launch_learned_order(scn, *scn.model, s)) != hipSuccess) return e;
-        learned = (const uint64_t *)(ws + L.learned);
+        learned = true;
     }
+    const PairJob job = make_pair_job(scn, M, learned);
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pairs, dim3(o.grid_blocks), dim3(kBlock), 0, s, sc, (const uint64_t *)cand,
-                       (const uint32_t *)prefix, n_items, queue, M, o, stats, learned);
+    hipLaunchKernelGGL(k_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PairJob *)nullptr,
+                       (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue), o, stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (o.events && (e = hipEventRecord(o.events[1], s)) != hipSuccess) return e;
     return hipSuccess;
@@ -936,15 +997,29 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
 __constant__ uint8_t kIdentOrder[kTreelets] = {0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13, 14, 15,
                                                16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
 
-// Items are (snapshot, side, chunk of 64 consecutive samples); each wave walks a
-// contiguous range of items so consecutive items share the Tx or Rx point.  A
-// lane first tests its sample's segment against the wave's recent blockers;
-// the misses are queued in LDS and traversed in full 64-lane batches.  The
-// queue is drained whenever the point changes.  Samples of facets already
-// known visible are skipped (a set bit is never cleared, so a stale read only
-// costs work).
-__global__ __launch_bounds__(kBlock) void k_points(SceneDev sc, int N, const float *tx, const float *rx, uint64_t *txv,
-                                                   uint64_t *rxv, TraverseOpts o, ivm_stats *st) {
+// Items are (job, snapshot, side, chunk of 64 consecutive samples); each wave
+// walks a contiguous range of global items so consecutive items share the Tx
+// or Rx point.  A lane first tests its sample's segment against the wave's
+// recent blockers; the misses are queued in LDS and traversed in full 64-lane
+// batches.  The queue is drained whenever the point (or the scene) changes.
+// Samples of facets already known visible are skipped (a set bit is never
+// cleared, so a stale read only costs work).
+__device__ inline void remember_blockers(int *cache, int &ncache, int &cpos, unsigned long long fm, int hit) {
+    for (int added = 0; fm && added < kCache; ++added) {
+        const int src = __ffsll((long long)fm) - 1;
+        fm &= fm - 1;
+        const int r = __shfl(hit, src);
+        bool dup = false;
+        for (int m = 0; m < ncache; ++m) dup |= cache[m] == r;
+        if (dup) continue;
+        if (ncache < kCache) cache[ncache++] = r;
+        else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
+    }
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob *many, int n_jobs,
+                                                   long long n_items, TraverseOpts o, ivm_stats *st) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
@@ -953,8 +1028,6 @@ __global__ __launch_bounds__(kBlock) void k_points(SceneDev sc, int N, const flo
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
     const bool f64 = o.fp64_only != 0;
-    const int nch = (sc.S + kWave - 1) / kWave;
-    const long long n_items = (long long)N * 2 * nch;
     const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
     const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
     const long long per = (n_items + nwaves - 1) / nwaves;
@@ -964,54 +1037,62 @@ __global__ __launch_bounds__(kBlock) void k_points(SceneDev sc, int N, const flo
     unsigned long long segs = 0, items = 0;
     int cache[kCache];
     int ncache = 0, cpos = 0, nmiss = 0, n_order = 0;
-    int cur = -1;  // current (snapshot, side) = 2 n + side
+    long long cur = -1;  // current (job, snapshot, side)
+    int cur_job = 0;
     float xx = 0.f, xy = 0.f, xz = 0.f;
     uint64_t *out = nullptr;
     for (long long it = it0; it <= it1; ++it) {
         const bool more = it < it1;
-        int key = -1, chunk = 0;
+        long long key = -1;
+        int js = 0, chunk = 0;
         if (more) {
-            const int n = (int)(it / (2 * nch));
-            const int rem = (int)(it - (long long)n * 2 * nch);
+            if (MULTI) {
+                int lo = 0, hi = n_jobs - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (many[mid].item_base <= it) lo = mid;
+                    else hi = mid - 1;
+                }
+                js = lo;
+            }
+            const PointJob &J = MULTI ? many[js] : one;
+            const int nch = (J.sc.S + kWave - 1) / kWave;
+            const long long local = it - J.item_base;
+            const int n = (int)(local / (2 * nch));
+            const int rem = (int)(local - (long long)n * 2 * nch);
             const int side = rem / nch;
             chunk = rem - side * nch;
-            key = 2 * n + side;
+            key = ((long long)js << 32) | (long long)(2 * n + side);
         }
         // drain the queue when the point changes (or at the end)
         while (nmiss > 0 && key != cur) {
+            const PointJob &CJ = MULTI ? many[cur_job] : one;
             const int k = min(kWave, nmiss);
             bool clear = false;
             int hit = -1, f = -1;
             if (lane < k) {
-                const int s = miss[nmiss - k + lane];
-                f = sc.sfacet[s];
-                const float4 P = sc.smp[s];
+                const int sidx = miss[nmiss - k + lane];
+                f = CJ.sc.sfacet[sidx];
+                const float4 P = CJ.sc.smp[sidx];
                 const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
-                hit = any_hit(sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+                hit = any_hit(CJ.sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
                 clear = hit < 0;
             }
             nmiss -= k;
             wave_sync();
             if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
-            unsigned long long fm = __ballot(lane < k && !clear);
-            for (int added = 0; fm && added < kCache; ++added) {
-                const int src = __ffsll((long long)fm) - 1;
-                fm &= fm - 1;
-                const int r = __shfl(hit, src);
-                bool dup = false;
-                for (int m = 0; m < ncache; ++m) dup |= cache[m] == r;
-                if (dup) continue;
-                if (ncache < kCache) cache[ncache++] = r;
-                else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
-            }
+            remember_blockers(cache, ncache, cpos, __ballot(lane < k && !clear), hit);
         }
         if (!more) break;
+        const PointJob &J = MULTI ? many[js] : one;
+        const SceneDev &sc = J.sc;
         if (key != cur) {
             cur = key;
-            const int n = key >> 1, side = key & 1;
-            const float *X = (side ? rx : tx) + 3 * n;
+            cur_job = js;
+            const int n = (int)(key & 0xffffffff) >> 1, side = (int)(key & 1);
+            const float *X = (side ? J.rx : J.tx) + 3 * n;
             xx = X[0]; xy = X[1]; xz = X[2];
-            out = (side ? rxv : txv) + (size_t)n * sc.W;
+            out = (side ? J.rxv : J.txv) + (size_t)n * sc.W;
             ncache = 0;
             cpos = 0;
             // treelet order for this point: nearest treelet box first (a heuristic only)
@@ -1059,30 +1140,16 @@ __global__ __launch_bounds__(kBlock) void k_points(SceneDev sc, int N, const flo
         // full traversal batches
         while (nmiss >= kWave) {
             const int k = kWave;
-            bool clear = false;
-            int hit = -1, f = -1;
-            {
-                const int s = miss[nmiss - k + lane];
-                f = sc.sfacet[s];
-                const float4 P = sc.smp[s];
-                const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
-                hit = any_hit(sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
-                clear = hit < 0;
-            }
+            const int s2 = miss[nmiss - k + lane];
+            const int f = sc.sfacet[s2];
+            const float4 P = sc.smp[s2];
+            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+            const int hit = any_hit(sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+            const bool clear = hit < 0;
             nmiss -= k;
             wave_sync();
             if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
-            unsigned long long fm = __ballot(!clear);
-            for (int added = 0; fm && added < kCache; ++added) {
-                const int src = __ffsll((long long)fm) - 1;
-                fm &= fm - 1;
-                const int r = __shfl(hit, src);
-                bool dup = false;
-                for (int m = 0; m < ncache; ++m) dup |= cache[m] == r;
-                if (dup) continue;
-                if (ncache < kCache) cache[ncache++] = r;
-                else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
-            }
+            remember_blockers(cache, ncache, cpos, __ballot(!clear), hit);
         }
     }
     flush_counters(st, c, segs, 0, items);
@@ -1123,21 +1190,66 @@ __global__ void k_check_points(SceneDev sc, int N, const float *tx, const float 
     if (bad) atomicOr(sc.status, bad);
 }
 
-hipError_t launch_points(Scene &scn, const TraverseOpts &o, int N, const float *tx, const float *rx, uint64_t *txv,
-                         uint64_t *rxv, uint8_t *los, ivm_stats *stats, hipStream_t s) {
+long long point_items(const Scene &scn, int N) {
+    const int nch = (scn.dev.S + kWave - 1) / kWave;
+    return (scn.dev.S > 0 && scn.dev.F > 0) ? (long long)N * 2 * nch : 0;
+}
+
+PointJob make_point_job(Scene &scn, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
+                        long long item_base) {
+    PointJob j;
+    j.sc = scn.dev;
+    j.N = N;
+    j.tx = tx;
+    j.rx = rx;
+    j.txv = txv;
+    j.rxv = rxv;
+    j.item_base = item_base;
+    return j;
+}
+
+// Zero the tables and check the positions (on grid, within the exactness budget).
+hipError_t launch_points_prep(Scene &scn, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
+                              hipStream_t s) {
     const SceneDev &sc = scn.dev;
     hipError_t e;
     if ((e = launch_fill_u64(txv, 0ull, (size_t)N * sc.W, s)) != hipSuccess) return e;
     if ((e = launch_fill_u64(rxv, 0ull, (size_t)N * sc.W, s)) != hipSuccess) return e;
+    if (N > 0) hipLaunchKernelGGL(k_check_points, dim3((2 * N + 255) / 256), dim3(256), 0, s, sc, N, tx, rx);
+    return hipGetLastError();
+}
+
+hipError_t launch_los(Scene &scn, const TraverseOpts &o, int N, const float *tx, const float *rx, uint8_t *los,
+                      hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_los, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, scn.dev, N, tx, rx, los, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_items, const TraverseOpts &o,
+                             ivm_stats *stats, hipStream_t s) {
+    if (total_items <= 0) return hipSuccess;
+    PointJob none{};
+    hipLaunchKernelGGL(k_points<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, n_jobs, total_items, o,
+                       stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_points(Scene &scn, const TraverseOpts &o, int N, const float *tx, const float *rx, uint64_t *txv,
+                         uint64_t *rxv, uint8_t *los, ivm_stats *stats, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_points_prep(scn, N, tx, rx, txv, rxv, s)) != hipSuccess) return e;
     if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_check_points, dim3((2 * N + 255) / 256), dim3(256), 0, s, sc, N, tx, rx);
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
-    if (sc.S > 0 && sc.F > 0)
-        hipLaunchKernelGGL(k_points, dim3(o.grid_blocks), dim3(kBlock), 0, s, sc, N, tx, rx, txv, rxv, o, stats);
+    const long long items = point_items(scn, N);
+    if (items > 0) {
+        const PointJob job = make_point_job(scn, N, tx, rx, txv, rxv, 0);
+        hipLaunchKernelGGL(k_points<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PointJob *)nullptr, 1,
+                           items, o, stats);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (o.events && (e = hipEventRecord(o.events[1], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_los, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, N, tx, rx, los, o);
-    return hipGetLastError();
+    return launch_los(scn, o, N, tx, rx, los, s);
 }
 
 }  // namespace ivm
