@@ -58,6 +58,7 @@ def _parse():
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the second-order (plain vs learned) pass")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates profiler byte counters)")
     return ap.parse_args()
@@ -353,7 +354,7 @@ def main():
                             "frac": ach_p / VALU_PEAK_TOPS, "kernel": "k_points"},
     }
     # the other traversal order on the same matrix, timed the same way, bits compared
-    if have_model:
+    if have_model and not args.no_compare:
         other = "plain" if args.order == "learned" else "learned"
         oo = ivm.make_opts(order_mode=ivm.IVM_ORDER_LEARNED if other == "learned" else ivm.IVM_ORDER_PLAIN,
                            fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu, stack_depth=args.stack,
