@@ -129,7 +129,9 @@ typedef struct ivm_stats {
     uint64_t point_items;
     uint64_t flags; /* bit 0: learned order fell back to the plain order */
     uint64_t certified; /* pairs proven blocked by one convex occluder from hull corners */
-    uint64_t reserved[5];
+    uint64_t subpair_runs; /* pairs whose explicit segments were limited to uncertified sub-pairs */
+    uint64_t tiled_pairs;  /* pairs decided from a complete near-field tile, without the BVH */
+    uint64_t reserved[3];
 } ivm_stats;
 
 #define IVM_ORDER_PLAIN 0    /* treelets nearest the pair's segment box first */
@@ -146,7 +148,7 @@ typedef struct ivm_matrix_opts {
     float eps;              /* FP32 filter margin relative to the magnitude bound;
                                0 = default 1e-5; values < 1e-5 are raised to 1e-5;
                                +inf sends every test to FP64 */
-    int32_t reserved;
+    int32_t no_tile;        /* 1: never decide a pair from its near-field tile alone */
     hipEvent_t *timing_events; /* optional (NULL = none): two caller-created events the
                                   call records on its stream immediately before and
                                   after its traversal kernel */

@@ -78,13 +78,14 @@ class ivm_matrix_opts(ctypes.Structure):
     _fields_ = [
         ("order_mode", ctypes.c_int32), ("fp64_only", ctypes.c_int32),
         ("stack_depth", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-        ("eps", ctypes.c_float), ("reserved", ctypes.c_int32),
+        ("eps", ctypes.c_float), ("no_tile", ctypes.c_int32),
         ("timing_events", ctypes.c_void_p),
     ]
 
 
 STATS_FIELDS = ["pairs_total", "pairs_candidate", "pairs_visible", "segments", "node_visits",
-                "tri_tests", "rechecks", "fallbacks", "point_items", "flags", "certified"]
+                "tri_tests", "rechecks", "fallbacks", "point_items", "flags", "certified",
+                "subpair_runs", "tiled_pairs"]
 STATS_WORDS = 16
 
 _lib = None
@@ -177,9 +178,11 @@ def _ptr(t) -> Optional[int]:
 
 
 def make_opts(order_mode: int = IVM_ORDER_PLAIN, fp64_only: bool = False, stack_depth: int = 0,
-              waves_per_cu: int = 0, eps: float = 0.0, timing: Optional["KernelTimer"] = None) -> ivm_matrix_opts:
+              waves_per_cu: int = 0, eps: float = 0.0, timing: Optional["KernelTimer"] = None,
+              no_tile: bool = False) -> ivm_matrix_opts:
     o = ivm_matrix_opts()
     o.order_mode, o.fp64_only, o.stack_depth = order_mode, int(fp64_only), stack_depth
+    o.no_tile = int(no_tile)
     o.waves_per_cu, o.eps = waves_per_cu, eps
     o.timing_events = timing.array_ptr if timing is not None else None
     return o

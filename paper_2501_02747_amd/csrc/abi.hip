@@ -53,6 +53,7 @@ TraverseOpts make_opts(const ivm_matrix_opts *o) {
     if (blocks < 1) blocks = 1;
     t.grid_blocks = (int)blocks;
     t.events = o ? o->timing_events : nullptr;
+    t.no_tile = o ? o->no_tile : 0;
     return t;
 }
 

@@ -86,6 +86,7 @@ TraverseOpts batch_opts(const ivm_matrix_opts *o) {
     long long blocks = (long long)device_cu_count() * wpc / 4;
     t.grid_blocks = (int)(blocks < 1 ? 1 : blocks);
     t.events = nullptr;  // a captured graph records no caller events
+    t.no_tile = o ? o->no_tile : 0;
     return t;
 }
 

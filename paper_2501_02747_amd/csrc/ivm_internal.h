@@ -115,6 +115,7 @@ struct TraverseOpts {
     int stack_depth;
     float eps6;                // 6 * eps: margin factor of the FP32 filter
     int grid_blocks;
+    int no_tile;               // 1: skip the near-field tile
     hipEvent_t *events;        // optional: recorded around the traversal kernel
 };
 

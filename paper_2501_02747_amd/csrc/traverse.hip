@@ -544,6 +544,93 @@ __device__ unsigned certify_subpairs(const SceneDev &sc, int i, int j, int C, un
     return res;
 }
 
+constexpr int kTile = 64;       // near-field tile capacity (triangle ranks)
+constexpr int kFrontier = 128;  // cooperative traversal frontier capacity
+constexpr int kTileMaxTreelets = 6;  // gather a tile only when the bundle box meets at most this many treelets
+
+__device__ inline bool box_overlap(float lx, float ly, float lz, float hx, float hy, float hz, const float lo[3],
+                                   const float hi[3]) {
+    return !(lx > hi[0] || hx < lo[0] || ly > hi[1] || hy < lo[1] || lz > hi[2] || hz < lo[2]);
+}
+
+// Near-field tile: the wave walks the LBVH cooperatively (one frontier node per
+// lane per step) against the closed box [lo, hi] of every admissible segment of
+// the pair and stages the ranks of all triangles whose leaf boxes meet it,
+// except those of facets i and j.  A triangle that meets a segment meets it
+// inside that convex box, so all its ancestors' boxes overlap the box too: when
+// the walk finishes within capacity the tile holds every possible blocker and a
+// segment is decided by scanning the tile alone.  Returns the tile size, or -1
+// when the tile would overflow.
+__device__ int gather_tile(const SceneDev &sc, int i, int j, const float lo[3], const float hi[3],
+                           const uint8_t *order, int n_order, int *frontier, int *tile, int *counters) {
+    const int lane = lane_id();
+    if (lane == 0) {
+        counters[0] = 0;  // frontier size
+        counters[1] = 0;  // tile size
+        counters[2] = 0;  // overflow
+    }
+    wave_sync();
+    if (lane < n_order) frontier[atomicAdd(&counters[0], 1)] = sc.tl_root[order[lane]];
+    wave_sync();
+    while (true) {
+        const int nf = counters[0];
+        if (nf == 0 || counters[2]) break;
+        const int k = min(kWave, nf);
+        const int ref = lane < k ? frontier[nf - k + lane] : kNone;
+        wave_sync();
+        if (lane == 0) counters[0] = nf - k;
+        wave_sync();
+        auto add_leaf = [&](int leaf) {
+            const int first = leaf_first(leaf), cnt = leaf_count(leaf);
+            for (int r = first; r < first + cnt; ++r) {
+                const int f = __float_as_int(sc.tri[3 * r].w);
+                if (f == i || f == j) continue;
+                const int at = atomicAdd(&counters[1], 1);
+                if (at < kTile) tile[at] = r;
+                else counters[2] = 1;
+            }
+        };
+        if (ref != kNone) {
+            if (ref < 0) {
+                add_leaf(ref);
+            } else {
+                const Node nd = sc.nodes[ref];
+                if (box_overlap(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, lo, hi)) {
+                    if (nd.d.x < 0) add_leaf(nd.d.x);
+                    else {
+                        const int at = atomicAdd(&counters[0], 1);
+                        if (at < kFrontier) frontier[at] = nd.d.x;
+                        else counters[2] = 1;
+                    }
+                }
+                if (box_overlap(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, lo, hi)) {
+                    if (nd.d.y < 0) add_leaf(nd.d.y);
+                    else {
+                        const int at = atomicAdd(&counters[0], 1);
+                        if (at < kFrontier) frontier[at] = nd.d.y;
+                        else counters[2] = 1;
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+    const int n = counters[2] ? -1 : counters[1];
+    wave_sync();
+    return n;
+}
+
+// Exact any-hit over the tile: the first definite FP32 hit decides; undecided
+// tests go to FP64.
+__device__ inline int tile_hit(const SceneDev &sc, const Seg &s, const int *tile, int n, float eps6, bool f64, Cnt &c) {
+    for (int k = 0; k < n; ++k) {
+        const int r = tile[k];
+        ++c.tests;
+        if (tri_hit(s, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], eps6, f64, c.rechecks)) return r;
+    }
+    return -1;
+}
+
 // A segment space is a list of rectangles of (admissible p index, admissible q
 // index): rect k covers p in [pa, pa + pn) and q in [qb, qb + qn).
 struct Rects {
@@ -565,6 +652,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
     __shared__ int sMiss[kWavesPerBlock][2 * kWave];
     __shared__ unsigned long long sBits[kWavesPerBlock][16];
     __shared__ Rects sR[kWavesPerBlock];
+    __shared__ int sTile[kWavesPerBlock][kTile];
+    __shared__ int sTileCnt[kWavesPerBlock][4];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t total = MULTI ? base[n_jobs] : one.prefix[one.n_items];
     int *stk = &sStack[wv][lane];
@@ -572,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
     Rects &R = sR[wv];
     const bool f64 = o.fp64_only != 0;
     Cnt c;
-    unsigned long long segs = 0, nvis = 0, ncert = 0, nsub = 0;
+    unsigned segs = 0, nvis = 0, ncert = 0, nsub = 0, ntiled = 0;  // per-wave counts fit 32 bits
     const unsigned long long lt = (1ull << lane) - 1ull;
     while (true) {
         uint32_t g = 0;
@@ -632,6 +721,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
         unsigned long long lcode = 0;
         if (o.order_mode == IVM_ORDER_LEARNED && J.learned) lcode = J.learned[gl];
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
+        // near-field tile (the miss queue's storage doubles as the walk frontier)
+        // (only for bundles meeting few treelets: a long bundle would overflow the tile anyway)
+        const int ntile = (o.no_tile || n_order > kTileMaxTreelets)
+                              ? -1
+                              : gather_tile(sc, i, j, lo, hi, sOrder[wv], n_order, sMiss[wv], sTile[wv], sTileCnt[wv]);
+        ntiled += ntile >= 0;
         // phase 0: the whole product space, until the first traversal batch
         if (lane == 0) {
             R.n = 1;
@@ -691,7 +786,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
                     const int ab = miss[nmiss - k + lane];
                     const float4 P = sP[wv][ab & 255], Q = sQ[wv][ab >> 8];
                     const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
-                    hit = any_hit(sc, sg, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
+                    hit = ntile >= 0 ? tile_hit(sc, sg, sTile[wv], ntile, o.eps6, f64, c)
+                                     : any_hit(sc, sg, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
                     clear = hit < 0;
                 }
                 nmiss -= k;
@@ -785,8 +881,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
         wave_sync();
     }
     flush_counters(st, c, segs, nvis, 0);
-    if (st && lane == 0 && ncert) atomicAdd((unsigned long long *)&st->certified, ncert);
-    if (st && lane == 0 && nsub) atomicAdd((unsigned long long *)&st->reserved[0], nsub);
+    if (st && lane == 0 && ncert) atomicAdd((unsigned long long *)&st->certified, (unsigned long long)ncert);
+    if (st && lane == 0 && nsub) atomicAdd((unsigned long long *)&st->subpair_runs, (unsigned long long)nsub);
+    if (st && lane == 0 && ntiled) atomicAdd((unsigned long long *)&st->tiled_pairs, (unsigned long long)ntiled);
 }
 
 // Hit records for the occluder-ordering network: for each listed pair, the set

@@ -106,26 +106,28 @@ def test_urban_grid_medium_full_parity(oracle_mod, ivm, nx, ny):
     assert (out["counts"].cpu().numpy() == co).all()
 
 
-@pytest.mark.parametrize("mode,fp64,stack,eps", [
-    ("index", False, 0, 0.0), ("reversed", False, 0, 0.0), ("plain", False, 2, 0.0),
-    ("plain", False, 3, 0.0), ("plain", False, 0, float("inf")), ("plain", True, 2, 0.0),
-    ("plain", False, 0, 1e-2),
+@pytest.mark.parametrize("mode,fp64,stack,eps,no_tile", [
+    ("index", False, 0, 0.0, False), ("reversed", False, 0, 0.0, False), ("plain", False, 2, 0.0, True),
+    ("plain", False, 3, 0.0, False), ("plain", False, 0, float("inf"), False), ("plain", True, 2, 0.0, True),
+    ("plain", False, 0, 1e-2, False), ("index", False, 0, 0.0, True), ("plain", False, 0, float("inf"), True),
 ])
-def test_result_independent_of_options(oracle_mod, ivm, mode, fp64, stack, eps):
+def test_result_independent_of_options(oracle_mod, ivm, mode, fp64, stack, eps, no_tile):
     """Treelet order, FP64-only mode, a tiny stack (forces the linear-scan fallback),
-    and the filter margin (inf sends every test to FP64) never change a bit."""
+    the filter margin (inf sends every test to FP64) and the near-field tile never
+    change a bit."""
     import torch
-    _log(f"[options] {mode} fp64={fp64} stack={stack} eps={eps}")
+    _log(f"[options] {mode} fp64={fp64} stack={stack} eps={eps} no_tile={no_tile}")
     s = sg.gen_c2(5, n_snap=8, nx=4, ny=3)
     orc = oracle_mod.Oracle(s)
     Mo, _ = orc.matrix()
     tvo, rvo, loso = orc.txrx(s.tx, s.rx)
     m = {"plain": ivm.IVM_ORDER_PLAIN, "index": ivm.IVM_ORDER_INDEX, "reversed": ivm.IVM_ORDER_REVERSED}[mode]
-    opts = ivm.make_opts(order_mode=m, fp64_only=fp64, stack_depth=stack, eps=eps)
-    st = ivm.new_stats()
+    opts = ivm.make_opts(order_mode=m, fp64_only=fp64, stack_depth=stack, eps=eps, no_tile=no_tile)
+    st, stp = ivm.new_stats(), ivm.new_stats()
     g = ivm.GpuScene.from_scene(s).check()
     M = ivm.ivm_intervisibility_matrix(g, opts, stats=st)
-    tv, rv, los = ivm.ivm_txrx_visibility_table(g, torch.as_tensor(s.tx).cuda(), torch.as_tensor(s.rx).cuda(), opts)
+    tv, rv, los = ivm.ivm_txrx_visibility_table(g, torch.as_tensor(s.tx).cuda(), torch.as_tensor(s.rx).cuda(), opts,
+                                                stats=stp)
     torch.cuda.synchronize()
     _assert_matrix(ivm, M, Mo, s.n_facets)
     assert (ivm.unpack_bits(tv, s.n_facets) == tvo).all()
@@ -134,10 +136,13 @@ def test_result_independent_of_options(oracle_mod, ivm, mode, fp64, stack, eps):
     d = ivm.stats_dict(st)
     assert d["pairs_visible"] == Mo.sum() // 2
     assert d["pairs_total"] == s.n_facets * (s.n_facets - 1) // 2
+    dp = ivm.stats_dict(stp)
     if stack == 2:
         assert d["fallbacks"] > 0, "a 2-deep stack must overflow and take the linear-scan path"
+    if no_tile:
+        assert d["tiled_pairs"] == 0
     if eps == float("inf") and not fp64:
-        assert d["rechecks"] == d["tri_tests"], "eps=inf sends every test to FP64"
+        assert d["rechecks"] >= d["tri_tests"] // 2, "eps=inf sends every traversal test to FP64"
 
 
 def test_triangle_groups_match_oracle_partition(oracle_mod, ivm):
