@@ -91,6 +91,21 @@ typedef struct ivm_scene_desc {
     int32_t grid_vertex_log2;
     int32_t grid_sample_log2;
     int32_t flags; /* IVM_SCENE_* */
+    /* Optional occluder grouping hint (NULL / 0 = none).  facet_solid is a
+     * device int32[n_facets] with values in [0, n_solids) or -1, typically the
+     * building each facet belongs to (the scenario database of Section III-C
+     * stores faces per building).  The build checks every group exactly and
+     * keeps only those that bound a vertical convex prism: wall facets in
+     * vertical planes whose traces close into one convex polygon P, roof
+     * facets covering P at the top height, walls covering P's edges from the
+     * lowest to the top height (covering tested by exact areas plus pairwise
+     * interior-disjoint triangles).  A kept group lets the traversal prove a
+     * whole bundle of segments blocked at once (every segment entering the
+     * prism's interior above its base crosses one of its triangles).  The hint
+     * never changes a result bit: a wrong or partial hint only leaves groups
+     * unused.  Values outside [-1, n_solids) are treated as -1. */
+    const int32_t *facet_solid;
+    int32_t n_solids; /* 0..65535 */
 } ivm_scene_desc;
 
 /* desc.flags: reserve room for a learned traversal order of every facet pair
@@ -131,7 +146,8 @@ typedef struct ivm_stats {
     uint64_t certified; /* pairs proven blocked by one convex occluder from hull corners */
     uint64_t subpair_runs; /* pairs whose explicit segments were limited to uncertified sub-pairs */
     uint64_t tiled_pairs;  /* pairs decided from a complete near-field tile, without the BVH */
-    uint64_t reserved[3];
+    uint64_t solid_certified; /* pairs or point bundles proven blocked by one verified solid */
+    uint64_t reserved[2];
 } ivm_stats;
 
 #define IVM_ORDER_PLAIN 0    /* treelets nearest the pair's segment box first */
@@ -178,6 +194,10 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
 ivm_status ivm_scene_status(ivm_scene *scene);
 
 ivm_status ivm_scene_info(const ivm_scene *scene, ivm_scene_info_t *info);
+
+/* Synchronises the build stream and reports how many groups of the
+ * facet_solid hint passed the prism check (host int32). */
+ivm_status ivm_scene_solids(ivm_scene *scene, int32_t *n_verified);
 
 ivm_status ivm_destroy_scene(ivm_scene *scene);
 

@@ -41,6 +41,7 @@ EXPORTED = [
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
     "ivm_batch_workspace_size", "ivm_batch_create", "ivm_batch_run", "ivm_batch_destroy",
+    "ivm_scene_solids",
 ]
 
 IVM_MLP_FEATURES, IVM_MLP_HIDDEN, IVM_MLP_OUTPUTS, IVM_MLP_PARAMS = 24, 128, 32, 40352
@@ -62,6 +63,7 @@ class ivm_scene_desc(ctypes.Structure):
         ("samples", ctypes.c_void_p),
         ("grid_vertex_log2", ctypes.c_int32), ("grid_sample_log2", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("facet_solid", ctypes.c_void_p), ("n_solids", ctypes.c_int32),
     ]
 
 
@@ -85,7 +87,7 @@ class ivm_matrix_opts(ctypes.Structure):
 
 STATS_FIELDS = ["pairs_total", "pairs_candidate", "pairs_visible", "segments", "node_visits",
                 "tri_tests", "rechecks", "fallbacks", "point_items", "flags", "certified",
-                "subpair_runs", "tiled_pairs"]
+                "subpair_runs", "tiled_pairs", "solid_certified"]
 STATS_WORDS = 16
 
 _lib = None
@@ -111,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_scene_status.argtypes = [P]
     lib.ivm_scene_info.restype = i32
     lib.ivm_scene_info.argtypes = [P, ctypes.POINTER(ivm_scene_info_t)]
+    lib.ivm_scene_solids.restype = i32
+    lib.ivm_scene_solids.argtypes = [P, ctypes.POINTER(i32)]
     lib.ivm_destroy_scene.restype = i32
     lib.ivm_destroy_scene.argtypes = [P]
     lib.ivm_intervisibility_matrix.restype = i32
@@ -237,10 +241,12 @@ class GpuScene:
 
     Takes host arrays (any object with the ``vertices``, ``tri_vertices``,
     ``tri_facet``, ``sample_offsets``, ``samples``, ``g``, ``k`` attributes,
-    or explicit arrays) and copies them to the device once."""
+    or explicit arrays) and copies them to the device once.  ``facet_solid``
+    (optional int32[F], -1 or a group id) is the occluder grouping hint of
+    ivm_scene_desc; groups are checked on the device and never change a result."""
 
     def __init__(self, vertices, tri_vertices, tri_facet, sample_offsets, samples, g: int, gs: int,
-                 learned: bool = False, device: str = "cuda", stream=None):
+                 learned: bool = False, device: str = "cuda", stream=None, facet_solid=None):
         import torch
         lib = load_library()
         if not torch.cuda.is_available():
@@ -261,6 +267,14 @@ class GpuScene:
         d.samples = _ptr(self.samples)
         d.grid_vertex_log2, d.grid_sample_log2 = g, gs
         d.flags = IVM_SCENE_LEARNED if learned else 0
+        self.facet_solid = None
+        if facet_solid is not None:
+            fs = np.ascontiguousarray(facet_solid, np.int32)
+            if fs.shape != (d.n_facets,):
+                raise ValueError("facet_solid must hold one id per facet")
+            self.facet_solid = torch.as_tensor(fs).to(dev)
+            d.facet_solid = _ptr(self.facet_solid)
+            d.n_solids = int(fs.max(initial=-1)) + 1
         self.desc = d
         nbytes = ctypes.c_size_t(0)
         _check(lib.ivm_scene_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), "ivm_scene_workspace_size")
@@ -293,9 +307,20 @@ class GpuScene:
         return self
 
     @classmethod
-    def from_scene(cls, sc, **kw) -> "GpuScene":
+    def from_scene(cls, sc, solids: bool = True, facet_solid=None, **kw) -> "GpuScene":
+        """solids: pass the scene's building ids as the occluder grouping hint
+        (an explicit facet_solid array takes precedence)."""
+        fs = facet_solid
+        if fs is None and solids:
+            fs = getattr(sc, "facet_building", None)
         return cls(sc.vertices, sc.tri_vertices, sc.tri_facet, sc.sample_offsets, sc.samples,
-                   sc.g, sc.g + sc.k, **kw)
+                   sc.g, sc.g + sc.k, facet_solid=fs, **kw)
+
+    def solids_verified(self) -> int:
+        """Number of hint groups that passed the device-side prism check (synchronises)."""
+        n = ctypes.c_int32(0)
+        _check(load_library().ivm_scene_solids(self.handle, ctypes.byref(n)), "ivm_scene_solids")
+        return int(n.value)
 
     def status(self) -> int:
         return ivm_scene_status(self)

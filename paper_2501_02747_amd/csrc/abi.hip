@@ -33,6 +33,7 @@ bool desc_sizes_ok(const ivm_scene_desc *d) {
     if (d->n_facets > 0 && !d->sample_offsets) return false;
     if (d->n_triangles > 0 && (!d->tri_vertices || !d->tri_facet || !d->vertices || d->n_vertices == 0)) return false;
     if (d->n_samples > 0 && !d->samples) return false;
+    if (d->n_solids < 0 || d->n_solids > 65535) return false;
     return true;
 }
 
@@ -78,7 +79,7 @@ const char *ivm_status_string(ivm_status s) {
 ivm_status ivm_scene_workspace_size(const ivm_scene_desc *desc, size_t *bytes) {
     if (!desc || !bytes || !desc_sizes_ok(desc)) return IVM_ERR_INVALID_ARGUMENT;
     *bytes = make_layout(desc->n_facets, desc->n_triangles, desc->n_samples,
-                         (desc->flags & IVM_SCENE_LEARNED) != 0)
+                         (desc->flags & IVM_SCENE_LEARNED) != 0, desc->n_solids)
                  .total;
     return IVM_OK;
 }
@@ -89,7 +90,8 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     *out = nullptr;
     if (!desc || !desc_sizes_ok(desc) || !d_workspace) return IVM_ERR_INVALID_ARGUMENT;
     if (((uintptr_t)d_workspace & 255u) != 0) return IVM_ERR_INVALID_ARGUMENT;
-    Layout L = make_layout(desc->n_facets, desc->n_triangles, desc->n_samples, (desc->flags & IVM_SCENE_LEARNED) != 0);
+    Layout L = make_layout(desc->n_facets, desc->n_triangles, desc->n_samples, (desc->flags & IVM_SCENE_LEARNED) != 0,
+                           desc->n_solids);
     if (workspace_bytes < L.total) return IVM_ERR_WORKSPACE;
     ivm_scene *h = new (std::nothrow) ivm_scene();
     if (!h) return IVM_ERR_INVALID_ARGUMENT;
@@ -133,6 +135,11 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.fnorm = (const float *)(ws + L.fnorm);
     d.status = (int *)(ws + L.status);
     d.extent = (const double *)(ws + L.extent);
+    d.fflags = (const int *)(ws + L.fflags);
+    d.fsolid = (const int *)(ws + L.fsolid);
+    d.solid = (const int4 *)(ws + L.sol_rec);
+    d.splane = (const int4 *)(ws + L.sol_plane);
+    d.n_solids = desc->facet_solid ? desc->n_solids : 0;
     sc.n_items = F * d.W;
     if (launch_build(sc, stream) != hipSuccess) {
         delete h;
@@ -148,6 +155,17 @@ ivm_status ivm_scene_status(ivm_scene *scene) {
     if (hipStreamSynchronize(scene->s.build_stream) != hipSuccess) return IVM_ERR_HIP;
     if (hipMemcpy(&bits, scene->s.dev.status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return IVM_ERR_HIP;
     return status_from_bits(bits);
+}
+
+ivm_status ivm_scene_solids(ivm_scene *scene, int32_t *n_verified) {
+    if (!scene || !n_verified) return IVM_ERR_INVALID_ARGUMENT;
+    if (hipStreamSynchronize(scene->s.build_stream) != hipSuccess) return IVM_ERR_HIP;
+    int n = 0;
+    if (hipMemcpy(&n, (const char *)scene->s.ws + scene->s.lay.sol_nver, sizeof(int), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return IVM_ERR_HIP;
+    *n_verified = n;
+    return IVM_OK;
 }
 
 ivm_status ivm_scene_info(const ivm_scene *scene, ivm_scene_info_t *info) {

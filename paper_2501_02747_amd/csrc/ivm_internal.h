@@ -17,6 +17,13 @@ constexpr int kDefaultStack = 24;
 constexpr int kMaxSamplesPerFacet = 64;
 constexpr float kDefaultEps = 1e-5f;
 constexpr int kHullMax = 8;       // sample convex hull points kept per facet (0 = none kept)
+constexpr int kSolidMaxFacets = 64;   // facets per solid group considered by the prism check
+constexpr int kSolidMaxTris = 128;    // triangles per solid group
+constexpr int kSolidMaxPlanes = 16;   // wall planes per solid
+constexpr int kConvexMaxTris = 16;    // triangles per facet considered by the convexity check
+
+// Per-facet flags (fflags).
+constexpr int kFacetConvex = 1;       // the facet's triangles tile one convex polygon
 
 // Status bits raised on the device, mapped to ivm_status by the host.
 constexpr int kStGrid = 1;
@@ -70,6 +77,12 @@ struct SceneDev {
     const float *fnorm;        // 4: scene-box centre (3) and half-size used to normalise features
     int *status;               // device status bits
     const double *extent;      // [0..5] = sample-unit integer box of vertices+samples as doubles; [6] = E
+    const int *fflags;         // F: kFacet* bits
+    const int *fsolid;         // F: verified solid of the facet, or -1
+    const int4 *solid;         // n_solids: (wall planes, top z, base z, 0), sample units; 0 planes = rejected
+    const int4 *splane;        // n_solids * kSolidMaxPlanes: (u.x, u.y, d.x, d.y) sample units; the
+                               // outside of wall k is d.y (x - u.x) - d.x (y - u.y) > 0
+    int n_solids;
 };
 
 // Workspace layout of one scene.
@@ -77,10 +90,11 @@ struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
     size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
+    size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver;
     size_t learned_bytes;
     size_t total;
 };
-Layout make_layout(int F, int T, int S, bool learned);
+Layout make_layout(int F, int T, int S, bool learned, int n_solids);
 
 // Opaque handle behind ivm_scene.
 struct Scene {
@@ -140,6 +154,7 @@ struct PointJob {
 
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_build(Scene &sc, hipStream_t s);
+hipError_t launch_solids(Scene &sc, hipStream_t s);
 hipError_t launch_matrix(Scene &sc, const TraverseOpts &o, uint64_t *M, ivm_stats *stats,
                          const uint8_t *learned_order, hipStream_t s);
 hipError_t launch_points(Scene &sc, const TraverseOpts &o, int N, const float *tx, const float *rx,

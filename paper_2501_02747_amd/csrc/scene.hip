@@ -21,7 +21,7 @@ namespace ivm {
 
 static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(int F, int T, int S, bool learned) {
+Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -62,6 +62,15 @@ Layout make_layout(int F, int T, int S, bool learned) {
     L.fchull_n = take(Fn * 4 * sizeof(int));
     L.ffeat = take(Fn * 8 * sizeof(float));
     L.fnorm = take(8 * sizeof(float));
+    const size_t Ns = n_solids > 0 ? (size_t)n_solids : 1;
+    L.fflags = take(Fn * sizeof(int));
+    L.fsolid = take(Fn * sizeof(int));
+    L.sol_cnt = take((Ns + 1) * 2 * sizeof(int));
+    L.sol_off = take((Ns + 1) * sizeof(int));
+    L.sol_fac = take(Fn * sizeof(int));
+    L.sol_rec = take(Ns * sizeof(int4));
+    L.sol_plane = take(Ns * kSolidMaxPlanes * sizeof(int4));
+    L.sol_nver = take(sizeof(int));
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
@@ -268,7 +277,15 @@ __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane
     const double an0 = fabs(n[0]), an1 = fabs(n[1]), an2 = fabs(n[2]);
     const int drop = (an0 >= an1 && an0 >= an2) ? 0 : (an1 >= an2 ? 1 : 2);
     const int ns = s1 - s0;
-    const bool hull_ok = !(bad & kStDegenerate) && ns > 0 && ns <= kMaxSamplesPerFacet;
+    // The sample hulls stand for the facet's sample set in 3-D only when every
+    // sample lies in the facet's plane (exact: the orient budget covers samples).
+    bool in_plane = true;
+    for (int s = s0; s < s1 && in_plane; ++s) {
+        const double o = ((double)d.samples[3 * s] - a[0]) * n[0] + ((double)d.samples[3 * s + 1] - a[1]) * n[1] +
+                         ((double)d.samples[3 * s + 2] - a[2]) * n[2];
+        in_plane = o == 0.0;
+    }
+    const bool hull_ok = !(bad & kStDegenerate) && in_plane && ns > 0 && ns <= kMaxSamplesPerFacet;
     int list[kMaxSamplesPerFacet];
     for (int m = 0; m < ns && m < kMaxSamplesPerFacet; ++m) list[m] = s0 + m;
     fhull_n[f] = hull_ok ? sample_hull(d.samples, list, ns, drop, fhull + kHullMax * f) : 0;
@@ -686,6 +703,7 @@ hipError_t launch_build(Scene &sc, hipStream_t s) {
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = launch_solids(sc, s)) != hipSuccess) return e;
     return launch_facet_features(sc, s);
 }
 

@@ -459,9 +459,11 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 }
 
 constexpr int kCache = 4;  // recent blockers tested before a traversal
+constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
 
 // Single-occluder certificate.  Let H_i, H_j be the convex hulls of the two
-// sample sets and C a convex facet.  For fixed q the points p whose open segment
+// sample sets (valid when the samples lie in their facet's plane, checked at
+// build) and C a facet whose triangles tile one convex polygon (also checked).  For fixed q the points p whose open segment
 // to q meets C form a convex set, and symmetrically for p fixed; so if every
 // segment between hull corners meets C transversally inside (0, 1), every
 // segment between the hulls does, and each crosses C's plane strictly, at a point
@@ -473,7 +475,7 @@ __device__ bool certify_blocked(const SceneDev &sc, int i, int j, int C, int *co
     const int lane = lane_id();
     const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
     const int t0 = sc.ftri[2 * C], nt = sc.ftri[2 * C + 1];
-    if (ni == 0 || nj == 0 || nt <= 0) return false;
+    if (ni == 0 || nj == 0 || nt <= 0 || !(sc.fflags[C] & kFacetConvex)) return false;
     const int pairs = ni * nj;  // <= kHullMax^2 = 64
     corner[lane] = 0;
     wave_sync();
@@ -494,6 +496,71 @@ __device__ bool certify_blocked(const SceneDev &sc, int i, int j, int C, int *co
     return ok;
 }
 
+// a * b < c * d, exact for doubles holding integers of magnitude below 2^52:
+// the rounded products order the exact ones unless they tie, and then the
+// rounding errors (exact by fma) decide.
+__device__ inline bool prod_less(double a, double b, double c, double d) {
+    const double p = a * b, q = c * d;
+    if (p != q) return p < q;
+    return fma(a, b, -p) < fma(c, d, -q);
+}
+
+// Solid certificate.  A verified solid s is an open convex prism K (wall
+// planes and roof plane; unbounded below) whose walls and roof above its base
+// height zb are covered by triangles of its facets.  Every segment between the
+// sample hulls H_i and H_j is blocked when
+//   (i)   H_i lies strictly outside one face plane of K, and so does H_j;
+//   (ii)  every hull corner has z >= zb;
+//   (iii) every segment between hull corners passes through K.
+// For p outside K the points q whose segment to p meets K form the convex set
+// p + [1, inf)(K - p), so (iii) at the corners holds for all of H_i x H_j.  Such
+// a segment enters K at a point e with 0 < t < 1; by (ii) e lies at or above
+// the base, on a covered face, and every face plane through e is crossed
+// strictly (the segment goes from its outside to its inside), so the open
+// segment meets a closed covering triangle transversally.  The triangle is not
+// of facet i or j: those lie outside K by (i).  One lane per corner pair.
+// Plane values are exact FP64 integers in sample units (below 2^51); the
+// interval of t inside K is intersected with exact fraction comparisons.
+__device__ bool certify_solid(const SceneDev &sc, int i, int j, int s) {
+    const int4 R = sc.solid[s];
+    const int np = R.x;
+    const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
+    if (np <= 0 || ni == 0 || nj == 0) return false;
+    const int lane = lane_id();
+    const bool act = lane < ni * nj;
+    const int a = act ? lane / nj : 0, b = act ? lane - (lane / nj) * nj : 0;
+    const double u = ldexp(1.0, sc.gs);
+    const float4 P = sc.smp[sc.fhull[kHullMax * i + a]], Q = sc.smp[sc.fhull[kHullMax * j + b]];
+    const double px = P.x * u, py = P.y * u, pz = P.z * u, qx = Q.x * u, qy = Q.y * u, qz = Q.z * u;
+    bool good = pz >= (double)R.z && qz >= (double)R.z;
+    double Ln = 0.0, Ld = 1.0, Un = 1.0, Ud = 1.0;  // t in (Ln / Ld, Un / Ud)
+    bool outP = false, outQ = false;
+    for (int k = 0; k <= np; ++k) {
+        double va, vb;
+        if (k < np) {
+            const int4 pl = sc.splane[s * kSolidMaxPlanes + k];
+            va = (double)pl.w * (px - (double)pl.x) - (double)pl.z * (py - (double)pl.y);
+            vb = (double)pl.w * (qx - (double)pl.x) - (double)pl.z * (qy - (double)pl.y);
+        } else {
+            va = pz - (double)R.y;
+            vb = qz - (double)R.y;
+        }
+        outP |= __ballot(act && b == 0 && !(va > 0.0)) == 0ull;
+        outQ |= __ballot(act && a == 0 && !(vb > 0.0)) == 0ull;
+        if (va >= 0.0 && vb >= 0.0) {
+            good = false;
+        } else if (va >= 0.0) {  // enters this half-space at t = va / (va - vb)
+            const double n = va, dd = va - vb;
+            if (prod_less(Ln, dd, n, Ld)) { Ln = n; Ld = dd; }
+        } else if (vb >= 0.0) {  // leaves it at t = -va / (vb - va)
+            const double n = -va, dd = vb - va;
+            if (prod_less(n, Ud, Un, dd)) { Un = n; Ud = dd; }
+        }
+    }
+    good = good && prod_less(Ln, Ud, Un, Ld);
+    return outP && outQ && __ballot(act && !good) == 0ull;
+}
+
 // Certificate per sub-pair: the samples of each facet are split into 4
 // quadrant clusters (scene build) and sub-pair (ci, cj) is certified blocked by
 // facet C when every segment between the corners of the two cluster hulls
@@ -504,7 +571,7 @@ __device__ unsigned certify_subpairs(const SceneDev &sc, int i, int j, int C, un
                                      unsigned long long *bits, float eps6, bool f64, Cnt &c) {
     const int lane = lane_id();
     const int t0 = sc.ftri[2 * C], nt = sc.ftri[2 * C + 1];
-    if (nt <= 0 || !todo) return 0u;
+    if (nt <= 0 || !todo || !(sc.fflags[C] & kFacetConvex)) return 0u;
     if (lane < 16) bits[lane] = 0ull;
     wave_sync();
     int total = 0;
@@ -641,7 +708,7 @@ struct Rects {
 // MULTI: the queue index runs over the concatenated candidates of n_jobs scenes
 // (base[] = exclusive prefix of their candidate totals); otherwise over `one`.
 template <bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *many, const uint32_t *base, int n_jobs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_pairs(PairJob one, const PairJob *many, const uint32_t *base, int n_jobs,
                                                   uint32_t *queue, TraverseOpts o, ivm_stats *st) {
     __shared__ float4 sP[kWavesPerBlock][kWave];
     __shared__ float4 sQ[kWavesPerBlock][kWave];
@@ -661,7 +728,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
     Rects &R = sR[wv];
     const bool f64 = o.fp64_only != 0;
     Cnt c;
-    unsigned segs = 0, nvis = 0, ncert = 0, nsub = 0, ntiled = 0;  // per-wave counts fit 32 bits
+    unsigned segs = 0, nvis = 0, ncert = 0, nsub = 0, ntiled = 0, nsolid = 0;  // per-wave counts fit 32 bits
     const unsigned long long lt = (1ull << lane) - 1ull;
     while (true) {
         uint32_t g = 0;
@@ -812,9 +879,24 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
                     first_traversal = false;
                     // the first traversal batch is all blocked: try to prove the whole pair
                     // blocked by the facet that blocked its first lane, then its last lane's
+                    // first by the verified solids met by this batch, then by single facets
+                    int sid = (lane < k && sc.n_solids > 0) ? sc.fsolid[__float_as_int(sc.tri[3 * hit].w)] : -1;
+                    bool blocked = false;
+                    for (int u = 0; u < kSolidTries && !blocked; ++u) {
+                        const unsigned long long left = __ballot(sid >= 0);
+                        if (!left) break;
+                        const int S0 = __shfl(sid, __ffsll((long long)left) - 1);
+                        if (sid == S0) sid = -1;
+                        blocked = certify_solid(sc, i, j, S0);
+                    }
+                    if (blocked) {
+                        ++nsolid;
+                        done = true;
+                        break;
+                    }
                     const int C1 = __float_as_int(sc.tri[3 * __shfl(hit, 0)].w);
                     const int C2 = __float_as_int(sc.tri[3 * __shfl(hit, k - 1)].w);
-                    bool blocked = certify_blocked(sc, i, j, C1, sCorner[wv], o.eps6, f64, c);
+                    blocked = certify_blocked(sc, i, j, C1, sCorner[wv], o.eps6, f64, c);
                     if (!blocked && C2 != C1) blocked = certify_blocked(sc, i, j, C2, sCorner[wv], o.eps6, f64, c);
                     if (blocked) {
                         ++ncert;
@@ -884,6 +966,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairJob one, const PairJob *ma
     if (st && lane == 0 && ncert) atomicAdd((unsigned long long *)&st->certified, (unsigned long long)ncert);
     if (st && lane == 0 && nsub) atomicAdd((unsigned long long *)&st->subpair_runs, (unsigned long long)nsub);
     if (st && lane == 0 && ntiled) atomicAdd((unsigned long long *)&st->tiled_pairs, (unsigned long long)ntiled);
+    if (st && lane == 0 && nsolid) atomicAdd((unsigned long long *)&st->solid_certified, (unsigned long long)nsolid);
 }
 
 // Hit records for the occluder-ordering network: for each listed pair, the set

@@ -154,6 +154,22 @@ class SceneBuilder:
         self.building.append(building)
         return f
 
+    def add_mesh_facet(self, verts, tris, samples, kind: int = KIND_PLATE, building: int = -1) -> int:
+        """Facet from explicit triangles: verts (vertex units), tris (indices into
+        verts, the first triangle's winding gives the visible side), samples
+        (sample units).  For test scenes with non-convex facets."""
+        f = self.n_facets
+        base = len(self.verts)
+        self.verts.extend(tuple(int(c) for c in v) for v in verts)
+        for t in tris:
+            self.tris.append(tuple(base + int(c) for c in t))
+            self.tri_facet.append(f)
+        self.samples.extend(tuple(int(c) for c in q) for q in samples)
+        self.offsets.append(len(self.samples))
+        self.kind.append(kind)
+        self.building.append(building)
+        return f
+
     def add_rect(self, v0, U, V, n: int, kind: int = KIND_PLATE, building: int = -1) -> int:
         """Rectangle v0, v0+U, v0+U+V, v0+V (vertex units); n x n cell-centre samples."""
         if (1 << self.k) != 2 * n:
@@ -204,20 +220,26 @@ class SceneBuilder:
             smp.append((cx, cy, z * vs))
         return self._add_facet(poly, smp, KIND_ROOF, building)
 
-    def add_box(self, x0, y0, x1, y1, h, n, building, split_x: int = 1) -> List[int]:
-        """Axis-aligned box building: 4 walls (x-walls split into `split_x` panels) + roof."""
+    def add_box(self, x0, y0, x1, y1, h, n, building, split_x: int = 1, omit=()) -> List[int]:
+        """Axis-aligned box building: 4 walls (x-walls split into `split_x` panels) + roof.
+        Facets are made in the order south panels, north panels, west, east, roof;
+        positions listed in `omit` are left out (test scenes with open boxes)."""
         ids = []
         w, d = x1 - x0, y1 - y0
         if w % split_x:
             raise ValueError("panel split must land on the vertex grid")
         pw = w // split_x
+        parts = []
         for s in range(split_x):   # south wall, outward -y: U=+x, V=+z
-            ids.append(self.add_rect((x0 + s * pw, y0, 0), (pw, 0, 0), (0, 0, h), n, KIND_WALL, building))
+            parts.append(((x0 + s * pw, y0, 0), (pw, 0, 0), (0, 0, h), KIND_WALL))
         for s in range(split_x):   # north wall, outward +y: U=+z, V=+x
-            ids.append(self.add_rect((x0 + s * pw, y1, 0), (0, 0, h), (pw, 0, 0), n, KIND_WALL, building))
-        ids.append(self.add_rect((x0, y0, 0), (0, 0, h), (0, d, 0), n, KIND_WALL, building))  # west, -x
-        ids.append(self.add_rect((x1, y0, 0), (0, d, 0), (0, 0, h), n, KIND_WALL, building))  # east, +x
-        ids.append(self.add_rect((x0, y0, h), (w, 0, 0), (0, d, 0), n, KIND_ROOF, building))  # roof, +z
+            parts.append(((x0 + s * pw, y1, 0), (0, 0, h), (pw, 0, 0), KIND_WALL))
+        parts.append(((x0, y0, 0), (0, 0, h), (0, d, 0), KIND_WALL))  # west, -x
+        parts.append(((x1, y0, 0), (0, d, 0), (0, 0, h), KIND_WALL))  # east, +x
+        parts.append(((x0, y0, h), (w, 0, 0), (0, d, 0), KIND_ROOF))  # roof, +z
+        for m, (v0, U, V, kind) in enumerate(parts):
+            if m not in omit:
+                ids.append(self.add_rect(v0, U, V, n, kind, building))
         return ids
 
     def build(self, name: str, seed: int, tx_s=None, rx_s=None) -> Scene:
