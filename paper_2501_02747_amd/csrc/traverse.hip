@@ -505,6 +505,23 @@ __device__ inline bool prod_less(double a, double b, double c, double d) {
     return fma(a, b, -p) < fma(c, d, -q);
 }
 
+// Up to kSolidTries distinct verified solids among the blockers `hit` of the
+// lanes with `blocked`, appended to the wave-uniform list (oldest replaced).
+__device__ inline void remember_solid_ids(const SceneDev &sc, int *solids, int &nsol, int &spos, bool blocked,
+                                          int hit) {
+    int sid = blocked ? sc.fsolid[__float_as_int(sc.tri[3 * hit].w)] : -1;
+    for (int m = 0; m < nsol; ++m)
+        if (sid == solids[m]) sid = -1;
+    for (int added = 0; added < kSolidTries; ++added) {
+        const unsigned long long left = __ballot(sid >= 0);
+        if (!left) break;
+        const int S0 = __shfl(sid, __ffsll((long long)left) - 1);
+        if (sid == S0) sid = -1;
+        if (nsol < kSolidTries) solids[nsol++] = S0;
+        else { solids[spos] = S0; spos = (spos + 1) % kSolidTries; }
+    }
+}
+
 // Solid certificate.  A verified solid s is an open convex prism K (wall
 // planes and roof plane; unbounded below) whose walls and roof above its base
 // height zb are covered by triangles of its facets.  Every segment between the
@@ -521,35 +538,49 @@ __device__ inline bool prod_less(double a, double b, double c, double d) {
 // of facet i or j: those lie outside K by (i).  One lane per corner pair.
 // Plane values are exact FP64 integers in sample units (below 2^51); the
 // interval of t inside K is intersected with exact fraction comparisons.
-__device__ bool certify_solid(const SceneDev &sc, int i, int j, int s) {
-    const int4 R = sc.solid[s];
-    const int np = R.x;
-    const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
-    if (np <= 0 || ni == 0 || nj == 0) return false;
+// Plane value of solid s's face k (k == number of walls: the roof) at a point
+// in sample units; > 0 outside.
+__device__ inline double solid_plane(const SceneDev &sc, int s, const int4 &R, int k, double x, double y, double z) {
+    if (k < R.x) {
+        const int4 pl = sc.splane[s * kSolidMaxPlanes + k];
+        return (double)pl.w * (x - (double)pl.x) - (double)pl.z * (y - (double)pl.y);
+    }
+    return z - (double)R.y;
+}
+
+// Condition (i): each facet's sample hull strictly outside one face plane.
+__device__ bool solid_sides(const SceneDev &sc, int i, int j, int s, const int4 &R) {
     const int lane = lane_id();
-    const bool act = lane < ni * nj;
-    const int a = act ? lane / nj : 0, b = act ? lane - (lane / nj) * nj : 0;
+    const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
     const double u = ldexp(1.0, sc.gs);
-    const float4 P = sc.smp[sc.fhull[kHullMax * i + a]], Q = sc.smp[sc.fhull[kHullMax * j + b]];
-    const double px = P.x * u, py = P.y * u, pz = P.z * u, qx = Q.x * u, qy = Q.y * u, qz = Q.z * u;
-    bool good = pz >= (double)R.z && qz >= (double)R.z;
-    double Ln = 0.0, Ld = 1.0, Un = 1.0, Ud = 1.0;  // t in (Ln / Ld, Un / Ud)
+    const float4 P = sc.smp[sc.fhull[kHullMax * i + (lane < ni ? lane : 0)]];
+    const float4 Q = sc.smp[sc.fhull[kHullMax * j + (lane < nj ? lane : 0)]];
     bool outP = false, outQ = false;
-    for (int k = 0; k <= np; ++k) {
-        double va, vb;
-        if (k < np) {
-            const int4 pl = sc.splane[s * kSolidMaxPlanes + k];
-            va = (double)pl.w * (px - (double)pl.x) - (double)pl.z * (py - (double)pl.y);
-            vb = (double)pl.w * (qx - (double)pl.x) - (double)pl.z * (qy - (double)pl.y);
-        } else {
-            va = pz - (double)R.y;
-            vb = qz - (double)R.y;
-        }
-        outP |= __ballot(act && b == 0 && !(va > 0.0)) == 0ull;
-        outQ |= __ballot(act && a == 0 && !(vb > 0.0)) == 0ull;
-        if (va >= 0.0 && vb >= 0.0) {
-            good = false;
-        } else if (va >= 0.0) {  // enters this half-space at t = va / (va - vb)
+    for (int k = 0; k <= R.x && !(outP && outQ); ++k) {
+        const double va = solid_plane(sc, s, R, k, P.x * u, P.y * u, P.z * u);
+        const double vb = solid_plane(sc, s, R, k, Q.x * u, Q.y * u, Q.z * u);
+        outP |= __ballot(lane < ni && !(va > 0.0)) == 0ull;
+        outQ |= __ballot(lane < nj && !(vb > 0.0)) == 0ull;
+    }
+    return outP && outQ;
+}
+
+// Conditions (ii) and (iii) for one segment: both ends at or above the base and
+// some t in [0, 1] with every plane value negative; also P strictly outside one
+// face plane (implied by (i) for the certificates; it makes the test stand
+// alone for single segments: P is not in the prism, so the entry is at t > 0).
+__device__ bool solid_segment(const SceneDev &sc, int s, const int4 &R, float4 P, float4 Q) {
+    const double u = ldexp(1.0, sc.gs);
+    const double px = P.x * u, py = P.y * u, pz = P.z * u, qx = Q.x * u, qy = Q.y * u, qz = Q.z * u;
+    if (!(pz >= (double)R.z && qz >= (double)R.z)) return false;
+    double Ln = 0.0, Ld = 1.0, Un = 1.0, Ud = 1.0;  // t in (Ln / Ld, Un / Ud)
+    bool pout = false;
+    for (int k = 0; k <= R.x; ++k) {
+        const double va = solid_plane(sc, s, R, k, px, py, pz);
+        const double vb = solid_plane(sc, s, R, k, qx, qy, qz);
+        if (va >= 0.0 && vb >= 0.0) return false;
+        pout |= va > 0.0;
+        if (va >= 0.0) {  // enters this half-space at t = va / (va - vb)
             const double n = va, dd = va - vb;
             if (prod_less(Ln, dd, n, Ld)) { Ln = n; Ld = dd; }
         } else if (vb >= 0.0) {  // leaves it at t = -va / (vb - va)
@@ -557,8 +588,57 @@ __device__ bool certify_solid(const SceneDev &sc, int i, int j, int s) {
             if (prod_less(n, Ud, Un, dd)) { Un = n; Ud = dd; }
         }
     }
-    good = good && prod_less(Ln, Ud, Un, Ld);
-    return outP && outQ && __ballot(act && !good) == 0ull;
+    return pout && prod_less(Ln, Ud, Un, Ld);
+}
+
+// Whole pair: one lane per pair of hull corners (at most 8 x 8).
+__device__ bool certify_solid(const SceneDev &sc, int i, int j, int s) {
+    const int4 R = sc.solid[s];
+    const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
+    if (R.x <= 0 || ni == 0 || nj == 0 || !solid_sides(sc, i, j, s, R)) return false;
+    const int lane = lane_id();
+    const bool act = lane < ni * nj;
+    const int a = act ? lane / nj : 0, b = act ? lane - (lane / nj) * nj : 0;
+    const bool good = solid_segment(sc, s, R, sc.smp[sc.fhull[kHullMax * i + a]], sc.smp[sc.fhull[kHullMax * j + b]]);
+    return __ballot(act && !good) == 0ull;
+}
+
+// Per sub-pair (quadrant clusters, as in certify_subpairs): the cluster hulls
+// lie inside the facet hulls, so (i) carries over; lanes run over the
+// flattened (sub-pair, corner, corner) items.  Returns the certified sub-pairs
+// among `todo`.
+__device__ unsigned certify_solid_subpairs(const SceneDev &sc, int i, int j, int s, unsigned todo,
+                                           unsigned long long *fail) {
+    const int4 R = sc.solid[s];
+    if (R.x <= 0 || !todo || sc.fhull_n[i] == 0 || sc.fhull_n[j] == 0 || !solid_sides(sc, i, j, s, R)) return 0u;
+    const int lane = lane_id();
+    if (lane < 16) fail[lane] = 0ull;
+    wave_sync();
+    int total = 0;
+    for (int sp = 0; sp < 16; ++sp)
+        if ((todo >> sp) & 1u) total += sc.fchull_n[4 * i + (sp >> 2)] * sc.fchull_n[4 * j + (sp & 3)];
+    for (int it = lane; it < total; it += kWave) {
+        int run = 0, sp = 0, hi = 0, hj = 0;
+        for (sp = 0; sp < 16; ++sp) {
+            if (!((todo >> sp) & 1u)) continue;
+            hi = sc.fchull_n[4 * i + (sp >> 2)];
+            hj = sc.fchull_n[4 * j + (sp & 3)];
+            if (it < run + hi * hj) break;
+            run += hi * hj;
+        }
+        const int cp = it - run;
+        const int a = cp / hj, b = cp - (cp / hj) * hj;
+        const float4 P = sc.smp[sc.fchull[(4 * i + (sp >> 2)) * kHullMax + a]];
+        const float4 Q = sc.smp[sc.fchull[(4 * j + (sp & 3)) * kHullMax + b]];
+        if (!solid_segment(sc, s, R, P, Q)) atomicOr(&fail[sp], 1ull);
+    }
+    wave_sync();
+    bool ok = false;
+    if (lane < 16 && ((todo >> lane) & 1u))
+        ok = sc.fchull_n[4 * i + (lane >> 2)] * sc.fchull_n[4 * j + (lane & 3)] > 0 && fail[lane] == 0ull;
+    const unsigned res = (unsigned)(__ballot(ok) & 0xffffull);
+    wave_sync();
+    return res;
 }
 
 // Certificate per sub-pair: the samples of each facet are split into 4
@@ -805,6 +885,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         bool vis = false, done = false, first_traversal = true;
         int cache[kCache];   // wave-uniform list of recent blockers (sorted ranks)
         int ncache = 0, cpos = 0, nmiss = 0;
+        int solids[kSolidTries];  // wave-uniform list of verified solids met by traversals
+        int nsol = 0, sspos = 0;
         for (int base = 0; !done; base += kWave) {
             const bool more = base < nseg;
             if (more) {
@@ -837,6 +919,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                                         c.rechecks))
                                 need = false;
                         }
+                        // then the solids met so far, segment by segment
+                        for (int m = 0; m < nsol && need; ++m)
+                            if (solid_segment(sc, solids[m], sc.solid[solids[m]], P, Q)) need = false;
                     }
                 }
                 const unsigned long long nm = __ballot(need);
@@ -863,6 +948,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     vis = done = true;
                     break;
                 }
+                if (sc.n_solids > 0) remember_solid_ids(sc, solids, nsol, sspos, lane < k, hit);
                 // remember up to kCache distinct new blockers
                 unsigned long long fm = __ballot(lane < k);
                 for (int added = 0; fm && added < kCache; ++added) {
@@ -880,15 +966,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     // the first traversal batch is all blocked: try to prove the whole pair
                     // blocked by the facet that blocked its first lane, then its last lane's
                     // first by the verified solids met by this batch, then by single facets
-                    int sid = (lane < k && sc.n_solids > 0) ? sc.fsolid[__float_as_int(sc.tri[3 * hit].w)] : -1;
                     bool blocked = false;
-                    for (int u = 0; u < kSolidTries && !blocked; ++u) {
-                        const unsigned long long left = __ballot(sid >= 0);
-                        if (!left) break;
-                        const int S0 = __shfl(sid, __ffsll((long long)left) - 1);
-                        if (sid == S0) sid = -1;
-                        blocked = certify_solid(sc, i, j, S0);
-                    }
+                    for (int u = 0; u < nsol && !blocked; ++u) blocked = certify_solid(sc, i, j, solids[u]);
                     if (blocked) {
                         ++nsolid;
                         done = true;
@@ -913,6 +992,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         biggest = max(biggest, pn * qn);
                     }
                     if (biggest >= 2 * kWave) {
+                        for (int u = 0; u < nsol && todo; ++u)
+                            todo &= ~certify_solid_subpairs(sc, i, j, solids[u], todo, sBits[wv]);
+                        if (!todo) {
+                            ++nsolid;
+                            done = true;
+                            break;
+                        }
                         int tried[kCache];
                         int ntried = 0;
                         for (int m = 0; m < ncache && todo; ++m) {
@@ -1197,6 +1283,34 @@ __device__ inline void remember_blockers(int *cache, int &ncache, int &cpos, uns
     }
 }
 
+// Solids that blocked recent segments from the current point X, kept when X is
+// strictly outside one of their face planes (so a segment from X that passes
+// through the prism enters it at 0 < t < 1, see the solid certificate).  A
+// sample's own facet never blocks it: if it is a face of the solid the sample
+// lies on that face plane while X is strictly in front, and the segment stays
+// outside the prism.
+constexpr int kSolidCache = 2;
+
+__device__ inline void remember_solids(const SceneDev &sc, int *scache, int &nsc, int &spos, float4 X, bool blocked,
+                                       int hit) {
+    int sid = blocked ? sc.fsolid[__float_as_int(sc.tri[3 * hit].w)] : -1;
+    for (int m = 0; m < nsc; ++m)
+        if (sid == scache[m]) sid = -1;
+    const double u = ldexp(1.0, sc.gs);
+    for (int added = 0; added < kSolidCache; ++added) {
+        const unsigned long long left = __ballot(sid >= 0);
+        if (!left) break;
+        const int S0 = __shfl(sid, __ffsll((long long)left) - 1);
+        if (sid == S0) sid = -1;
+        const int4 R = sc.solid[S0];
+        bool out = false;
+        for (int k = 0; k <= R.x && !out; ++k) out = solid_plane(sc, S0, R, k, X.x * u, X.y * u, X.z * u) > 0.0;
+        if (!out) continue;
+        if (nsc < kSolidCache) scache[nsc++] = S0;
+        else { scache[spos] = S0; spos = (spos + 1) % kSolidCache; }
+    }
+}
+
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob *many, int n_jobs,
                                                    long long n_items, TraverseOpts o, ivm_stats *st) {
@@ -1217,6 +1331,9 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
     unsigned long long segs = 0, items = 0;
     int cache[kCache];
     int ncache = 0, cpos = 0, nmiss = 0, n_order = 0;
+    int scache[kSolidCache];
+    int nsc = 0, spos = 0;
+    unsigned long long nsolid = 0;
     long long cur = -1;  // current (job, snapshot, side)
     int cur_job = 0;
     float xx = 0.f, xy = 0.f, xz = 0.f;
@@ -1275,6 +1392,8 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             out = (side ? J.rxv : J.txv) + (size_t)n * sc.W;
             ncache = 0;
             cpos = 0;
+            nsc = 0;
+            spos = 0;
             // treelet order for this point: nearest treelet box first (a heuristic only)
             const float xp[3] = {xx, xy, xz};
             const int mode = o.order_mode == IVM_ORDER_LEARNED ? IVM_ORDER_PLAIN : o.order_mode;
@@ -1299,7 +1418,14 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             need = orient(sc.fplane + 6 * f, xx, xy, xz) > 0.0 && !((out[f >> 6] >> (f & 63)) & 1ull);
             if (need) {
                 ++segs;
-                if (ncache > 0) {
+                for (int m = 0; m < nsc && need; ++m) {
+                    const int sid = scache[m];
+                    if (solid_segment(sc, sid, sc.solid[sid], make_float4(xx, xy, xz, 0.f), sc.smp[sidx])) {
+                        need = false;
+                        ++nsolid;
+                    }
+                }
+                if (need && ncache > 0) {
                     const float4 P = sc.smp[sidx];
                     const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
                     for (int k = 0; k < ncache && need; ++k) {
@@ -1330,9 +1456,12 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             wave_sync();
             if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
             remember_blockers(cache, ncache, cpos, __ballot(!clear), hit);
+            if (sc.n_solids > 0) remember_solids(sc, scache, nsc, spos, make_float4(xx, xy, xz, 0.f), !clear, hit);
         }
     }
     flush_counters(st, c, segs, 0, items);
+    nsolid = wave_sum_u64(nsolid);
+    if (st && lane == 0 && nsolid) atomicAdd((unsigned long long *)&st->solid_certified, nsolid);
 }
 
 __global__ __launch_bounds__(kBlock) void k_los(SceneDev sc, int N, const float *tx, const float *rx, uint8_t *los,
