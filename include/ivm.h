@@ -146,8 +146,9 @@ typedef struct ivm_stats {
     uint64_t certified; /* pairs proven blocked by one convex occluder from hull corners */
     uint64_t subpair_runs; /* pairs whose explicit segments were limited to uncertified sub-pairs */
     uint64_t tiled_pairs;  /* pairs decided from a complete near-field tile, without the BVH */
-    uint64_t solid_certified; /* pairs or point bundles proven blocked by one verified solid */
-    uint64_t reserved[2];
+    uint64_t solid_certified; /* pairs proven blocked by verified solids on whole or sub-pair bundles */
+    uint64_t traversed;       /* segments sent to a BVH (or near-field tile) any-hit search */
+    uint64_t solid_segments;  /* segments decided blocked by a verified solid one at a time */
 } ivm_stats;
 
 #define IVM_ORDER_PLAIN 0    /* treelets nearest the pair's segment box first */
@@ -165,12 +166,15 @@ typedef struct ivm_matrix_opts {
                                0 = default 1e-5; values < 1e-5 are raised to 1e-5;
                                +inf sends every test to FP64 */
     int32_t no_tile;        /* 1: never decide a pair from its near-field tile alone */
+    int32_t exhaustive;     /* 1: give every admissible segment its own BVH search: no
+                               blocker caches, no bundle certificates, no near-field
+                               tile (a measurement baseline) */
     hipEvent_t *timing_events; /* optional (NULL = none): two caller-created events the
                                   call records on its stream immediately before and
                                   after its traversal kernel */
 } ivm_matrix_opts;
 
-#define IVM_MAX_STACK 32
+#define IVM_MAX_STACK 24
 
 const char *ivm_status_string(ivm_status s);
 

@@ -31,7 +31,7 @@ IVM_ERR_MODEL = -7
 
 IVM_ORDER_PLAIN, IVM_ORDER_LEARNED, IVM_ORDER_INDEX, IVM_ORDER_REVERSED = 0, 1, 2, 3
 IVM_SCENE_LEARNED = 1
-IVM_MAX_STACK = 32
+IVM_MAX_STACK = 24
 
 EXPORTED = [
     "ivm_status_string", "ivm_scene_workspace_size", "ivm_build_scene", "ivm_scene_status",
@@ -81,13 +81,14 @@ class ivm_matrix_opts(ctypes.Structure):
         ("order_mode", ctypes.c_int32), ("fp64_only", ctypes.c_int32),
         ("stack_depth", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
         ("eps", ctypes.c_float), ("no_tile", ctypes.c_int32),
+        ("exhaustive", ctypes.c_int32),
         ("timing_events", ctypes.c_void_p),
     ]
 
 
 STATS_FIELDS = ["pairs_total", "pairs_candidate", "pairs_visible", "segments", "node_visits",
                 "tri_tests", "rechecks", "fallbacks", "point_items", "flags", "certified",
-                "subpair_runs", "tiled_pairs", "solid_certified"]
+                "subpair_runs", "tiled_pairs", "solid_certified", "traversed", "solid_segments"]
 STATS_WORDS = 16
 
 _lib = None
@@ -183,10 +184,11 @@ def _ptr(t) -> Optional[int]:
 
 def make_opts(order_mode: int = IVM_ORDER_PLAIN, fp64_only: bool = False, stack_depth: int = 0,
               waves_per_cu: int = 0, eps: float = 0.0, timing: Optional["KernelTimer"] = None,
-              no_tile: bool = False) -> ivm_matrix_opts:
+              no_tile: bool = False, exhaustive: bool = False) -> ivm_matrix_opts:
     o = ivm_matrix_opts()
     o.order_mode, o.fp64_only, o.stack_depth = order_mode, int(fp64_only), stack_depth
     o.no_tile = int(no_tile)
+    o.exhaustive = int(exhaustive)
     o.waves_per_cu, o.eps = waves_per_cu, eps
     o.timing_events = timing.array_ptr if timing is not None else None
     return o

@@ -17,7 +17,7 @@ from typing import Dict, List, Optional, Tuple
 from . import GpuScene, ivm_intervisibility_matrix, make_opts
 
 WAVES_PER_CU = (8, 12, 16, 24, 32)
-STACK_DEPTHS = (12, 16, 24, 32)
+STACK_DEPTHS = (12, 16, 20, 24)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ivm_autotune.json")
 
 

@@ -54,7 +54,8 @@ TraverseOpts make_opts(const ivm_matrix_opts *o) {
     if (blocks < 1) blocks = 1;
     t.grid_blocks = (int)blocks;
     t.events = o ? o->timing_events : nullptr;
-    t.no_tile = o ? o->no_tile : 0;
+    t.exhaustive = o ? o->exhaustive : 0;
+    t.no_tile = (o ? o->no_tile : 0) || t.exhaustive;
     return t;
 }
 

@@ -86,7 +86,8 @@ TraverseOpts batch_opts(const ivm_matrix_opts *o) {
     long long blocks = (long long)device_cu_count() * wpc / 4;
     t.grid_blocks = (int)(blocks < 1 ? 1 : blocks);
     t.events = nullptr;  // a captured graph records no caller events
-    t.no_tile = o ? o->no_tile : 0;
+    t.exhaustive = o ? o->exhaustive : 0;
+    t.no_tile = (o ? o->no_tile : 0) || t.exhaustive;
     return t;
 }
 

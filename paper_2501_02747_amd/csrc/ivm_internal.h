@@ -130,6 +130,7 @@ struct TraverseOpts {
     float eps6;                // 6 * eps: margin factor of the FP32 filter
     int grid_blocks;
     int no_tile;               // 1: skip the near-field tile
+    int exhaustive;            // 1: every admissible segment gets its own search
     hipEvent_t *events;        // optional: recorded around the traversal kernel
 };
 

@@ -179,7 +179,7 @@ __device__ inline bool tri_hit(const Seg &s, float4 A, float4 B, float4 C, float
 }
 
 struct Cnt {
-    unsigned visits = 0, tests = 0, rechecks = 0, fallbacks = 0;
+    unsigned visits = 0, tests = 0, rechecks = 0, fallbacks = 0, traversed = 0, solid_segs = 0;
 };
 
 __device__ inline int test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
@@ -427,7 +427,10 @@ __device__ inline void flush_counters(ivm_stats *st, const Cnt &c, unsigned long
     const unsigned long long v = wave_sum_u64(c.visits), t = wave_sum_u64(c.tests);
     const unsigned long long r = wave_sum_u64(c.rechecks), f = wave_sum_u64(c.fallbacks);
     const unsigned long long sg = wave_sum_u64(segs);
+    const unsigned long long tv = wave_sum_u64(c.traversed), ss = wave_sum_u64(c.solid_segs);
     if (lane_id() == 0) {
+        if (tv) atomicAdd((unsigned long long *)&st->traversed, tv);
+        if (ss) atomicAdd((unsigned long long *)&st->solid_segments, ss);
         atomicAdd((unsigned long long *)&st->node_visits, v);
         atomicAdd((unsigned long long *)&st->tri_tests, t);
         atomicAdd((unsigned long long *)&st->rechecks, r);
@@ -460,6 +463,7 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 
 constexpr int kCache = 4;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
+constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time
 
 // Single-occluder certificate.  Let H_i, H_j be the convex hulls of the two
 // sample sets (valid when the samples lie in their facet's plane, checked at
@@ -507,20 +511,7 @@ __device__ inline bool prod_less(double a, double b, double c, double d) {
 
 // Up to kSolidTries distinct verified solids among the blockers `hit` of the
 // lanes with `blocked`, appended to the wave-uniform list (oldest replaced).
-__device__ inline void remember_solid_ids(const SceneDev &sc, int *solids, int &nsol, int &spos, bool blocked,
-                                          int hit) {
-    int sid = blocked ? sc.fsolid[__float_as_int(sc.tri[3 * hit].w)] : -1;
-    for (int m = 0; m < nsol; ++m)
-        if (sid == solids[m]) sid = -1;
-    for (int added = 0; added < kSolidTries; ++added) {
-        const unsigned long long left = __ballot(sid >= 0);
-        if (!left) break;
-        const int S0 = __shfl(sid, __ffsll((long long)left) - 1);
-        if (sid == S0) sid = -1;
-        if (nsol < kSolidTries) solids[nsol++] = S0;
-        else { solids[spos] = S0; spos = (spos + 1) % kSolidTries; }
-    }
-}
+
 
 // Solid certificate.  A verified solid s is an open convex prism K (wall
 // planes and roof plane; unbounded below) whose walls and roof above its base
@@ -538,46 +529,44 @@ __device__ inline void remember_solid_ids(const SceneDev &sc, int *solids, int &
 // of facet i or j: those lie outside K by (i).  One lane per corner pair.
 // Plane values are exact FP64 integers in sample units (below 2^51); the
 // interval of t inside K is intersected with exact fraction comparisons.
-// Plane value of solid s's face k (k == number of walls: the roof) at a point
-// in sample units; > 0 outside.
-__device__ inline double solid_plane(const SceneDev &sc, int s, const int4 &R, int k, double x, double y, double z) {
+// A verified solid staged in LDS: its wall planes, then (at kSolidMaxPlanes)
+// its record (walls, top z, base z, 0), all in sample units.
+struct SolidLds {
+    int4 pl[kSolidMaxPlanes + 1];
+};
+
+// One load round: lane k < kSolidMaxPlanes fetches plane k, the next lane the record.
+__device__ inline void stage_solid(const SceneDev &sc, int s, SolidLds &dst) {
+    const int lane = lane_id();
+    if (lane < kSolidMaxPlanes) dst.pl[lane] = sc.splane[s * kSolidMaxPlanes + lane];
+    else if (lane == kSolidMaxPlanes) dst.pl[kSolidMaxPlanes] = sc.solid[s];
+    wave_sync();
+}
+
+// Plane value of face k (k == number of walls: the roof) at a point in sample
+// units; > 0 outside.
+__device__ inline double solid_plane(const SolidLds &S, int k, double x, double y, double z) {
+    const int4 R = S.pl[kSolidMaxPlanes];
     if (k < R.x) {
-        const int4 pl = sc.splane[s * kSolidMaxPlanes + k];
-        return (double)pl.w * (x - (double)pl.x) - (double)pl.z * (y - (double)pl.y);
+        const int4 p = S.pl[k];
+        return (double)p.w * (x - (double)p.x) - (double)p.z * (y - (double)p.y);
     }
     return z - (double)R.y;
 }
 
-// Condition (i): each facet's sample hull strictly outside one face plane.
-__device__ bool solid_sides(const SceneDev &sc, int i, int j, int s, const int4 &R) {
-    const int lane = lane_id();
-    const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
-    const double u = ldexp(1.0, sc.gs);
-    const float4 P = sc.smp[sc.fhull[kHullMax * i + (lane < ni ? lane : 0)]];
-    const float4 Q = sc.smp[sc.fhull[kHullMax * j + (lane < nj ? lane : 0)]];
-    bool outP = false, outQ = false;
-    for (int k = 0; k <= R.x && !(outP && outQ); ++k) {
-        const double va = solid_plane(sc, s, R, k, P.x * u, P.y * u, P.z * u);
-        const double vb = solid_plane(sc, s, R, k, Q.x * u, Q.y * u, Q.z * u);
-        outP |= __ballot(lane < ni && !(va > 0.0)) == 0ull;
-        outQ |= __ballot(lane < nj && !(vb > 0.0)) == 0ull;
-    }
-    return outP && outQ;
-}
-
-// Conditions (ii) and (iii) for one segment: both ends at or above the base and
-// some t in [0, 1] with every plane value negative; also P strictly outside one
-// face plane (implied by (i) for the certificates; it makes the test stand
-// alone for single segments: P is not in the prism, so the entry is at t > 0).
-__device__ bool solid_segment(const SceneDev &sc, int s, const int4 &R, float4 P, float4 Q) {
-    const double u = ldexp(1.0, sc.gs);
-    const double px = P.x * u, py = P.y * u, pz = P.z * u, qx = Q.x * u, qy = Q.y * u, qz = Q.z * u;
+// Conditions (ii) and (iii) for one segment (ends in sample units): both ends
+// at or above the base and some t in [0, 1] with every plane value negative;
+// also P strictly outside one face plane (implied by (i) for the certificates;
+// it makes the test stand alone for single segments: P is not in the prism,
+// so the entry is at t > 0).
+__device__ bool solid_segment(const SolidLds &S, double px, double py, double pz, double qx, double qy, double qz) {
+    const int4 R = S.pl[kSolidMaxPlanes];
     if (!(pz >= (double)R.z && qz >= (double)R.z)) return false;
     double Ln = 0.0, Ld = 1.0, Un = 1.0, Ud = 1.0;  // t in (Ln / Ld, Un / Ud)
     bool pout = false;
     for (int k = 0; k <= R.x; ++k) {
-        const double va = solid_plane(sc, s, R, k, px, py, pz);
-        const double vb = solid_plane(sc, s, R, k, qx, qy, qz);
+        const double va = solid_plane(S, k, px, py, pz);
+        const double vb = solid_plane(S, k, qx, qy, qz);
         if (va >= 0.0 && vb >= 0.0) return false;
         pout |= va > 0.0;
         if (va >= 0.0) {  // enters this half-space at t = va / (va - vb)
@@ -591,15 +580,58 @@ __device__ bool solid_segment(const SceneDev &sc, int s, const int4 &R, float4 P
     return pout && prod_less(Ln, Ud, Un, Ld);
 }
 
+__device__ inline bool solid_segment(const SolidLds &S, float4 P, float4 Q, double u) {
+    return solid_segment(S, P.x * u, P.y * u, P.z * u, Q.x * u, Q.y * u, Q.z * u);
+}
+
+// The sample hulls of a pair staged in LDS: hc[0, 8) facet i, hc[8, 16) facet j;
+// cc[(side * 4 + cluster) * kHullMax + k] the cluster hulls, ccn their sizes.
+struct HullLds {
+    float4 hc[2 * kHullMax];
+    float4 cc[8 * kHullMax];
+    int ccn[8];
+    int ni, nj;
+};
+
+__device__ inline void stage_hulls(const SceneDev &sc, int i, int j, HullLds &H) {
+    const int lane = lane_id();
+    const int side = lane >> 5, cl = (lane >> 3) & 3, k = lane & 7, f = side ? j : i;
+    const int n = sc.fchull_n[4 * f + cl];
+    const int hn = sc.fhull_n[f];
+    const int ci = k < n ? sc.fchull[(4 * f + cl) * kHullMax + k] : -1;
+    const int hi = (cl == 0 && k < hn) ? sc.fhull[kHullMax * f + k] : -1;
+    if (ci >= 0) H.cc[(side * 4 + cl) * kHullMax + k] = sc.smp[ci];
+    if (hi >= 0) H.hc[side * kHullMax + k] = sc.smp[hi];
+    if (k == 0) H.ccn[side * 4 + cl] = n;
+    if (lane == 0) H.ni = hn;
+    if (lane == 32) H.nj = hn;
+    wave_sync();
+}
+
+// Condition (i): each facet's sample hull strictly outside one face plane.
+__device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u) {
+    const int lane = lane_id();
+    const int ni = H.ni, nj = H.nj;
+    const float4 P = H.hc[lane < ni ? lane : 0], Q = H.hc[kHullMax + (lane < nj ? lane : 0)];
+    const int np = S.pl[kSolidMaxPlanes].x;
+    bool outP = false, outQ = false;
+    for (int k = 0; k <= np && !(outP && outQ); ++k) {
+        const double va = solid_plane(S, k, P.x * u, P.y * u, P.z * u);
+        const double vb = solid_plane(S, k, Q.x * u, Q.y * u, Q.z * u);
+        outP |= __ballot(lane < ni && !(va > 0.0)) == 0ull;
+        outQ |= __ballot(lane < nj && !(vb > 0.0)) == 0ull;
+    }
+    return outP && outQ;
+}
+
 // Whole pair: one lane per pair of hull corners (at most 8 x 8).
-__device__ bool certify_solid(const SceneDev &sc, int i, int j, int s) {
-    const int4 R = sc.solid[s];
-    const int ni = sc.fhull_n[i], nj = sc.fhull_n[j];
-    if (R.x <= 0 || ni == 0 || nj == 0 || !solid_sides(sc, i, j, s, R)) return false;
+__device__ bool certify_solid(const SolidLds &S, const HullLds &H, double u) {
+    const int ni = H.ni, nj = H.nj;
+    if (S.pl[kSolidMaxPlanes].x <= 0 || ni == 0 || nj == 0 || !solid_sides(S, H, u)) return false;
     const int lane = lane_id();
     const bool act = lane < ni * nj;
     const int a = act ? lane / nj : 0, b = act ? lane - (lane / nj) * nj : 0;
-    const bool good = solid_segment(sc, s, R, sc.smp[sc.fhull[kHullMax * i + a]], sc.smp[sc.fhull[kHullMax * j + b]]);
+    const bool good = solid_segment(S, H.hc[a], H.hc[kHullMax + b], u);
     return __ballot(act && !good) == 0ull;
 }
 
@@ -607,38 +639,56 @@ __device__ bool certify_solid(const SceneDev &sc, int i, int j, int s) {
 // lie inside the facet hulls, so (i) carries over; lanes run over the
 // flattened (sub-pair, corner, corner) items.  Returns the certified sub-pairs
 // among `todo`.
-__device__ unsigned certify_solid_subpairs(const SceneDev &sc, int i, int j, int s, unsigned todo,
+__device__ unsigned certify_solid_subpairs(const SolidLds &S, const HullLds &H, double u, unsigned todo,
                                            unsigned long long *fail) {
-    const int4 R = sc.solid[s];
-    if (R.x <= 0 || !todo || sc.fhull_n[i] == 0 || sc.fhull_n[j] == 0 || !solid_sides(sc, i, j, s, R)) return 0u;
+    if (S.pl[kSolidMaxPlanes].x <= 0 || !todo || H.ni == 0 || H.nj == 0 || !solid_sides(S, H, u)) return 0u;
     const int lane = lane_id();
     if (lane < 16) fail[lane] = 0ull;
     wave_sync();
     int total = 0;
     for (int sp = 0; sp < 16; ++sp)
-        if ((todo >> sp) & 1u) total += sc.fchull_n[4 * i + (sp >> 2)] * sc.fchull_n[4 * j + (sp & 3)];
+        if ((todo >> sp) & 1u) total += H.ccn[sp >> 2] * H.ccn[4 + (sp & 3)];
     for (int it = lane; it < total; it += kWave) {
         int run = 0, sp = 0, hi = 0, hj = 0;
         for (sp = 0; sp < 16; ++sp) {
             if (!((todo >> sp) & 1u)) continue;
-            hi = sc.fchull_n[4 * i + (sp >> 2)];
-            hj = sc.fchull_n[4 * j + (sp & 3)];
+            hi = H.ccn[sp >> 2];
+            hj = H.ccn[4 + (sp & 3)];
             if (it < run + hi * hj) break;
             run += hi * hj;
         }
         const int cp = it - run;
         const int a = cp / hj, b = cp - (cp / hj) * hj;
-        const float4 P = sc.smp[sc.fchull[(4 * i + (sp >> 2)) * kHullMax + a]];
-        const float4 Q = sc.smp[sc.fchull[(4 * j + (sp & 3)) * kHullMax + b]];
-        if (!solid_segment(sc, s, R, P, Q)) atomicOr(&fail[sp], 1ull);
+        if (!solid_segment(S, H.cc[(sp >> 2) * kHullMax + a], H.cc[(4 + (sp & 3)) * kHullMax + b], u))
+            atomicOr(&fail[sp], 1ull);
     }
     wave_sync();
     bool ok = false;
-    if (lane < 16 && ((todo >> lane) & 1u))
-        ok = sc.fchull_n[4 * i + (lane >> 2)] * sc.fchull_n[4 * j + (lane & 3)] > 0 && fail[lane] == 0ull;
+    if (lane < 16 && ((todo >> lane) & 1u)) ok = H.ccn[lane >> 2] * H.ccn[4 + (lane & 3)] > 0 && fail[lane] == 0ull;
     const unsigned res = (unsigned)(__ballot(ok) & 0xffffull);
     wave_sync();
     return res;
+}
+
+// Up to kSolidTries distinct verified solids among the blockers `hit` of the
+// lanes with `blocked`, appended to the wave-uniform list (oldest replaced) and
+// staged in LDS.
+__device__ inline void remember_solid_ids(const SceneDev &sc, int *solids, int &nsol, int &spos, SolidLds *lds,
+                                          int cap, bool blocked, int hit) {
+    int sid = blocked ? sc.fsolid[__float_as_int(sc.tri[3 * hit].w)] : -1;
+    for (int m = 0; m < nsol; ++m)
+        if (sid == solids[m]) sid = -1;
+    for (int added = 0; added < cap; ++added) {
+        const unsigned long long left = __ballot(sid >= 0);
+        if (!left) break;
+        const int S0 = __shfl(sid, __ffsll((long long)left) - 1);
+        if (sid == S0) sid = -1;
+        int slot;
+        if (nsol < cap) slot = nsol++;
+        else { slot = spos; spos = (spos + 1) % cap; }
+        solids[slot] = S0;
+        stage_solid(sc, S0, lds[slot]);
+    }
 }
 
 // Certificate per sub-pair: the samples of each facet are split into 4
@@ -785,6 +835,27 @@ struct Rects {
     int pa[16], pn[16], qb[16], qn[16], pre[17];
 };
 
+// Segment space of the sub-pairs in `todo`: sub-pair (ci, cj) covers the
+// admissible samples of cluster ci of i (sP[pco[ci], pco[ci + 1])) times those
+// of cluster cj of j.  Written by lane 0.
+__device__ inline void set_rects(Rects &R, unsigned todo, const int *pco, const int *qco) {
+    if (lane_id() != 0) return;
+    int nr = 0, run = 0;
+    for (int sp = 0; sp < 16; ++sp) {
+        if (!((todo >> sp) & 1u)) continue;
+        const int ci = sp >> 2, cj = sp & 3;
+        R.pa[nr] = pco[ci];
+        R.pn[nr] = pco[ci + 1] - pco[ci];
+        R.qb[nr] = qco[cj];
+        R.qn[nr] = qco[cj + 1] - qco[cj];
+        R.pre[nr] = run;
+        run += R.pn[nr] * R.qn[nr];
+        ++nr;
+    }
+    R.pre[nr] = run;
+    R.n = nr;
+}
+
 // MULTI: the queue index runs over the concatenated candidates of n_jobs scenes
 // (base[] = exclusive prefix of their candidate totals); otherwise over `one`.
 template <bool MULTI>
@@ -801,6 +872,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     __shared__ Rects sR[kWavesPerBlock];
     __shared__ int sTile[kWavesPerBlock][kTile];
     __shared__ int sTileCnt[kWavesPerBlock][4];
+    __shared__ SolidLds sSL[kWavesPerBlock][kSolidTries];
+    __shared__ HullLds sH[kWavesPerBlock];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t total = MULTI ? base[n_jobs] : one.prefix[one.n_items];
     int *stk = &sStack[wv][lane];
@@ -810,11 +883,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     Cnt c;
     unsigned segs = 0, nvis = 0, ncert = 0, nsub = 0, ntiled = 0, nsolid = 0;  // per-wave counts fit 32 bits
     const unsigned long long lt = (1ull << lane) - 1ull;
+    // A wave takes kPairChunk consecutive candidates at a time (same facet i,
+    // neighbouring j), and keeps its recent blocker triangles and solids from
+    // one pair to the next within a scene.
+    int cache[kCache];        // wave-uniform list of recent blockers (sorted ranks)
+    int ncache = 0, cpos = 0;
+    int solids[kSolidTries];  // wave-uniform list of verified solids met by traversals
+    int nsol = 0, sspos = 0;
+    int cur_js = -1;
+    uint32_t g_next = 0, g_end = 0;
     while (true) {
-        uint32_t g = 0;
-        if (lane == 0) g = atomicAdd(queue, 1u);
-        g = __shfl(g, 0);
-        if (g >= total) break;
+        if (g_next >= g_end) {
+            uint32_t g0 = 0;
+            if (lane == 0) g0 = atomicAdd(queue, (uint32_t)kPairChunk);
+            g0 = __shfl(g0, 0);
+            if (g0 >= total) break;
+            g_next = g0;
+            g_end = min(total, g0 + (uint32_t)kPairChunk);
+        }
+        const uint32_t g = g_next++;
         int js = 0;
         uint32_t gl = g;
         if (MULTI) {
@@ -829,6 +916,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         const PairJob &J = MULTI ? many[js] : one;
         const SceneDev &sc = J.sc;
+        if (js != cur_js) {
+            cur_js = js;
+            ncache = cpos = nsol = sspos = 0;
+        }
         int i, j;
         decode_pair(sc, J.cand, J.prefix, J.n_items, gl, i, j);
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
@@ -865,6 +956,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             lo[0] = wave_min(l0); lo[1] = wave_min(l1); lo[2] = wave_min(l2);
             hi[0] = wave_max(h0); hi[1] = wave_max(h1); hi[2] = wave_max(h2);
         }
+        // the solids that blocked the previous pairs first: a whole-pair certificate
+        // costs far less than one traversal batch
+        // sub-pairs (quadrant clusters) with admissible samples on both sides
+        unsigned todo = 0u;
+        int biggest = 0;
+        for (int sp = 0; sp < 16; ++sp) {
+            const int pn = pco[(sp >> 2) + 1] - pco[sp >> 2], qn = qco[(sp & 3) + 1] - qco[sp & 3];
+            if (pn > 0 && qn > 0) todo |= 1u << sp;
+            biggest = max(biggest, pn * qn);
+        }
+        const unsigned all_sub = todo;
+        const bool split = biggest >= 2 * kWave;  // sub-pairs worth certifying one by one
+        const double gsu = ldexp(1.0, sc.gs);  // metres -> sample units (exact)
+        bool hulls = false;                    // sample hulls staged in LDS for this pair
+        bool early = false;
+        if (!o.exhaustive && nsol > 0) {
+            stage_hulls(sc, i, j, sH[wv]);
+            hulls = true;
+            for (int m = 0; m < nsol && !early; ++m) early = certify_solid(sSL[wv][m], sH[wv], gsu);
+            for (int m = 0; m < nsol && !early && split; ++m) {
+                todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv]);
+                early = todo == 0u;
+            }
+        }
+        if (early) {
+            ++nsolid;
+            continue;
+        }
         unsigned long long lcode = 0;
         if (o.order_mode == IVM_ORDER_LEARNED && J.learned) lcode = J.learned[gl];
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
@@ -874,19 +993,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                               ? -1
                               : gather_tile(sc, i, j, lo, hi, sOrder[wv], n_order, sMiss[wv], sTile[wv], sTileCnt[wv]);
         ntiled += ntile >= 0;
-        // phase 0: the whole product space, until the first traversal batch
-        if (lane == 0) {
+        // the segment space: the whole product (one rectangle, spread order over
+        // all of it) unless some sub-pairs are already certified
+        if (todo != all_sub) {
+            set_rects(R, todo, pco, qco);
+            ++nsub;
+        } else if (lane == 0) {
             R.n = 1;
             R.pa[0] = 0; R.pn[0] = np; R.qb[0] = 0; R.qn[0] = nq;
             R.pre[0] = 0; R.pre[1] = np * nq;
         }
         wave_sync();
-        int nseg = np * nq;
+        int nseg = R.pre[R.n];
         bool vis = false, done = false, first_traversal = true;
-        int cache[kCache];   // wave-uniform list of recent blockers (sorted ranks)
-        int ncache = 0, cpos = 0, nmiss = 0;
-        int solids[kSolidTries];  // wave-uniform list of verified solids met by traversals
-        int nsol = 0, sspos = 0;
+        int nmiss = 0;
         for (int base = 0; !done; base += kWave) {
             const bool more = base < nseg;
             if (more) {
@@ -909,11 +1029,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     ab = a | (b << 8);
                     ++segs;
                     need = true;
-                    if (ncache > 0) {
+                    if (ncache > 0 && !o.exhaustive) {
                         const float4 P = sP[wv][a], Q = sQ[wv][b];
                         const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
                         for (int m = 0; m < ncache && need; ++m) {
                             const int r = cache[m];
+                            const int fr = __float_as_int(sc.tri[3 * r].w);
+                            if (fr == i || fr == j) continue;  // kept from another pair
                             ++c.tests;
                             if (tri_hit(sg, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], o.eps6, f64,
                                         c.rechecks))
@@ -921,7 +1043,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         }
                         // then the solids met so far, segment by segment
                         for (int m = 0; m < nsol && need; ++m)
-                            if (solid_segment(sc, solids[m], sc.solid[solids[m]], P, Q)) need = false;
+                            if (solid_segment(sSL[wv][m], P, Q, gsu)) {
+                                need = false;
+                                ++c.solid_segs;
+                            }
                     }
                 }
                 const unsigned long long nm = __ballot(need);
@@ -938,6 +1063,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     const int ab = miss[nmiss - k + lane];
                     const float4 P = sP[wv][ab & 255], Q = sQ[wv][ab >> 8];
                     const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+                    ++c.traversed;
                     hit = ntile >= 0 ? tile_hit(sc, sg, sTile[wv], ntile, o.eps6, f64, c)
                                      : any_hit(sc, sg, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
                     clear = hit < 0;
@@ -948,7 +1074,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     vis = done = true;
                     break;
                 }
-                if (sc.n_solids > 0) remember_solid_ids(sc, solids, nsol, sspos, lane < k, hit);
+                if (sc.n_solids > 0) remember_solid_ids(sc, solids, nsol, sspos, sSL[wv], kSolidTries, lane < k, hit);
                 // remember up to kCache distinct new blockers
                 unsigned long long fm = __ballot(lane < k);
                 for (int added = 0; fm && added < kCache; ++added) {
@@ -961,13 +1087,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     if (ncache < kCache) cache[ncache++] = r;
                     else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
                 }
-                if (first_traversal && nseg > kWave) {
+                if (first_traversal && nseg > kWave && !o.exhaustive) {
                     first_traversal = false;
                     // the first traversal batch is all blocked: try to prove the whole pair
                     // blocked by the facet that blocked its first lane, then its last lane's
                     // first by the verified solids met by this batch, then by single facets
                     bool blocked = false;
-                    for (int u = 0; u < nsol && !blocked; ++u) blocked = certify_solid(sc, i, j, solids[u]);
+                    if (nsol > 0 && !hulls) {
+                        stage_hulls(sc, i, j, sH[wv]);
+                        hulls = true;
+                    }
+                    for (int m = 0; m < nsol && !blocked; ++m) blocked = certify_solid(sSL[wv][m], sH[wv], gsu);
                     if (blocked) {
                         ++nsolid;
                         done = true;
@@ -982,18 +1112,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         done = true;
                         break;
                     }
-                    // then sub-pair by sub-pair with every facet seen blocking so far; the
-                    // uncertified sub-pairs become the new segment space
-                    unsigned todo = 0u;
-                    int biggest = 0;
-                    for (int sp = 0; sp < 16; ++sp) {
-                        const int pn = pco[(sp >> 2) + 1] - pco[sp >> 2], qn = qco[(sp & 3) + 1] - qco[sp & 3];
-                        if (pn > 0 && qn > 0) todo |= 1u << sp;
-                        biggest = max(biggest, pn * qn);
-                    }
-                    if (biggest >= 2 * kWave) {
-                        for (int u = 0; u < nsol && todo; ++u)
-                            todo &= ~certify_solid_subpairs(sc, i, j, solids[u], todo, sBits[wv]);
+                    // then sub-pair by sub-pair with every solid and facet seen blocking so
+                    // far; the uncertified sub-pairs become the new segment space
+                    if (split) {
+                        const unsigned before = todo;
+                        for (int m = 0; m < nsol && todo; ++m)
+                            todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv]);
                         if (!todo) {
                             ++nsolid;
                             done = true;
@@ -1014,28 +1138,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                             done = true;
                             break;
                         }
-                        ++nsub;
-                        if (lane == 0) {
-                            int nr = 0, run = 0;
-                            for (int sp = 0; sp < 16; ++sp) {
-                                if (!((todo >> sp) & 1u)) continue;
-                                const int ci = sp >> 2, cj = sp & 3;
-                                R.pa[nr] = pco[ci];
-                                R.pn[nr] = pco[ci + 1] - pco[ci];
-                                R.qb[nr] = qco[cj];
-                                R.qn[nr] = qco[cj + 1] - qco[cj];
-                                R.pre[nr] = run;
-                                run += R.pn[nr] * R.qn[nr];
-                                ++nr;
-                            }
-                            R.pre[nr] = run;
-                            R.n = nr;
+                        if (todo != before) {
+                            if (before == all_sub) ++nsub;
+                            set_rects(R, todo, pco, qco);
+                            wave_sync();
+                            nseg = R.pre[R.n];
+                            base = -kWave;  // restart the cache passes over the new space
+                            nmiss = 0;
+                            break;
                         }
-                        wave_sync();
-                        nseg = R.pre[R.n];
-                        base = -kWave;  // restart the cache passes over the new space
-                        nmiss = 0;
-                        break;
                     }
                 }
             }
@@ -1283,33 +1394,13 @@ __device__ inline void remember_blockers(int *cache, int &ncache, int &cpos, uns
     }
 }
 
-// Solids that blocked recent segments from the current point X, kept when X is
-// strictly outside one of their face planes (so a segment from X that passes
-// through the prism enters it at 0 < t < 1, see the solid certificate).  A
-// sample's own facet never blocks it: if it is a face of the solid the sample
-// lies on that face plane while X is strictly in front, and the segment stays
-// outside the prism.
+// Solids that blocked recent segments from the current point X, staged in LDS
+// and tested segment by segment (X strictly outside one face plane, so a
+// segment from X that passes through the prism enters it at 0 < t < 1, see the
+// solid certificate).  A sample's own facet never blocks it: if it is a face of
+// the solid the sample lies on that face plane while X is strictly in front,
+// and the segment stays outside the prism.
 constexpr int kSolidCache = 2;
-
-__device__ inline void remember_solids(const SceneDev &sc, int *scache, int &nsc, int &spos, float4 X, bool blocked,
-                                       int hit) {
-    int sid = blocked ? sc.fsolid[__float_as_int(sc.tri[3 * hit].w)] : -1;
-    for (int m = 0; m < nsc; ++m)
-        if (sid == scache[m]) sid = -1;
-    const double u = ldexp(1.0, sc.gs);
-    for (int added = 0; added < kSolidCache; ++added) {
-        const unsigned long long left = __ballot(sid >= 0);
-        if (!left) break;
-        const int S0 = __shfl(sid, __ffsll((long long)left) - 1);
-        if (sid == S0) sid = -1;
-        const int4 R = sc.solid[S0];
-        bool out = false;
-        for (int k = 0; k <= R.x && !out; ++k) out = solid_plane(sc, S0, R, k, X.x * u, X.y * u, X.z * u) > 0.0;
-        if (!out) continue;
-        if (nsc < kSolidCache) scache[nsc++] = S0;
-        else { scache[spos] = S0; spos = (spos + 1) % kSolidCache; }
-    }
-}
 
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob *many, int n_jobs,
@@ -1318,6 +1409,7 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
     __shared__ int sMiss[kWavesPerBlock][2 * kWave];
+    __shared__ SolidLds sSL[kWavesPerBlock][kSolidCache];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
@@ -1333,7 +1425,6 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
     int ncache = 0, cpos = 0, nmiss = 0, n_order = 0;
     int scache[kSolidCache];
     int nsc = 0, spos = 0;
-    unsigned long long nsolid = 0;
     long long cur = -1;  // current (job, snapshot, side)
     int cur_job = 0;
     float xx = 0.f, xy = 0.f, xz = 0.f;
@@ -1372,6 +1463,7 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
                 f = CJ.sc.sfacet[sidx];
                 const float4 P = CJ.sc.smp[sidx];
                 const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+                ++c.traversed;
                 hit = any_hit(CJ.sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
                 clear = hit < 0;
             }
@@ -1418,14 +1510,13 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             need = orient(sc.fplane + 6 * f, xx, xy, xz) > 0.0 && !((out[f >> 6] >> (f & 63)) & 1ull);
             if (need) {
                 ++segs;
-                for (int m = 0; m < nsc && need; ++m) {
-                    const int sid = scache[m];
-                    if (solid_segment(sc, sid, sc.solid[sid], make_float4(xx, xy, xz, 0.f), sc.smp[sidx])) {
+                for (int m = 0; m < nsc && need && !o.exhaustive; ++m) {
+                    if (solid_segment(sSL[wv][m], make_float4(xx, xy, xz, 0.f), sc.smp[sidx], ldexp(1.0, sc.gs))) {
                         need = false;
-                        ++nsolid;
+                        ++c.solid_segs;
                     }
                 }
-                if (need && ncache > 0) {
+                if (need && ncache > 0 && !o.exhaustive) {
                     const float4 P = sc.smp[sidx];
                     const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
                     for (int k = 0; k < ncache && need; ++k) {
@@ -1450,18 +1541,17 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             const int f = sc.sfacet[s2];
             const float4 P = sc.smp[s2];
             const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+            ++c.traversed;
             const int hit = any_hit(sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
             const bool clear = hit < 0;
             nmiss -= k;
             wave_sync();
             if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
             remember_blockers(cache, ncache, cpos, __ballot(!clear), hit);
-            if (sc.n_solids > 0) remember_solids(sc, scache, nsc, spos, make_float4(xx, xy, xz, 0.f), !clear, hit);
+            if (sc.n_solids > 0) remember_solid_ids(sc, scache, nsc, spos, sSL[wv], kSolidCache, !clear, hit);
         }
     }
     flush_counters(st, c, segs, 0, items);
-    nsolid = wave_sum_u64(nsolid);
-    if (st && lane == 0 && nsolid) atomicAdd((unsigned long long *)&st->solid_certified, nsolid);
 }
 
 __global__ __launch_bounds__(kBlock) void k_los(SceneDev sc, int N, const float *tx, const float *rx, uint8_t *los,

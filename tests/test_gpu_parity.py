@@ -106,23 +106,26 @@ def test_urban_grid_medium_full_parity(oracle_mod, ivm, nx, ny):
     assert (out["counts"].cpu().numpy() == co).all()
 
 
-@pytest.mark.parametrize("mode,fp64,stack,eps,no_tile", [
-    ("index", False, 0, 0.0, False), ("reversed", False, 0, 0.0, False), ("plain", False, 2, 0.0, True),
-    ("plain", False, 3, 0.0, False), ("plain", False, 0, float("inf"), False), ("plain", True, 2, 0.0, True),
-    ("plain", False, 0, 1e-2, False), ("index", False, 0, 0.0, True), ("plain", False, 0, float("inf"), True),
+@pytest.mark.parametrize("mode,fp64,stack,eps,no_tile,exh", [
+    ("index", False, 0, 0.0, False, False), ("reversed", False, 0, 0.0, False, False),
+    ("plain", False, 2, 0.0, True, True), ("plain", False, 3, 0.0, False, False),
+    ("plain", False, 0, float("inf"), False, False), ("plain", True, 2, 0.0, True, True),
+    ("plain", False, 0, 1e-2, False, False), ("index", False, 0, 0.0, True, False),
+    ("plain", False, 0, float("inf"), True, False), ("plain", False, 0, 0.0, False, True),
 ])
-def test_result_independent_of_options(oracle_mod, ivm, mode, fp64, stack, eps, no_tile):
-    """Treelet order, FP64-only mode, a tiny stack (forces the linear-scan fallback),
-    the filter margin (inf sends every test to FP64) and the near-field tile never
+def test_result_independent_of_options(oracle_mod, ivm, mode, fp64, stack, eps, no_tile, exh):
+    """Treelet order, FP64-only mode, a tiny stack (forces the linear-scan fallback;
+    run exhaustively so that every segment is searched), the filter margin (inf
+    sends every test to FP64), the near-field tile and the exhaustive mode never
     change a bit."""
     import torch
-    _log(f"[options] {mode} fp64={fp64} stack={stack} eps={eps} no_tile={no_tile}")
+    _log(f"[options] {mode} fp64={fp64} stack={stack} eps={eps} no_tile={no_tile} exhaustive={exh}")
     s = sg.gen_c2(5, n_snap=8, nx=4, ny=3)
     orc = oracle_mod.Oracle(s)
     Mo, _ = orc.matrix()
     tvo, rvo, loso = orc.txrx(s.tx, s.rx)
     m = {"plain": ivm.IVM_ORDER_PLAIN, "index": ivm.IVM_ORDER_INDEX, "reversed": ivm.IVM_ORDER_REVERSED}[mode]
-    opts = ivm.make_opts(order_mode=m, fp64_only=fp64, stack_depth=stack, eps=eps, no_tile=no_tile)
+    opts = ivm.make_opts(order_mode=m, fp64_only=fp64, stack_depth=stack, eps=eps, no_tile=no_tile, exhaustive=exh)
     st, stp = ivm.new_stats(), ivm.new_stats()
     g = ivm.GpuScene.from_scene(s).check()
     M = ivm.ivm_intervisibility_matrix(g, opts, stats=st)
@@ -139,8 +142,11 @@ def test_result_independent_of_options(oracle_mod, ivm, mode, fp64, stack, eps, 
     dp = ivm.stats_dict(stp)
     if stack == 2:
         assert d["fallbacks"] > 0, "a 2-deep stack must overflow and take the linear-scan path"
-    if no_tile:
+    if no_tile or exh:
         assert d["tiled_pairs"] == 0
+    if exh:
+        assert d["certified"] == d["solid_certified"] == d["solid_segments"] == dp["solid_segments"] == 0
+        assert 0 < d["traversed"] <= d["segments"] and 0 < dp["traversed"] <= dp["segments"]
     if eps == float("inf") and not fp64:
         assert d["rechecks"] >= d["tri_tests"] // 2, "eps=inf sends every traversal test to FP64"
 
