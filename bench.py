@@ -30,8 +30,16 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic work per counted unit (VALU lane-ops): a node visit tests two child
 # boxes (2 x 14), a segment/triangle test ~43 (Moller-Trumbore 33 + filter 10),
-# an FP64 recheck ~35 more.
-OPS_NODE, OPS_TRI, OPS_RECHECK = 28, 43, 35
+# an FP64 recheck ~35 more, one face-plane step of an exact solid test ~25 FP64
+# ops (two plane values, the interval update with an exact product compare;
+# MI355X issues FP64 vector ops at one per lane per clock, the rate the peak
+# below counts).
+OPS_NODE, OPS_TRI, OPS_RECHECK, OPS_SOLID_PLANE = 28, 43, 35, 25
+
+
+def lane_ops(st: dict) -> int:
+    return (st["node_visits"] * OPS_NODE + st["tri_tests"] * OPS_TRI + st["rechecks"] * OPS_RECHECK
+            + st["solid_planes"] * OPS_SOLID_PLANE)
 
 WORKLOADS = {
     "c1": "tiny urban 200x200 m, 8 boxes, 42 facets / 84 tris, 4x4 samples, 10 snapshots",
@@ -180,7 +188,7 @@ def run_batched(args, ivm, torch, sg):
     progress(f"timed {args.steps} graph runs: {ms:.2f} ms each")
     n_pairs = int((F * (F - 1) // 2).sum())
     sd = {k: v // args.steps for k, v in ivm.stats_dict(st).items()}
-    ops = sd["node_visits"] * OPS_NODE + sd["tri_tests"] * OPS_TRI + sd["rechecks"] * OPS_RECHECK
+    ops = lane_ops(sd)
     ach = ops / (ms / 1e3) / 1e12
     out = {
         "metric": "facet-pair vis queries/s + Tx/Rx table ms/snapshot, learned vs plain, bit-exact",
@@ -322,8 +330,8 @@ def main():
     sm, sp = ivm.stats_dict(st_m), ivm.stats_dict(st_p)
     n_pairs = F * (F - 1) // 2
     value = n_pairs / (med["matrix"] / 1e3)
-    ops_pairs = sm["node_visits"] * OPS_NODE + sm["tri_tests"] * OPS_TRI + sm["rechecks"] * OPS_RECHECK
-    ops_points = sp["node_visits"] * OPS_NODE + sp["tri_tests"] * OPS_TRI + sp["rechecks"] * OPS_RECHECK
+    ops_pairs = lane_ops(sm)
+    ops_points = lane_ops(sp)
     ach = ops_pairs / (pairs_kernel_ms / 1e3) / 1e12
     ach_p = ops_points / (points_kernel_ms / 1e3) / 1e12
     out = {

@@ -149,6 +149,8 @@ typedef struct ivm_stats {
     uint64_t solid_certified; /* pairs proven blocked by verified solids on whole or sub-pair bundles */
     uint64_t traversed;       /* segments sent to a BVH (or near-field tile) any-hit search */
     uint64_t solid_segments;  /* segments decided blocked by a verified solid one at a time */
+    uint64_t solid_planes;    /* segment x face-plane steps of solid tests (certificates included) */
+    uint64_t reserved[3];
 } ivm_stats;
 
 #define IVM_ORDER_PLAIN 0    /* treelets nearest the pair's segment box first */

@@ -116,11 +116,14 @@ __device__ inline bool seg_box(const Seg &s, float lx, float ly, float lz, float
 
 // Exact test in FP64 (division-free Moller-Trumbore, closed triangle, open
 // segment; a segment parallel to the plane never hits).
-__device__ __noinline__ bool tri_hit_f64(const Seg &s, float4 A, float4 B, float4 C) {
-    const double dx = s.dx, dy = s.dy, dz = s.dz;
+// The segment comes in registers (a reference would put it in scratch memory
+// at every call site of this out-of-line function).
+__device__ __noinline__ bool tri_hit_f64(float px, float py, float pz, float sdx, float sdy, float sdz, float4 A,
+                                         float4 B, float4 C) {
+    const double dx = sdx, dy = sdy, dz = sdz;
     const double ex = B.x, ey = B.y, ez = B.z;   // e1
     const double fx = C.x, fy = C.y, fz = C.z;   // e2
-    const double sx = (double)s.px - (double)A.x, sy = (double)s.py - (double)A.y, sz = (double)s.pz - (double)A.z;
+    const double sx = (double)px - (double)A.x, sy = (double)py - (double)A.y, sz = (double)pz - (double)A.z;
     const double hx = dy * fz - dz * fy, hy = dz * fx - dx * fz, hz = dx * fy - dy * fx;
     const double det = ex * hx + ey * hy + ez * hz;
     if (det == 0.0) return false;
@@ -141,7 +144,7 @@ __device__ __noinline__ bool tri_hit_f64(const Seg &s, float4 A, float4 B, float
 // Returns 1 hit, 0 miss; counts rechecks.
 __device__ inline bool tri_hit(const Seg &s, float4 A, float4 B, float4 C, float eps6, bool f64only,
                                unsigned &rechecks) {
-    if (f64only) return tri_hit_f64(s, A, B, C);
+    if (f64only) return tri_hit_f64(s.px, s.py, s.pz, s.dx, s.dy, s.dz, A, B, C);
     const float sx = s.px - A.x, sy = s.py - A.y, sz = s.pz - A.z;  // exact
     const float hx = s.dy * C.z - s.dz * C.y;
     const float hy = s.dz * C.x - s.dx * C.z;
@@ -150,7 +153,7 @@ __device__ inline bool tri_hit(const Seg &s, float4 A, float4 B, float4 C, float
     const float mdet = eps6 * s.dm * B.w * C.w;
     if (!(fabsf(det) > mdet)) {
         ++rechecks;
-        return tri_hit_f64(s, A, B, C);
+        return tri_hit_f64(s.px, s.py, s.pz, s.dx, s.dy, s.dz, A, B, C);
     }
     const float sg = det > 0.f ? 1.f : -1.f;
     const float S = fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz)));
@@ -175,11 +178,11 @@ __device__ inline bool tri_hit(const Seg &s, float4 A, float4 B, float4 C, float
     if (x < -mx) return false;
     if (u > mu && v > mv && w > mw && t > mt && x > mx) return true;
     ++rechecks;
-    return tri_hit_f64(s, A, B, C);
+    return tri_hit_f64(s.px, s.py, s.pz, s.dx, s.dy, s.dz, A, B, C);
 }
 
 struct Cnt {
-    unsigned visits = 0, tests = 0, rechecks = 0, fallbacks = 0, traversed = 0, solid_segs = 0;
+    unsigned visits = 0, tests = 0, rechecks = 0, fallbacks = 0, traversed = 0, solid_segs = 0, solid_planes = 0;
 };
 
 __device__ inline int test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
@@ -428,9 +431,11 @@ __device__ inline void flush_counters(ivm_stats *st, const Cnt &c, unsigned long
     const unsigned long long r = wave_sum_u64(c.rechecks), f = wave_sum_u64(c.fallbacks);
     const unsigned long long sg = wave_sum_u64(segs);
     const unsigned long long tv = wave_sum_u64(c.traversed), ss = wave_sum_u64(c.solid_segs);
+    const unsigned long long sp = wave_sum_u64(c.solid_planes);
     if (lane_id() == 0) {
         if (tv) atomicAdd((unsigned long long *)&st->traversed, tv);
         if (ss) atomicAdd((unsigned long long *)&st->solid_segments, ss);
+        if (sp) atomicAdd((unsigned long long *)&st->solid_planes, sp);
         atomicAdd((unsigned long long *)&st->node_visits, v);
         atomicAdd((unsigned long long *)&st->tri_tests, t);
         atomicAdd((unsigned long long *)&st->rechecks, r);
@@ -559,12 +564,14 @@ __device__ inline double solid_plane(const SolidLds &S, int k, double x, double 
 // also P strictly outside one face plane (implied by (i) for the certificates;
 // it makes the test stand alone for single segments: P is not in the prism,
 // so the entry is at t > 0).
-__device__ bool solid_segment(const SolidLds &S, double px, double py, double pz, double qx, double qy, double qz) {
+__device__ bool solid_segment(const SolidLds &S, double px, double py, double pz, double qx, double qy, double qz,
+                              Cnt &c) {
     const int4 R = S.pl[kSolidMaxPlanes];
     if (!(pz >= (double)R.z && qz >= (double)R.z)) return false;
     double Ln = 0.0, Ld = 1.0, Un = 1.0, Ud = 1.0;  // t in (Ln / Ld, Un / Ud)
     bool pout = false;
     for (int k = 0; k <= R.x; ++k) {
+        ++c.solid_planes;
         const double va = solid_plane(S, k, px, py, pz);
         const double vb = solid_plane(S, k, qx, qy, qz);
         if (va >= 0.0 && vb >= 0.0) return false;
@@ -580,8 +587,8 @@ __device__ bool solid_segment(const SolidLds &S, double px, double py, double pz
     return pout && prod_less(Ln, Ud, Un, Ld);
 }
 
-__device__ inline bool solid_segment(const SolidLds &S, float4 P, float4 Q, double u) {
-    return solid_segment(S, P.x * u, P.y * u, P.z * u, Q.x * u, Q.y * u, Q.z * u);
+__device__ inline bool solid_segment(const SolidLds &S, float4 P, float4 Q, double u, Cnt &c) {
+    return solid_segment(S, P.x * u, P.y * u, P.z * u, Q.x * u, Q.y * u, Q.z * u, c);
 }
 
 // The sample hulls of a pair staged in LDS: hc[0, 8) facet i, hc[8, 16) facet j;
@@ -609,13 +616,14 @@ __device__ inline void stage_hulls(const SceneDev &sc, int i, int j, HullLds &H)
 }
 
 // Condition (i): each facet's sample hull strictly outside one face plane.
-__device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u) {
+__device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u, Cnt &c) {
     const int lane = lane_id();
     const int ni = H.ni, nj = H.nj;
     const float4 P = H.hc[lane < ni ? lane : 0], Q = H.hc[kHullMax + (lane < nj ? lane : 0)];
     const int np = S.pl[kSolidMaxPlanes].x;
     bool outP = false, outQ = false;
     for (int k = 0; k <= np && !(outP && outQ); ++k) {
+        c.solid_planes += lane < max(ni, nj);
         const double va = solid_plane(S, k, P.x * u, P.y * u, P.z * u);
         const double vb = solid_plane(S, k, Q.x * u, Q.y * u, Q.z * u);
         outP |= __ballot(lane < ni && !(va > 0.0)) == 0ull;
@@ -625,13 +633,14 @@ __device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u) {
 }
 
 // Whole pair: one lane per pair of hull corners (at most 8 x 8).
-__device__ bool certify_solid(const SolidLds &S, const HullLds &H, double u) {
+__device__ bool certify_solid(const SolidLds &S, const HullLds &H, double u, Cnt &c) {
     const int ni = H.ni, nj = H.nj;
-    if (S.pl[kSolidMaxPlanes].x <= 0 || ni == 0 || nj == 0 || !solid_sides(S, H, u)) return false;
+    if (S.pl[kSolidMaxPlanes].x <= 0 || ni == 0 || nj == 0 || !solid_sides(S, H, u, c)) return false;
     const int lane = lane_id();
     const bool act = lane < ni * nj;
     const int a = act ? lane / nj : 0, b = act ? lane - (lane / nj) * nj : 0;
-    const bool good = solid_segment(S, H.hc[a], H.hc[kHullMax + b], u);
+    Cnt dummy;
+    const bool good = solid_segment(S, H.hc[a], H.hc[kHullMax + b], u, act ? c : dummy);
     return __ballot(act && !good) == 0ull;
 }
 
@@ -640,8 +649,8 @@ __device__ bool certify_solid(const SolidLds &S, const HullLds &H, double u) {
 // flattened (sub-pair, corner, corner) items.  Returns the certified sub-pairs
 // among `todo`.
 __device__ unsigned certify_solid_subpairs(const SolidLds &S, const HullLds &H, double u, unsigned todo,
-                                           unsigned long long *fail) {
-    if (S.pl[kSolidMaxPlanes].x <= 0 || !todo || H.ni == 0 || H.nj == 0 || !solid_sides(S, H, u)) return 0u;
+                                           unsigned long long *fail, Cnt &c) {
+    if (S.pl[kSolidMaxPlanes].x <= 0 || !todo || H.ni == 0 || H.nj == 0 || !solid_sides(S, H, u, c)) return 0u;
     const int lane = lane_id();
     if (lane < 16) fail[lane] = 0ull;
     wave_sync();
@@ -659,7 +668,7 @@ __device__ unsigned certify_solid_subpairs(const SolidLds &S, const HullLds &H, 
         }
         const int cp = it - run;
         const int a = cp / hj, b = cp - (cp / hj) * hj;
-        if (!solid_segment(S, H.cc[(sp >> 2) * kHullMax + a], H.cc[(4 + (sp & 3)) * kHullMax + b], u))
+        if (!solid_segment(S, H.cc[(sp >> 2) * kHullMax + a], H.cc[(4 + (sp & 3)) * kHullMax + b], u, c))
             atomicOr(&fail[sp], 1ull);
     }
     wave_sync();
@@ -874,6 +883,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     __shared__ int sTileCnt[kWavesPerBlock][4];
     __shared__ SolidLds sSL[kWavesPerBlock][kSolidTries];
     __shared__ HullLds sH[kWavesPerBlock];
+    // wave-uniform lists live in LDS: dynamically indexed private arrays would
+    // go to scratch memory
+    __shared__ int sList[kWavesPerBlock][kCache + kSolidTries + kCache + 10];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t total = MULTI ? base[n_jobs] : one.prefix[one.n_items];
     int *stk = &sStack[wv][lane];
@@ -886,9 +898,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     // A wave takes kPairChunk consecutive candidates at a time (same facet i,
     // neighbouring j), and keeps its recent blocker triangles and solids from
     // one pair to the next within a scene.
-    int cache[kCache];        // wave-uniform list of recent blockers (sorted ranks)
+    int *cache = sList[wv];                  // recent blockers (sorted ranks)
+    int *solids = cache + kCache;            // verified solids met by traversals
+    int *tried = solids + kSolidTries;       // facets tried by a sub-pair certificate
+    int *pco = tried + kCache, *qco = pco + 5;  // cluster offsets of the admissible samples
     int ncache = 0, cpos = 0;
-    int solids[kSolidTries];  // wave-uniform list of verified solids met by traversals
     int nsol = 0, sspos = 0;
     int cur_js = -1;
     uint32_t g_next = 0, g_end = 0;
@@ -933,7 +947,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int clq = lane < nj ? sc.scluster[sj0 + lane] : 0;
         // compact admissible samples grouped by cluster: cluster c of i occupies
         // [pco[c], pco[c + 1]) of sP
-        int pco[5], qco[5];
         pco[0] = qco[0] = 0;
         for (int cl = 0; cl < 4; ++cl) {
             const unsigned long long mpc = __ballot(okp && clp == cl), mqc = __ballot(okq && clq == cl);
@@ -974,9 +987,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (!o.exhaustive && nsol > 0) {
             stage_hulls(sc, i, j, sH[wv]);
             hulls = true;
-            for (int m = 0; m < nsol && !early; ++m) early = certify_solid(sSL[wv][m], sH[wv], gsu);
+            for (int m = 0; m < nsol && !early; ++m) early = certify_solid(sSL[wv][m], sH[wv], gsu, c);
             for (int m = 0; m < nsol && !early && split; ++m) {
-                todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv]);
+                todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv], c);
                 early = todo == 0u;
             }
         }
@@ -1043,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         }
                         // then the solids met so far, segment by segment
                         for (int m = 0; m < nsol && need; ++m)
-                            if (solid_segment(sSL[wv][m], P, Q, gsu)) {
+                            if (solid_segment(sSL[wv][m], P, Q, gsu, c)) {
                                 need = false;
                                 ++c.solid_segs;
                             }
@@ -1097,7 +1110,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         stage_hulls(sc, i, j, sH[wv]);
                         hulls = true;
                     }
-                    for (int m = 0; m < nsol && !blocked; ++m) blocked = certify_solid(sSL[wv][m], sH[wv], gsu);
+                    for (int m = 0; m < nsol && !blocked; ++m) blocked = certify_solid(sSL[wv][m], sH[wv], gsu, c);
                     if (blocked) {
                         ++nsolid;
                         done = true;
@@ -1117,13 +1130,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     if (split) {
                         const unsigned before = todo;
                         for (int m = 0; m < nsol && todo; ++m)
-                            todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv]);
+                            todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv], c);
                         if (!todo) {
                             ++nsolid;
                             done = true;
                             break;
                         }
-                        int tried[kCache];
                         int ntried = 0;
                         for (int m = 0; m < ncache && todo; ++m) {
                             const int C = __float_as_int(sc.tri[3 * cache[m]].w);
@@ -1410,6 +1422,7 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
     __shared__ int sMiss[kWavesPerBlock][2 * kWave];
     __shared__ SolidLds sSL[kWavesPerBlock][kSolidCache];
+    __shared__ int sList[kWavesPerBlock][kCache + kSolidCache];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
@@ -1421,9 +1434,8 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
     const unsigned long long lt = (1ull << lane) - 1ull;
     Cnt c;
     unsigned long long segs = 0, items = 0;
-    int cache[kCache];
+    int *cache = sList[wv], *scache = cache + kCache;  // wave-uniform lists in LDS
     int ncache = 0, cpos = 0, nmiss = 0, n_order = 0;
-    int scache[kSolidCache];
     int nsc = 0, spos = 0;
     long long cur = -1;  // current (job, snapshot, side)
     int cur_job = 0;
@@ -1511,7 +1523,7 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             if (need) {
                 ++segs;
                 for (int m = 0; m < nsc && need && !o.exhaustive; ++m) {
-                    if (solid_segment(sSL[wv][m], make_float4(xx, xy, xz, 0.f), sc.smp[sidx], ldexp(1.0, sc.gs))) {
+                    if (solid_segment(sSL[wv][m], make_float4(xx, xy, xz, 0.f), sc.smp[sidx], ldexp(1.0, sc.gs), c)) {
                         need = false;
                         ++c.solid_segs;
                     }
