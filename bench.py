@@ -61,6 +61,8 @@ def _parse():
     ap.add_argument("--snapshots", type=int, default=None)
     ap.add_argument("--order", default="plain", choices=["plain", "index", "reversed", "learned"])
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--exhaustive", action="store_true",
+                    help="ablation: every admissible segment searched on its own (no caches or certificates)")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--stack", type=int, default=0)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
@@ -272,9 +274,9 @@ def main():
     st_m, st_p = ivm.new_stats(), ivm.new_stats()
     t_pairs, t_points = ivm.KernelTimer(), ivm.KernelTimer()
     om = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu,
-                       stack_depth=args.stack, timing=t_pairs)
+                       stack_depth=args.stack, timing=t_pairs, exhaustive=args.exhaustive)
     op = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu,
-                       stack_depth=args.stack, timing=t_points)
+                       stack_depth=args.stack, timing=t_points, exhaustive=args.exhaustive)
 
     def step(rec):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -349,7 +351,8 @@ def main():
         "data": "synthetic (seeded scene generator)",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "facets": F,
                    "triangles": scene.n_triangles, "samples": scene.n_samples, "snapshots": N,
-                   "seed": scene.seed, "order": args.order, "parallelism": "single GPU"},
+                   "seed": scene.seed, "order": args.order, "exhaustive": bool(args.exhaustive),
+                   "parallelism": "single GPU"},
         "txrx_ms_per_snapshot": (med["txrx"] + med["cand"]) / N,
         "phase_ms_median": med,
         "kernel_ms": {"k_pairs": pairs_kernel_ms, "k_points": points_kernel_ms},

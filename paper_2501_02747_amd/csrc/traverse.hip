@@ -1414,6 +1414,17 @@ __device__ inline void remember_blockers(int *cache, int &ncache, int &cpos, uns
 // and the segment stays outside the prism.
 constexpr int kSolidCache = 2;
 
+// Set the visible bit of facet f for the lanes with `clear`.  Queue entries of
+// one facet are adjacent, so only a lane whose nearest clear lane below holds
+// another facet issues the atomic (repeats would only cost memory traffic).
+__device__ inline void mark_visible(uint64_t *out, bool clear, int f) {
+    const int lane = lane_id();
+    const unsigned long long below = __ballot(clear) & ((1ull << lane) - 1ull);
+    const int prev = below ? 63 - __clzll((long long)below) : lane;
+    const int fprev = __shfl(f, prev);
+    if (clear && (prev == lane || fprev != f)) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+}
+
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob *many, int n_jobs,
                                                    long long n_items, TraverseOpts o, ivm_stats *st) {
@@ -1481,7 +1492,7 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             }
             nmiss -= k;
             wave_sync();
-            if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+            mark_visible(out, clear, f);
             remember_blockers(cache, ncache, cpos, __ballot(lane < k && !clear), hit);
         }
         if (!more) break;
@@ -1558,7 +1569,7 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             const bool clear = hit < 0;
             nmiss -= k;
             wave_sync();
-            if (clear) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+            mark_visible(out, clear, f);
             remember_blockers(cache, ncache, cpos, __ballot(!clear), hit);
             if (sc.n_solids > 0) remember_solid_ids(sc, scache, nsc, spos, sSL[wv], kSolidCache, !clear, hit);
         }
