@@ -270,6 +270,105 @@ __device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr ord
     }
 }
 
+// Wave-synchronous any-hit over one batch: every lane traverses its own
+// segment (the same steps as any_hit), and after each step the wave applies an
+// abort rule to lanes whose answer no longer matters:
+//   kAbortAll      - once any lane is clear, all stop (a pair is visible as soon
+//                    as one admissible segment is clear);
+//   kAbortSameKey  - once a lane is clear, the lanes with the same key stop (a
+//                    facet is visible from a point as soon as one sample is).
+// Returns the hit rank (>= 0), -1 clear, or -2 for a lane that did not run or
+// was stopped.
+constexpr int kAbortAll = 1, kAbortSameKey = 2;
+
+template <typename OrderPtr>
+__device__ int any_hit_wave(const SceneDev &sc, Seg s, bool active, int exA, int exB, OrderPtr order, int n_order,
+                            int *stk, int depth, float eps6, bool f64, Cnt &c, int rule, int key) {
+    if (active) with_inverse(s);
+    int r = 0, sp = 0;
+    int ref = kNone;
+    int res = active ? -3 : -2;  // -3 = running
+    while (true) {
+        const bool run = res == -3;
+        if (!__ballot(run)) break;
+        if (run) {
+            if (ref == kNone) {
+                if (sp > 0) {
+                    ref = stk[(--sp) * kWave];
+                } else {
+                    while (r < n_order) {
+                        const int k = order[r++];
+                        const int root = sc.tl_root[k];
+                        if (root == kNone) continue;  // empty treelet: its inverted box must never be entered
+                        const float *b = sc.tl_box + 6 * k;
+                        float te;
+                        if (seg_box(s, b[0], b[1], b[2], b[3], b[4], b[5], te)) {
+                            ref = root;
+                            break;
+                        }
+                    }
+                    if (ref == kNone) res = -1;
+                }
+            }
+            if (res == -3 && ref != kNone) {
+                if (ref >= 0) {
+                    ++c.visits;
+                    const Node nd = sc.nodes[ref];
+                    float t0, t1;
+                    const bool h0 = seg_box(s, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, t0);
+                    const bool h1 = seg_box(s, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, t1);
+                    if (h0 && h1) {
+                        const int nearc = t0 <= t1 ? nd.d.x : nd.d.y;
+                        const int farc = t0 <= t1 ? nd.d.y : nd.d.x;
+                        ref = nearc;
+                        if (sp < depth) {
+                            stk[(sp++) * kWave] = farc;
+                        } else {
+                            ++c.fallbacks;
+                            int first, count;
+                            if (farc < 0) {
+                                first = leaf_first(farc);
+                                count = leaf_count(farc);
+                            } else {
+                                const int4 rg = sc.nodes[farc].d;
+                                first = rg.z;
+                                count = rg.w - rg.z + 1;
+                            }
+                            const int h = test_range(sc, s, first, count, exA, exB, eps6, f64, c);
+                            if (h >= 0) res = h;
+                        }
+                    } else if (h0) {
+                        ref = nd.d.x;
+                    } else if (h1) {
+                        ref = nd.d.y;
+                    } else {
+                        ref = kNone;
+                    }
+                } else {
+                    const int h = test_range(sc, s, leaf_first(ref), leaf_count(ref), exA, exB, eps6, f64, c);
+                    if (h >= 0) res = h;
+                    ref = kNone;
+                }
+            }
+        }
+        const unsigned long long cl = __ballot(run && res == -1);  // lanes that just turned out clear
+        if (cl) {
+            if (rule == kAbortAll) {
+                if (res == -3) res = -2;
+            } else if (rule == kAbortSameKey) {
+                unsigned long long m = cl;
+                while (m) {
+                    const int src = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const int kc = __shfl(key, src);
+                    if (res == -3 && key == kc) res = -2;
+                }
+            }
+        }
+    }
+    return res;
+}
+
 // Per-wave treelet order.  Lane k < 32 holds a 64-bit key for treelet k
 // (UINT64_MAX = skip); the wave ranks the keys (index breaks ties) into
 // order[0..n).  Returns n.
@@ -1072,14 +1171,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 const int k = min(kWave, nmiss);
                 int hit = -1;
                 bool clear = false;
-                if (lane < k) {
-                    const int ab = miss[nmiss - k + lane];
+                {
+                    const int ab = lane < k ? miss[nmiss - k + lane] : 0;
                     const float4 P = sP[wv][ab & 255], Q = sQ[wv][ab >> 8];
                     const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
-                    ++c.traversed;
-                    hit = ntile >= 0 ? tile_hit(sc, sg, sTile[wv], ntile, o.eps6, f64, c)
-                                     : any_hit(sc, sg, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
-                    clear = hit < 0;
+                    if (lane < k) ++c.traversed;
+                    if (ntile >= 0) {
+                        if (lane < k) hit = tile_hit(sc, sg, sTile[wv], ntile, o.eps6, f64, c);
+                    } else {
+                        hit = any_hit_wave(sc, sg, lane < k, i, j, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64,
+                                           c, kAbortAll, 0);
+                    }
+                    clear = lane < k && hit == -1;
                 }
                 nmiss -= k;
                 wave_sync();
@@ -1479,21 +1582,18 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
         while (nmiss > 0 && key != cur) {
             const PointJob &CJ = MULTI ? many[cur_job] : one;
             const int k = min(kWave, nmiss);
-            bool clear = false;
-            int hit = -1, f = -1;
-            if (lane < k) {
-                const int sidx = miss[nmiss - k + lane];
-                f = CJ.sc.sfacet[sidx];
-                const float4 P = CJ.sc.smp[sidx];
-                const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
-                ++c.traversed;
-                hit = any_hit(CJ.sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
-                clear = hit < 0;
-            }
+            const int sidx = miss[nmiss - (lane < k ? k - lane : 1)];
+            const int f = CJ.sc.sfacet[sidx];
+            const float4 P = CJ.sc.smp[sidx];
+            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+            if (lane < k) ++c.traversed;
+            const int hit = any_hit_wave(CJ.sc, sg, lane < k, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6,
+                                         f64, c, kAbortSameKey, f);
+            const bool clear = hit == -1;
             nmiss -= k;
             wave_sync();
             mark_visible(out, clear, f);
-            remember_blockers(cache, ncache, cpos, __ballot(lane < k && !clear), hit);
+            remember_blockers(cache, ncache, cpos, __ballot(hit >= 0), hit);
         }
         if (!more) break;
         const PointJob &J = MULTI ? many[js] : one;
@@ -1565,13 +1665,14 @@ __global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob 
             const float4 P = sc.smp[s2];
             const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
             ++c.traversed;
-            const int hit = any_hit(sc, sg, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c);
-            const bool clear = hit < 0;
+            const int hit = any_hit_wave(sc, sg, true, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c,
+                                         kAbortSameKey, f);
+            const bool clear = hit == -1;
             nmiss -= k;
             wave_sync();
             mark_visible(out, clear, f);
-            remember_blockers(cache, ncache, cpos, __ballot(!clear), hit);
-            if (sc.n_solids > 0) remember_solid_ids(sc, scache, nsc, spos, sSL[wv], kSolidCache, !clear, hit);
+            remember_blockers(cache, ncache, cpos, __ballot(hit >= 0), hit);
+            if (sc.n_solids > 0) remember_solid_ids(sc, scache, nsc, spos, sSL[wv], kSolidCache, hit >= 0, hit);
         }
     }
     flush_counters(st, c, segs, 0, items);
