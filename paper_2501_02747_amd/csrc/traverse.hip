@@ -637,13 +637,56 @@ __device__ inline bool prod_less(double a, double b, double c, double d) {
 // its record (walls, top z, base z, 0), all in sample units.
 struct SolidLds {
     int4 pl[kSolidMaxPlanes + 1];
+    float4 lo, hi;  // metres: footprint box and (base, top) heights in .z
 };
 
-// One load round: lane k < kSolidMaxPlanes fetches plane k, the next lane the record.
+// One load round: lane k < kSolidMaxPlanes fetches plane k, the next lane the
+// record; the footprint box comes from the walls' corner points.
 __device__ inline void stage_solid(const SceneDev &sc, int s, SolidLds &dst) {
     const int lane = lane_id();
-    if (lane < kSolidMaxPlanes) dst.pl[lane] = sc.splane[s * kSolidMaxPlanes + lane];
-    else if (lane == kSolidMaxPlanes) dst.pl[kSolidMaxPlanes] = sc.solid[s];
+    int4 v = make_int4(0, 0, 0, 0);
+    if (lane < kSolidMaxPlanes) v = sc.splane[s * kSolidMaxPlanes + lane];
+    else if (lane == kSolidMaxPlanes) v = sc.solid[s];
+    if (lane <= kSolidMaxPlanes) dst.pl[lane] = v;
+    const int np = __shfl(v.x, kSolidMaxPlanes), top = __shfl(v.y, kSolidMaxPlanes);
+    const int base = __shfl(v.z, kSolidMaxPlanes);
+    const float m = ldexpf(1.0f, -sc.gs);  // sample units -> metres (exact: integers below 2^24)
+    const bool w = lane < np;
+    const float x0 = wave_min(w ? (float)v.x * m : INFINITY), x1 = wave_max(w ? (float)v.x * m : -INFINITY);
+    const float y0 = wave_min(w ? (float)v.y * m : INFINITY), y1 = wave_max(w ? (float)v.y * m : -INFINITY);
+    if (lane == 0) {
+        dst.lo = make_float4(x0, y0, (float)base * m, 0.f);
+        dst.hi = make_float4(x1, y1, (float)top * m, 0.f);
+    }
+    wave_sync();
+}
+
+// A segment set inside the box [lo, hi] can pass through the open prism only if
+// that box reaches into the open footprint box and below the top (a necessary
+// test before the exact ones).
+__device__ inline bool solid_box_reach(const SolidLds &S, const float lo[3], const float hi[3]) {
+    return hi[0] > S.lo.x && lo[0] < S.hi.x && hi[1] > S.lo.y && lo[1] < S.hi.y && lo[2] < S.hi.z;
+}
+
+// Swap the staged solid in slot `a` with the one in slot 0 (wave-uniform).
+__device__ inline void solid_to_front(int *solids, SolidLds *lds, int a) {
+    if (a <= 0) return;
+    const int lane = lane_id();
+    int4 *x = (int4 *)&lds[0], *y = (int4 *)&lds[a];
+    constexpr int n = sizeof(SolidLds) / sizeof(int4);
+    int4 vx = make_int4(0, 0, 0, 0), vy = vx;
+    if (lane < n) {
+        vx = x[lane];
+        vy = y[lane];
+    }
+    const int t0 = solids[0], ta = solids[a];
+    wave_sync();
+    if (lane < n) {
+        x[lane] = vy;
+        y[lane] = vx;
+    }
+    solids[0] = ta;
+    solids[a] = t0;
     wave_sync();
 }
 
@@ -731,15 +774,19 @@ __device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u, Cnt &
     return outP && outQ;
 }
 
-// Whole pair: one lane per pair of hull corners (at most 8 x 8).
-__device__ bool certify_solid(const SolidLds &S, const HullLds &H, double u, Cnt &c) {
+// Whole pair: one lane per pair of hull corners (at most 8 x 8).  `reach` gets
+// whether any corner segment passes through the prism (a sub-pair bundle holds
+// such a corner segment whenever its clusters hold hull corners).
+__device__ bool certify_solid(const SolidLds &S, const HullLds &H, double u, Cnt &c, bool *reach = nullptr) {
     const int ni = H.ni, nj = H.nj;
+    if (reach) *reach = false;
     if (S.pl[kSolidMaxPlanes].x <= 0 || ni == 0 || nj == 0 || !solid_sides(S, H, u, c)) return false;
     const int lane = lane_id();
     const bool act = lane < ni * nj;
     const int a = act ? lane / nj : 0, b = act ? lane - (lane / nj) * nj : 0;
     Cnt dummy;
     const bool good = solid_segment(S, H.hc[a], H.hc[kHullMax + b], u, act ? c : dummy);
+    if (reach) *reach = __ballot(act && good) != 0ull;
     return __ballot(act && !good) == 0ull;
 }
 
@@ -1084,10 +1131,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         bool hulls = false;                    // sample hulls staged in LDS for this pair
         bool early = false;
         if (!o.exhaustive && nsol > 0) {
-            stage_hulls(sc, i, j, sH[wv]);
-            hulls = true;
-            for (int m = 0; m < nsol && !early; ++m) early = certify_solid(sSL[wv][m], sH[wv], gsu, c);
+            // only solids whose box reaches the segment box; a solid that certifies
+            // the pair moves to the front of the wave's list
+            unsigned reach_sub = 0u;
+            for (int m = 0; m < nsol && !early; ++m) {
+                if (!solid_box_reach(sSL[wv][m], lo, hi)) continue;
+                if (!hulls) {
+                    stage_hulls(sc, i, j, sH[wv]);
+                    hulls = true;
+                }
+                bool reach = false;
+                early = certify_solid(sSL[wv][m], sH[wv], gsu, c, &reach);
+                if (early) solid_to_front(solids, sSL[wv], m);
+                else if (reach) reach_sub |= 1u << m;
+            }
             for (int m = 0; m < nsol && !early && split; ++m) {
+                if (!((reach_sub >> m) & 1u)) continue;
                 todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv], c);
                 early = todo == 0u;
             }
