@@ -567,7 +567,9 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 
 constexpr int kCache = 4;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
-constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time
+constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time (small jobs)
+constexpr int kPairChunkLarge = 32;       // ... when a wave has many pairs to do (better reuse)
+constexpr uint32_t kLargePerWave = 2048;  // candidate pairs per wave above which chunks are large
 
 // Single-occluder certificate.  Let H_i, H_j be the convex hulls of the two
 // sample sets (valid when the samples lie in their facet's plane, checked at
@@ -1041,7 +1043,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     Cnt c;
     unsigned segs = 0, nvis = 0, ncert = 0, nsub = 0, ntiled = 0, nsolid = 0;  // per-wave counts fit 32 bits
     const unsigned long long lt = (1ull << lane) - 1ull;
-    // A wave takes kPairChunk consecutive candidates at a time (same facet i,
+    // A wave takes a chunk of consecutive candidates at a time (same facet i,
     // neighbouring j), and keeps its recent blocker triangles and solids from
     // one pair to the next within a scene.
     int *cache = sList[wv];                  // recent blockers (sorted ranks)
@@ -1052,14 +1054,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     int nsol = 0, sspos = 0;
     int cur_js = -1;
     uint32_t g_next = 0, g_end = 0;
+    const uint32_t nwaves_all = gridDim.x * (uint32_t)kWavesPerBlock;
+    const uint32_t chunk = total / nwaves_all > kLargePerWave ? (uint32_t)kPairChunkLarge : (uint32_t)kPairChunk;
     while (true) {
         if (g_next >= g_end) {
             uint32_t g0 = 0;
-            if (lane == 0) g0 = atomicAdd(queue, (uint32_t)kPairChunk);
+            if (lane == 0) g0 = atomicAdd(queue, chunk);
             g0 = __shfl(g0, 0);
             if (g0 >= total) break;
             g_next = g0;
-            g_end = min(total, g0 + (uint32_t)kPairChunk);
+            g_end = min(total, g0 + chunk);
         }
         const uint32_t g = g_next++;
         int js = 0;
