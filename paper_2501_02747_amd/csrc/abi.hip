@@ -118,6 +118,7 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.tri_orig = (const int *)(ws + L.tri_orig);
     d.tri_group = (const int *)(ws + L.tri_group);
     d.nodes = (const Node *)(ws + L.nodes);
+    d.nodes4 = (const Node4 *)(ws + L.nodes4);
     d.tl_box = (const float *)(ws + L.tl_box);
     d.tl_root = (const int *)(ws + L.tl_root);
     d.fplane = (const double *)(ws + L.fplane);

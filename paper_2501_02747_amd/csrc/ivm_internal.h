@@ -41,6 +41,18 @@ struct __align__(16) Node {
     int4 d;
 };
 
+// 4-wide view of the same tree: record x (one per binary internal node x) lists
+// the grandchildren of x, a leaf child standing for itself: 2 to 4 children,
+// boxes stored across the four lanes of each float4.  Empty slots hold kNoRef.
+// Traversal starts at a treelet root's record and only ever reaches records of
+// nodes at even depth.
+constexpr int kNoRef = 0x7fffffff;
+struct __align__(16) Node4 {
+    float4 lox, loy, loz, hix, hiy, hiz;
+    int4 ref;   // >= 0 binary internal node (and its record); < 0 leaf; kNoRef empty
+    int4 pad;
+};
+
 __host__ __device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }
 __host__ __device__ inline int leaf_first(int ref) { return (~ref) >> 3; }
 __host__ __device__ inline int leaf_count(int ref) { return ((~ref) & 7) + 1; }
@@ -59,6 +71,7 @@ struct SceneDev {
     const int *tri_orig;       // sorted rank -> caller's triangle index
     const int *tri_group;      // caller's triangle index -> treelet
     const Node *nodes;         // T (internal nodes at global slots)
+    const Node4 *nodes4;       // T: 4-wide records, same slots
     const float *tl_box;       // kTreelets * 6 (lo.xyz, hi.xyz)
     const int *tl_root;        // kTreelets root refs (0x7fffffff = empty)
     const double *fplane;      // F * 6: a.xyz, n.xyz
@@ -90,7 +103,7 @@ struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
     size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
-    size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver;
+    size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4;
     size_t learned_bytes;
     size_t total;
 };

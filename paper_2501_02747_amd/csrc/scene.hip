@@ -71,6 +71,7 @@ Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
     L.sol_rec = take(Ns * sizeof(int4));
     L.sol_plane = take(Ns * kSolidMaxPlanes * sizeof(int4));
     L.sol_nver = take(sizeof(int));
+    L.nodes4 = take(Tn * sizeof(Node4));
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
@@ -581,6 +582,61 @@ __global__ void k_finalize(int T, const float4 *tri, const int *child, const int
     nodes[x] = nd;
 }
 
+// 4-wide records from the finished binary nodes (one thread per slot).
+__global__ void k_wide(int T, const Node *nodes, Node4 *nodes4) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T) return;
+    float lo[3][4], hi[3][4];
+    int ref[4];
+    for (int q = 0; q < 4; ++q) {
+        ref[q] = kNoRef;
+        for (int k = 0; k < 3; ++k) {
+            lo[k][q] = INFINITY;
+            hi[k][q] = -INFINITY;
+        }
+    }
+    if (is_internal_slot(x, T)) {
+        const Node nd = nodes[x];
+        const int cref[2] = {nd.d.x, nd.d.y};
+        const float cb[2][6] = {{nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y},
+                                {nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w}};
+        int n = 0;
+        for (int h = 0; h < 2; ++h) {
+            if (cref[h] < 0) {  // a leaf child stands for itself
+                ref[n] = cref[h];
+                for (int k = 0; k < 3; ++k) {
+                    lo[k][n] = cb[h][k];
+                    hi[k][n] = cb[h][3 + k];
+                }
+                ++n;
+            } else {            // an internal child contributes its two children
+                const Node cd = nodes[cref[h]];
+                const int gref[2] = {cd.d.x, cd.d.y};
+                const float gb[2][6] = {{cd.a.x, cd.a.y, cd.a.z, cd.a.w, cd.b.x, cd.b.y},
+                                        {cd.b.z, cd.b.w, cd.c.x, cd.c.y, cd.c.z, cd.c.w}};
+                for (int g2 = 0; g2 < 2; ++g2) {
+                    ref[n] = gref[g2];
+                    for (int k = 0; k < 3; ++k) {
+                        lo[k][n] = gb[g2][k];
+                        hi[k][n] = gb[g2][3 + k];
+                    }
+                    ++n;
+                }
+            }
+        }
+    }
+    Node4 w;
+    w.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+    w.loy = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+    w.loz = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+    w.hix = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+    w.hiy = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+    w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
+    w.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
+    w.pad = make_int4(0, 0, 0, 0);
+    nodes4[x] = w;
+}
+
 __global__ void k_treelets(int T, const float4 *tri, const float *nbox, float *tl_box, int *tl_root) {
     int k = threadIdx.x;
     if (k >= kTreelets) return;
@@ -695,6 +751,8 @@ hipError_t launch_build(Scene &sc, hipStream_t s) {
         hipLaunchKernelGGL(k_node_boxes, dim3(nblk(T, 128)), dim3(128), 0, s, T, tri, range, nbox);
         hipLaunchKernelGGL(k_finalize, dim3(nblk(T, 256)), dim3(256), 0, s, T, tri, child, range, nbox,
                            (Node *)(ws + L.nodes));
+        hipLaunchKernelGGL(k_wide, dim3(nblk(T, 256)), dim3(256), 0, s, T, (const Node *)(ws + L.nodes),
+                           (Node4 *)(ws + L.nodes4));
         hipLaunchKernelGGL(k_treelets, dim3(1), dim3(64), 0, s, T, tri, nbox, (float *)(ws + L.tl_box),
                            (int *)(ws + L.tl_root));
     } else {

@@ -312,15 +312,37 @@ __device__ int any_hit_wave(const SceneDev &sc, Seg s, bool active, int exA, int
             }
             if (res == -3 && ref != kNone) {
                 if (ref >= 0) {
+                    // a 4-wide record: test the up-to-four children, descend into the
+                    // nearest, push the others far to near
                     ++c.visits;
-                    const Node nd = sc.nodes[ref];
-                    float t0, t1;
-                    const bool h0 = seg_box(s, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, t0);
-                    const bool h1 = seg_box(s, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, t1);
-                    if (h0 && h1) {
-                        const int nearc = t0 <= t1 ? nd.d.x : nd.d.y;
-                        const int farc = t0 <= t1 ? nd.d.y : nd.d.x;
-                        ref = nearc;
+                    const Node4 nd = sc.nodes4[ref];
+                    float a0, a1, a2, a3;
+                    int b0 = nd.ref.x, b1 = nd.ref.y, b2 = nd.ref.z, b3 = nd.ref.w;
+                    const bool h0 = b0 != kNone && seg_box(s, nd.lox.x, nd.loy.x, nd.loz.x, nd.hix.x, nd.hiy.x, nd.hiz.x, a0);
+                    const bool h1 = b1 != kNone && seg_box(s, nd.lox.y, nd.loy.y, nd.loz.y, nd.hix.y, nd.hiy.y, nd.hiz.y, a1);
+                    const bool h2 = b2 != kNone && seg_box(s, nd.lox.z, nd.loy.z, nd.loz.z, nd.hix.z, nd.hiy.z, nd.hiz.z, a2);
+                    const bool h3 = b3 != kNone && seg_box(s, nd.lox.w, nd.loy.w, nd.loz.w, nd.hix.w, nd.hiy.w, nd.hiz.w, a3);
+                    const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
+                    if (!h0) a0 = INFINITY;
+                    if (!h1) a1 = INFINITY;
+                    if (!h2) a2 = INFINITY;
+                    if (!h3) a3 = INFINITY;
+                    // sorting network on (a, b): hits (finite a) come first, nearest first
+                    auto cswap = [](float &x, int &xr, float &y, int &yr) {
+                        if (y < x) {
+                            const float t = x; x = y; y = t;
+                            const int tr = xr; xr = yr; yr = tr;
+                        }
+                    };
+                    cswap(a0, b0, a1, b1);
+                    cswap(a2, b2, a3, b3);
+                    cswap(a0, b0, a2, b2);
+                    cswap(a1, b1, a3, b3);
+                    cswap(a1, b1, a2, b2);
+                    ref = nh > 0 ? b0 : kNone;
+                    const int pend[3] = {b3, b2, b1};
+                    for (int q = 4 - nh; q < 3 && res == -3; ++q) {
+                        const int farc = pend[q];
                         if (sp < depth) {
                             stk[(sp++) * kWave] = farc;
                         } else {
@@ -337,12 +359,6 @@ __device__ int any_hit_wave(const SceneDev &sc, Seg s, bool active, int exA, int
                             const int h = test_range(sc, s, first, count, exA, exB, eps6, f64, c);
                             if (h >= 0) res = h;
                         }
-                    } else if (h0) {
-                        ref = nd.d.x;
-                    } else if (h1) {
-                        ref = nd.d.y;
-                    } else {
-                        ref = kNone;
                     }
                 } else {
                     const int h = test_range(sc, s, leaf_first(ref), leaf_count(ref), exA, exB, eps6, f64, c);
@@ -1592,7 +1608,7 @@ __device__ inline void mark_visible(uint64_t *out, bool clear, int f) {
 }
 
 template <bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_points(PointJob one, const PointJob *many, int n_jobs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_points(PointJob one, const PointJob *many, int n_jobs,
                                                    long long n_items, TraverseOpts o, ivm_stats *st) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
