@@ -141,6 +141,7 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.fsolid = (const int *)(ws + L.fsolid);
     d.solid = (const int4 *)(ws + L.sol_rec);
     d.splane = (const int4 *)(ws + L.sol_plane);
+    d.sbox = (const float4 *)(ws + L.sol_box);
     d.n_solids = desc->facet_solid ? desc->n_solids : 0;
     sc.n_items = F * d.W;
     if (launch_build(sc, stream) != hipSuccess) {

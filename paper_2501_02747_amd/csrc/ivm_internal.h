@@ -96,6 +96,7 @@ struct SceneDev {
     const int4 *splane;        // n_solids * kSolidMaxPlanes: (u.x, u.y, d.x, d.y) sample units; the
                                // outside of wall k is d.y (x - u.x) - d.x (y - u.y) > 0
     int n_solids;
+    const float4 *sbox;        // n_solids * 2: footprint box and (base, top) in .z, metres; empty if rejected
 };
 
 // Workspace layout of one scene.
@@ -103,7 +104,7 @@ struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
     size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
-    size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4;
+    size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4, sol_box;
     size_t learned_bytes;
     size_t total;
 };

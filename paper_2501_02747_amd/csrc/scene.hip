@@ -72,6 +72,7 @@ Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
     L.sol_plane = take(Ns * kSolidMaxPlanes * sizeof(int4));
     L.sol_nver = take(sizeof(int));
     L.nodes4 = take(Tn * sizeof(Node4));
+    L.sol_box = take(Ns * 2 * sizeof(float4));
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));

@@ -183,7 +183,7 @@ __device__ inline bool angle_less(long long ax, long long ay, long long bx, long
 // the triangle pairs for overlapping interiors.
 __global__ __launch_bounds__(64) void k_solid_verify(ivm_scene_desc d, const int *ffirst, const double *fplane,
                                                      const int *off, const int *fac, int4 *rec, int4 *planes,
-                                                     int *fsolid, int *n_verified) {
+                                                     float4 *sbox, int *fsolid, int *n_verified) {
     const int s = blockIdx.x, lane = threadIdx.x;
     __shared__ int mem[kSolidMaxFacets];
     __shared__ long long tv[kSolidMaxTris][9];   // x, y, z of the three vertices
@@ -377,6 +377,21 @@ __global__ __launch_bounds__(64) void k_solid_verify(ivm_scene_desc d, const int
     if (lane == 0) {
         rec[s] = make_int4(ok ? npl : 0, ok ? (int)H : 0, ok ? (int)ZB : 0, 0);
         if (ok) atomicAdd(n_verified, 1);
+        // footprint box and heights in metres (exact: sample-grid integers below 2^24)
+        float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f), hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+        if (ok) {
+            const float mu = ldexpf(1.0f, -d.grid_sample_log2);
+            for (int k = 0; k < npl; ++k) {
+                lo.x = fminf(lo.x, (float)pu[k][0] * mu);
+                lo.y = fminf(lo.y, (float)pu[k][1] * mu);
+                hi.x = fmaxf(hi.x, (float)pu[k][0] * mu);
+                hi.y = fmaxf(hi.y, (float)pu[k][1] * mu);
+            }
+            lo.z = (float)ZB * mu;
+            hi.z = (float)H * mu;
+        }
+        sbox[2 * s] = lo;
+        sbox[2 * s + 1] = hi;
     }
     if (ok) {
         if (lane < npl) planes[s * kSolidMaxPlanes + lane] = make_int4((int)pu[lane][0], (int)pu[lane][1],
@@ -417,7 +432,8 @@ hipError_t launch_solids(Scene &sc, hipStream_t s) {
         hipLaunchKernelGGL(k_solid_scatter, dim3(nblk(F, 256)), dim3(256), 0, s, F, ns, d.facet_solid,
                            (const int *)off, fill, fac);
         hipLaunchKernelGGL(k_solid_verify, dim3(ns), dim3(64), 0, s, d, ffirst, fplane, (const int *)off,
-                           (const int *)fac, (int4 *)(ws + L.sol_rec), (int4 *)(ws + L.sol_plane), fsolid, nver);
+                           (const int *)fac, (int4 *)(ws + L.sol_rec), (int4 *)(ws + L.sol_plane),
+                           (float4 *)(ws + L.sol_box), fsolid, nver);
     }
     return hipGetLastError();
 }

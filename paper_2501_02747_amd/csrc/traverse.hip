@@ -41,6 +41,10 @@ __device__ inline float wave_max(float v) {
     for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
     return v;
 }
+__device__ inline float wave_sum(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
     return v;
@@ -583,6 +587,8 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 
 constexpr int kCache = 4;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
+constexpr int kScanMaxSolids = 1024;  // scenes with at most this many solids scan them all per pair
+constexpr int kScanTries = 4;         // solids from the scan tried per pair
 constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time (small jobs)
 constexpr int kPairChunkLarge = 32;       // ... when a wave has many pairs to do (better reuse)
 constexpr uint32_t kLargePerWave = 2048;  // candidate pairs per wave above which chunks are large
@@ -1150,7 +1156,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const double gsu = ldexp(1.0, sc.gs);  // metres -> sample units (exact)
         bool hulls = false;                    // sample hulls staged in LDS for this pair
         bool early = false;
-        if (!o.exhaustive && nsol > 0) {
+        if (!o.exhaustive && sc.n_solids > 0) {
             // only solids whose box reaches the segment box; a solid that certifies
             // the pair moves to the front of the wave's list
             unsigned reach_sub = 0u;
@@ -1164,6 +1170,72 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 early = certify_solid(sSL[wv][m], sH[wv], gsu, c, &reach);
                 if (early) solid_to_front(solids, sSL[wv], m);
                 else if (reach) reach_sub |= 1u << m;
+            }
+            // then solids from the whole scene met by the segment joining the centroids
+            // of the admissible samples, those nearest to either end first
+            if (!early && sc.n_solids <= kScanMaxSolids) {
+                const float cpx = wave_sum(okp ? p.x : 0.f) / np, cpy = wave_sum(okp ? p.y : 0.f) / np;
+                const float cpz = wave_sum(okp ? p.z : 0.f) / np;
+                const float cqx = wave_sum(okq ? q.x : 0.f) / nq, cqy = wave_sum(okq ? q.y : 0.f) / nq;
+                const float cqz = wave_sum(okq ? q.z : 0.f) / nq;
+                const float dx = cqx - cpx, dy = cqy - cpy;
+                const int own_i = sc.fsolid[i], own_j = sc.fsolid[j];
+                float bkey = INFINITY;
+                int bsol = -1;
+                for (int b0 = 0; b0 < sc.n_solids; b0 += kWave) {
+                    const int sid = b0 + lane;
+                    if (sid >= sc.n_solids || sid == own_i || sid == own_j) continue;
+                    bool listed = false;
+                    for (int m = 0; m < nsol; ++m) listed |= solids[m] == sid;
+                    if (listed) continue;
+                    const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
+                    if (!(hi[0] > L.x && lo[0] < H.x && hi[1] > L.y && lo[1] < H.y && fminf(cpz, cqz) < H.z &&
+                          lo[2] >= L.z))
+                        continue;
+                    float t0 = 0.f, t1 = 1.f;
+                    if (dx != 0.f) {
+                        const float a = (L.x - cpx) / dx, b = (H.x - cpx) / dx;
+                        t0 = fmaxf(t0, fminf(a, b));
+                        t1 = fminf(t1, fmaxf(a, b));
+                    } else if (!(cpx > L.x && cpx < H.x)) {
+                        continue;
+                    }
+                    if (dy != 0.f) {
+                        const float a = (L.y - cpy) / dy, b = (H.y - cpy) / dy;
+                        t0 = fmaxf(t0, fminf(a, b));
+                        t1 = fminf(t1, fmaxf(a, b));
+                    } else if (!(cpy > L.y && cpy < H.y)) {
+                        continue;
+                    }
+                    if (!(t0 < t1)) continue;
+                    const float key = fminf(t0, 1.f - t1);
+                    if (key < bkey) {
+                        bkey = key;
+                        bsol = sid;
+                    }
+                }
+                for (int tr = 0; tr < kScanTries && !early; ++tr) {
+                    const float kmin = wave_min(bkey);
+                    if (!(kmin < INFINITY)) break;
+                    const unsigned long long win = __ballot(bkey == kmin);
+                    const int src = __ffsll((long long)win) - 1;
+                    const int sid = __shfl(bsol, src);
+                    if (lane == src) bkey = INFINITY;
+                    int slot;
+                    if (nsol < kSolidTries) slot = nsol++;
+                    else { slot = sspos; sspos = (sspos + 1) % kSolidTries; }
+                    reach_sub &= ~(1u << slot);
+                    solids[slot] = sid;
+                    stage_solid(sc, sid, sSL[wv][slot]);
+                    if (!hulls) {
+                        stage_hulls(sc, i, j, sH[wv]);
+                        hulls = true;
+                    }
+                    bool reach = false;
+                    early = certify_solid(sSL[wv][slot], sH[wv], gsu, c, &reach);
+                    if (early) solid_to_front(solids, sSL[wv], slot);
+                    else if (reach) reach_sub |= 1u << slot;
+                }
             }
             for (int m = 0; m < nsol && !early && split; ++m) {
                 if (!((reach_sub >> m) & 1u)) continue;
