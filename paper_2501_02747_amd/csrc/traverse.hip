@@ -587,7 +587,7 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 
 constexpr int kCache = 4;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
-constexpr int kScanMaxSolids = 1024;  // scenes with at most this many solids scan them all per pair
+constexpr int kScanMaxSolids = 4096;  // scenes with at most this many solids scan them all per pair
 constexpr int kScanTries = 4;         // solids from the scan tried per pair
 constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time (small jobs)
 constexpr int kPairChunkLarge = 32;       // ... when a wave has many pairs to do (better reuse)
