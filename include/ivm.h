@@ -146,7 +146,8 @@ typedef struct ivm_stats {
     uint64_t certified; /* pairs proven blocked by one convex occluder from hull corners */
     uint64_t subpair_runs; /* pairs whose explicit segments were limited to uncertified sub-pairs */
     uint64_t tiled_pairs;  /* pairs decided from a complete near-field tile, without the BVH */
-    uint64_t solid_certified; /* pairs proven blocked by verified solids on whole or sub-pair bundles */
+    uint64_t solid_certified; /* matrix: pairs proven blocked by verified solids on whole or sub-pair
+                                 bundles; table: (point, facet) pairs proven blocked by one solid */
     uint64_t traversed;       /* segments sent to a BVH (or near-field tile) any-hit search */
     uint64_t solid_segments;  /* segments decided blocked by a verified solid one at a time */
     uint64_t solid_planes;    /* segment x face-plane steps of solid tests (certificates included) */

@@ -589,6 +589,7 @@ constexpr int kCache = 4;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
 constexpr int kScanMaxSolids = 4096;  // scenes with at most this many solids scan them all per pair
 constexpr int kScanTries = 4;         // solids from the scan tried per pair
+constexpr int kScanMaxSolidsPoint = 1024;  // the same scan per (point, facet) in the Tx/Rx kernel
 constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time (small jobs)
 constexpr int kPairChunkLarge = 32;       // ... when a wave has many pairs to do (better reuse)
 constexpr uint32_t kLargePerWave = 2048;  // candidate pairs per wave above which chunks are large
@@ -1679,6 +1680,76 @@ __device__ inline void mark_visible(uint64_t *out, bool clear, int f) {
     if (clear && (prev == lane || fprev != f)) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
 }
 
+// Point certificate: every segment from X to the sample hull of facet f passes
+// through solid K (X strictly outside one face plane, X and the hull corners at
+// or above the base; for fixed X the q whose segment meets K form a convex set),
+// so no sample of f is visible from X.  The candidates come from a scan of the
+// scene's solid boxes met by the segment from X to f's box centre, nearest to
+// either end first; they are staged in the wave's solid cache slots.  One lane
+// per hull corner.
+__device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLds *lds, int *scache, int &nsc,
+                                    int &spos, Cnt &c) {
+    const int lane = lane_id();
+    const int nh = sc.fhull_n[f];
+    if (nh == 0) return false;
+    const double gu = ldexp(1.0, sc.gs);
+    const float4 corner = sc.smp[sc.fhull[kHullMax * f + (lane < nh ? lane : 0)]];
+    const float *fb = sc.fbox + 6 * f;
+    const float cx = 0.5f * (fb[0] + fb[3]), cy = 0.5f * (fb[1] + fb[4]);
+    const float bx0 = fminf(X.x, fb[0]), bx1 = fmaxf(X.x, fb[3]), by0 = fminf(X.y, fb[1]), by1 = fmaxf(X.y, fb[4]);
+    const float bz0 = fminf(X.z, fb[2]);
+    const float dx = cx - X.x, dy = cy - X.y;
+    const int own = sc.fsolid[f];
+    float bkey = INFINITY;
+    int bsol = -1;
+    for (int b0 = 0; b0 < sc.n_solids; b0 += kWave) {
+        const int sid = b0 + lane;
+        if (sid >= sc.n_solids || sid == own) continue;
+        bool listed = false;
+        for (int m = 0; m < nsc; ++m) listed |= scache[m] == sid;
+        if (listed) continue;
+        const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
+        if (!(bx1 > L.x && bx0 < H.x && by1 > L.y && by0 < H.y && bz0 < H.z && bz0 >= L.z)) continue;
+        float t0 = 0.f, t1 = 1.f;
+        if (dx != 0.f) {
+            const float a = (L.x - X.x) / dx, b = (H.x - X.x) / dx;
+            t0 = fmaxf(t0, fminf(a, b));
+            t1 = fminf(t1, fmaxf(a, b));
+        } else if (!(X.x > L.x && X.x < H.x)) {
+            continue;
+        }
+        if (dy != 0.f) {
+            const float a = (L.y - X.y) / dy, b = (H.y - X.y) / dy;
+            t0 = fmaxf(t0, fminf(a, b));
+            t1 = fminf(t1, fmaxf(a, b));
+        } else if (!(X.y > L.y && X.y < H.y)) {
+            continue;
+        }
+        if (!(t0 < t1)) continue;
+        const float key = fminf(t0, 1.f - t1);
+        if (key < bkey) {
+            bkey = key;
+            bsol = sid;
+        }
+    }
+    for (int tr = 0; tr < kScanTries; ++tr) {
+        const float kmin = wave_min(bkey);
+        if (!(kmin < INFINITY)) break;
+        const int src = __ffsll((long long)__ballot(bkey == kmin)) - 1;
+        const int sid = __shfl(bsol, src);
+        if (lane == src) bkey = INFINITY;
+        int slot;
+        if (nsc < kSolidCache) slot = nsc++;
+        else { slot = spos; spos = (spos + 1) % kSolidCache; }
+        scache[slot] = sid;
+        stage_solid(sc, sid, lds[slot]);
+        Cnt dummy;
+        const bool good = lane < nh && solid_segment(lds[slot], X, corner, gu, lane < nh ? c : dummy);
+        if (__ballot(lane < nh && !good) == 0ull) return true;
+    }
+    return false;
+}
+
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_points(PointJob one, const PointJob *many, int n_jobs,
                                                    long long n_items, TraverseOpts o, ivm_stats *st) {
@@ -1701,6 +1772,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     unsigned long long segs = 0, items = 0;
     int *cache = sList[wv], *scache = cache + kCache;  // wave-uniform lists in LDS
     int ncache = 0, cpos = 0, nmiss = 0, n_order = 0;
+    unsigned long long nsolidf = 0;  // (point, facet) pairs certified by a solid
     int nsc = 0, spos = 0;
     long long cur = -1;  // current (job, snapshot, side)
     int cur_job = 0;
@@ -1803,7 +1875,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 }
             }
         }
-        const unsigned long long nm = __ballot(need);
+        unsigned long long nm = __ballot(need);
+        // a facet left with misses: try to prove it blocked from X by a solid of the scene
+        if (nm && !o.exhaustive && sc.n_solids > 0 && sc.n_solids <= kScanMaxSolidsPoint) {
+            const int fl = sidx < sc.S ? sc.sfacet[sidx] : -1;
+            unsigned long long left = nm;
+            while (left) {
+                const int fc = __shfl(fl, __ffsll((long long)left) - 1);
+                left &= ~__ballot(need && fl == fc);
+                if (certify_point_facet(sc, fc, make_float4(xx, xy, xz, 0.f), sSL[wv], scache, nsc, spos, c)) {
+                    if (fl == fc) need = false;
+                    ++nsolidf;
+                }
+            }
+            nm = __ballot(need);
+        }
         if (nm) ++items;
         if (need) miss[nmiss + __popcll(nm & lt)] = sidx;
         nmiss += __popcll(nm);
@@ -1827,6 +1913,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
     }
     flush_counters(st, c, segs, 0, items);
+    if (st && lane == 0 && nsolidf) atomicAdd((unsigned long long *)&st->solid_certified, nsolidf);
 }
 
 __global__ __launch_bounds__(kBlock) void k_los(SceneDev sc, int N, const float *tx, const float *rx, uint8_t *los,
