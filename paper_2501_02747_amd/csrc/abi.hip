@@ -142,6 +142,10 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.solid = (const int4 *)(ws + L.sol_rec);
     d.splane = (const int4 *)(ws + L.sol_plane);
     d.sbox = (const float4 *)(ws + L.sol_box);
+    d.gridp = (const float4 *)(ws + L.grid_p);
+    d.gridi = (const int *)(ws + L.grid_p + sizeof(float4));
+    d.gcell_off = (const int *)(ws + L.grid_off);
+    d.gcell_list = (const int *)(ws + L.grid_list);
     d.n_solids = desc->facet_solid ? desc->n_solids : 0;
     sc.n_items = F * d.W;
     if (launch_build(sc, stream) != hipSuccess) {

@@ -22,6 +22,20 @@ constexpr int kSolidMaxTris = 128;    // triangles per solid group
 constexpr int kSolidMaxPlanes = 16;   // wall planes per solid
 constexpr int kConvexMaxTris = 16;    // triangles per facet considered by the convexity check
 
+// 2-D grid over the footprints of the verified solids (to find the solids a
+// segment passes over): G x G cells with G = clamp(ceil(sqrt(2 n_solids)), 1, 256);
+// a solid is listed in every cell its footprint box overlaps (up to
+// kGridMaxCellsPerSolid cells; larger solids are left out, which only costs
+// speed); at most kGridEntriesPerSolid * n_solids + 1024 entries, else the grid
+// is marked unusable and scans go over all solids.
+constexpr int kGridMaxCellsPerSolid = 256;
+constexpr int kGridEntriesPerSolid = 16;
+__host__ __device__ inline int solid_grid_dim(int n_solids) {
+    int g = 1;
+    while (g < 256 && g * g < 2 * n_solids) ++g;
+    return g;
+}
+
 // Per-facet flags (fflags).
 constexpr int kFacetConvex = 1;       // the facet's triangles tile one convex polygon
 
@@ -97,6 +111,10 @@ struct SceneDev {
                                // outside of wall k is d.y (x - u.x) - d.x (y - u.y) > 0
     int n_solids;
     const float4 *sbox;        // n_solids * 2: footprint box and (base, top) in .z, metres; empty if rejected
+    const float4 *gridp;       // (x0, y0, cell width, cell height) of the solid grid
+    const int *gridi;          // (G, usable, entries, 0)
+    const int *gcell_off;      // G * G + 1: CSR offsets of the cells' solid lists
+    const int *gcell_list;     // solid ids, sorted within each cell
 };
 
 // Workspace layout of one scene.
@@ -105,6 +123,7 @@ struct Layout {
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
     size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
     size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4, sol_box;
+    size_t grid_p, grid_cnt, grid_off, grid_list;
     size_t learned_bytes;
     size_t total;
 };

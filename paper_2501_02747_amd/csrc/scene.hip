@@ -73,6 +73,13 @@ Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
     L.sol_nver = take(sizeof(int));
     L.nodes4 = take(Tn * sizeof(Node4));
     L.sol_box = take(Ns * 2 * sizeof(float4));
+    {
+        const size_t G = (size_t)solid_grid_dim(n_solids > 0 ? n_solids : 1), ncell = G * G;
+        L.grid_p = take(2 * sizeof(float4));
+        L.grid_cnt = take(2 * ncell * sizeof(int));
+        L.grid_off = take((ncell + 1) * sizeof(int));
+        L.grid_list = take(((size_t)kGridEntriesPerSolid * Ns + 1024) * sizeof(int));
+    }
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));

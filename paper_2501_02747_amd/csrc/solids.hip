@@ -400,6 +400,89 @@ __global__ __launch_bounds__(64) void k_solid_verify(ivm_scene_desc d, const int
     }
 }
 
+// Grid extent from the verified solids' boxes (one block).
+__global__ __launch_bounds__(1024) void k_grid_extent(int ns, const float4 *sbox, int G, float4 *gridp, int *gridi) {
+    __shared__ float red[4][1024];
+    const int t = threadIdx.x;
+    float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+    for (int s = t; s < ns; s += 1024) {
+        const float4 lo = sbox[2 * s], hi = sbox[2 * s + 1];
+        if (lo.x <= hi.x) {
+            x0 = fminf(x0, lo.x); y0 = fminf(y0, lo.y);
+            x1 = fmaxf(x1, hi.x); y1 = fmaxf(y1, hi.y);
+        }
+    }
+    red[0][t] = x0; red[1][t] = y0; red[2][t] = -x1; red[3][t] = -y1;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 4; ++k) red[k][t] = fminf(red[k][t], red[k][t + w]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        const float a = red[0][0], b = red[1][0], c = -red[2][0], e = -red[3][0];
+        const bool ok = a <= c && b <= e;
+        const float cw = ok ? fmaxf((c - a) / G, 1e-3f) : 1.f, ch = ok ? fmaxf((e - b) / G, 1e-3f) : 1.f;
+        gridp[0] = make_float4(ok ? a : 0.f, ok ? b : 0.f, cw, ch);
+        gridi[0] = G;
+        gridi[1] = ok ? 1 : 0;
+        gridi[2] = 0;
+        gridi[3] = 0;
+    }
+}
+
+__device__ inline bool grid_cells(const float4 *gridp, int G, float4 lo, float4 hi, int &cx0, int &cx1, int &cy0,
+                                  int &cy1) {
+    const float4 gp = gridp[0];
+    cx0 = min(G - 1, max(0, (int)floorf((lo.x - gp.x) / gp.z)));
+    cx1 = min(G - 1, max(0, (int)floorf((hi.x - gp.x) / gp.z)));
+    cy0 = min(G - 1, max(0, (int)floorf((lo.y - gp.y) / gp.w)));
+    cy1 = min(G - 1, max(0, (int)floorf((hi.y - gp.y) / gp.w)));
+    return (cx1 - cx0 + 1) * (cy1 - cy0 + 1) <= kGridMaxCellsPerSolid;
+}
+
+// Count, then fill, the cells each verified solid's footprint box overlaps.
+__global__ void k_grid_insert(int ns, const float4 *sbox, const float4 *gridp, const int *gridi, const int *off,
+                              int *cnt, int *list, int cap) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns || !gridi[1]) return;
+    const float4 lo = sbox[2 * s], hi = sbox[2 * s + 1];
+    if (!(lo.x <= hi.x)) return;
+    const int G = gridi[0];
+    int cx0, cx1, cy0, cy1;
+    if (!grid_cells(gridp, G, lo, hi, cx0, cx1, cy0, cy1)) return;
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int cell = cy * G + cx;
+            if (!off) {
+                atomicAdd(&cnt[cell], 1);
+            } else {
+                const int pos = off[cell] + atomicAdd(&cnt[cell], 1);
+                if (pos < cap) list[pos] = s;
+            }
+        }
+}
+
+// Sort each cell's list (deterministic order) and mark the grid unusable on overflow.
+__global__ void k_grid_finish(int ncell, const int *off, int *list, int cap, int *gridi) {
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell == 0) {
+        gridi[2] = off[ncell];
+        if (off[ncell] > cap) gridi[1] = 0;
+    }
+    if (cell >= ncell || off[ncell] > cap) return;
+    const int a = off[cell], b = off[cell + 1];
+    for (int m = a + 1; m < b; ++m) {
+        const int x = list[m];
+        int k = m - 1;
+        while (k >= a && list[k] > x) {
+            list[k + 1] = list[k];
+            --k;
+        }
+        list[k + 1] = x;
+    }
+}
+
 __global__ void k_fill_i32(int *p, int v, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -434,6 +517,23 @@ hipError_t launch_solids(Scene &sc, hipStream_t s) {
         hipLaunchKernelGGL(k_solid_verify, dim3(ns), dim3(64), 0, s, d, ffirst, fplane, (const int *)off,
                            (const int *)fac, (int4 *)(ws + L.sol_rec), (int4 *)(ws + L.sol_plane),
                            (float4 *)(ws + L.sol_box), fsolid, nver);
+        // grid over the verified solids' footprints
+        const int G = solid_grid_dim(ns), ncell = G * G, cap = kGridEntriesPerSolid * ns + 1024;
+        float4 *gridp = (float4 *)(ws + L.grid_p);
+        int *gridi = (int *)(ws + L.grid_p + sizeof(float4));
+        int *gcnt = (int *)(ws + L.grid_cnt), *goff = (int *)(ws + L.grid_off), *glist = (int *)(ws + L.grid_list);
+        const float4 *sbox = (const float4 *)(ws + L.sol_box);
+        hipLaunchKernelGGL(k_grid_extent, dim3(1), dim3(1024), 0, s, ns, sbox, G, gridp, gridi);
+        hipLaunchKernelGGL(k_fill_i32, dim3(nblk(2 * ncell, 256)), dim3(256), 0, s, gcnt, 0, 2 * ncell);
+        hipLaunchKernelGGL(k_grid_insert, dim3(nblk(ns, 256)), dim3(256), 0, s, ns, sbox, (const float4 *)gridp,
+                           (const int *)gridi, (const int *)nullptr, gcnt, glist, cap);
+        hipLaunchKernelGGL(k_solid_scan, dim3(1), dim3(1024), 0, s, ncell, (const int *)gcnt, goff);
+        hipLaunchKernelGGL(k_grid_insert, dim3(nblk(ns, 256)), dim3(256), 0, s, ns, sbox, (const float4 *)gridp,
+                           (const int *)gridi, (const int *)goff, gcnt + ncell, glist, cap);
+        hipLaunchKernelGGL(k_grid_finish, dim3(nblk(ncell, 256)), dim3(256), 0, s, ncell, (const int *)goff, glist,
+                           cap, gridi);
+    } else {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int *)(ws + L.grid_p + sizeof(float4)), 0, 4);
     }
     return hipGetLastError();
 }

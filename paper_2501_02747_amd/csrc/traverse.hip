@@ -589,7 +589,8 @@ constexpr int kCache = 4;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
 constexpr int kScanMaxSolids = 4096;  // scenes with at most this many solids scan them all per pair
 constexpr int kScanTries = 4;         // solids from the scan tried per pair
-constexpr int kScanMaxSolidsPoint = 1024;  // the same scan per (point, facet) in the Tx/Rx kernel
+constexpr int kScanLinearMax = 256;   // up to this many solids a scan reads them all instead of the grid
+constexpr int kScanMaxSolidsPoint = 4096;  // the same scan per (point, facet) in the Tx/Rx kernel
 constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time (small jobs)
 constexpr int kPairChunkLarge = 32;       // ... when a wave has many pairs to do (better reuse)
 constexpr uint32_t kLargePerWave = 2048;  // candidate pairs per wave above which chunks are large
@@ -797,6 +798,67 @@ __device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u, Cnt &
         outQ |= __ballot(lane < nj && !(vb > 0.0)) == 0ull;
     }
     return outP && outQ;
+}
+
+// Candidate solids under the 2-D segment A -> B: the lanes split it into 64
+// pieces and visit the grid cells under each piece's box (all solids, 64 per
+// step, when there are few of them or the grid is unusable).  key_of(sid) ranks a solid (INFINITY rejects it); each lane
+// keeps its best.  Which solids are found only affects speed.
+template <class KeyOf>
+__device__ inline void scan_solids(const SceneDev &sc, float ax, float ay, float bx, float by, KeyOf key_of,
+                                   float &bkey, int &bsol) {
+    const int lane = lane_id();
+    bkey = INFINITY;
+    bsol = -1;
+    auto consider = [&](int sid) {
+        const float key = key_of(sid);
+        if (key < bkey) {
+            bkey = key;
+            bsol = sid;
+        }
+    };
+    if (sc.gridi[1] && sc.n_solids > kScanLinearMax) {
+        const float4 gp = sc.gridp[0];
+        const int G = sc.gridi[0];
+        const float t0 = (float)lane * (1.0f / kWave), t1 = (float)(lane + 1) * (1.0f / kWave);
+        const float xa = ax + (bx - ax) * t0, xb = ax + (bx - ax) * t1;
+        const float ya = ay + (by - ay) * t0, yb = ay + (by - ay) * t1;
+        const int cx0 = min(G - 1, max(0, (int)floorf((fminf(xa, xb) - gp.x) / gp.z)));
+        const int cx1 = min(G - 1, max(0, (int)floorf((fmaxf(xa, xb) - gp.x) / gp.z)));
+        const int cy0 = min(G - 1, max(0, (int)floorf((fminf(ya, yb) - gp.y) / gp.w)));
+        const int cy1 = min(G - 1, max(0, (int)floorf((fmaxf(ya, yb) - gp.y) / gp.w)));
+        for (int cy = cy0; cy <= cy1; ++cy)
+            for (int cx = cx0; cx <= cx1; ++cx) {
+                const int cell = cy * G + cx;
+                const int e1 = sc.gcell_off[cell + 1];
+                for (int e = sc.gcell_off[cell]; e < e1; ++e) consider(sc.gcell_list[e]);
+            }
+    } else {
+        for (int b0 = 0; b0 < sc.n_solids; b0 += kWave)
+            if (b0 + lane < sc.n_solids) consider(b0 + lane);
+    }
+}
+
+// Key of a solid for the segment A -> B: how near either end its footprint box
+// starts along the segment (INFINITY if the 2-D segment misses the box).
+__device__ inline float segment_box_key(float ax, float ay, float bx, float by, float4 L, float4 H) {
+    const float dx = bx - ax, dy = by - ay;
+    float t0 = 0.f, t1 = 1.f;
+    if (dx != 0.f) {
+        const float a = (L.x - ax) / dx, b = (H.x - ax) / dx;
+        t0 = fmaxf(t0, fminf(a, b));
+        t1 = fminf(t1, fmaxf(a, b));
+    } else if (!(ax > L.x && ax < H.x)) {
+        return INFINITY;
+    }
+    if (dy != 0.f) {
+        const float a = (L.y - ay) / dy, b = (H.y - ay) / dy;
+        t0 = fmaxf(t0, fminf(a, b));
+        t1 = fminf(t1, fmaxf(a, b));
+    } else if (!(ay > L.y && ay < H.y)) {
+        return INFINITY;
+    }
+    return t0 < t1 ? fminf(t0, 1.f - t1) : INFINITY;
 }
 
 // Whole pair: one lane per pair of hull corners (at most 8 x 8).  `reach` gets
@@ -1179,49 +1241,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 const float cpz = wave_sum(okp ? p.z : 0.f) / np;
                 const float cqx = wave_sum(okq ? q.x : 0.f) / nq, cqy = wave_sum(okq ? q.y : 0.f) / nq;
                 const float cqz = wave_sum(okq ? q.z : 0.f) / nq;
-                const float dx = cqx - cpx, dy = cqy - cpy;
                 const int own_i = sc.fsolid[i], own_j = sc.fsolid[j];
-                float bkey = INFINITY;
-                int bsol = -1;
-                for (int b0 = 0; b0 < sc.n_solids; b0 += kWave) {
-                    const int sid = b0 + lane;
-                    if (sid >= sc.n_solids || sid == own_i || sid == own_j) continue;
-                    bool listed = false;
-                    for (int m = 0; m < nsol; ++m) listed |= solids[m] == sid;
-                    if (listed) continue;
-                    const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
-                    if (!(hi[0] > L.x && lo[0] < H.x && hi[1] > L.y && lo[1] < H.y && fminf(cpz, cqz) < H.z &&
-                          lo[2] >= L.z))
-                        continue;
-                    float t0 = 0.f, t1 = 1.f;
-                    if (dx != 0.f) {
-                        const float a = (L.x - cpx) / dx, b = (H.x - cpx) / dx;
-                        t0 = fmaxf(t0, fminf(a, b));
-                        t1 = fminf(t1, fmaxf(a, b));
-                    } else if (!(cpx > L.x && cpx < H.x)) {
-                        continue;
-                    }
-                    if (dy != 0.f) {
-                        const float a = (L.y - cpy) / dy, b = (H.y - cpy) / dy;
-                        t0 = fmaxf(t0, fminf(a, b));
-                        t1 = fminf(t1, fmaxf(a, b));
-                    } else if (!(cpy > L.y && cpy < H.y)) {
-                        continue;
-                    }
-                    if (!(t0 < t1)) continue;
-                    const float key = fminf(t0, 1.f - t1);
-                    if (key < bkey) {
-                        bkey = key;
-                        bsol = sid;
-                    }
-                }
+                const float zlow = fminf(cpz, cqz);
+                float bkey;
+                int bsol;
+                scan_solids(
+                    sc, cpx, cpy, cqx, cqy,
+                    [&](int sid) -> float {
+                        if (sid == own_i || sid == own_j) return INFINITY;
+                        for (int m = 0; m < nsol; ++m)
+                            if (solids[m] == sid) return INFINITY;
+                        const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
+                        if (!(hi[0] > L.x && lo[0] < H.x && hi[1] > L.y && lo[1] < H.y && zlow < H.z && lo[2] >= L.z))
+                            return INFINITY;
+                        return segment_box_key(cpx, cpy, cqx, cqy, L, H);
+                    },
+                    bkey, bsol);
                 for (int tr = 0; tr < kScanTries && !early; ++tr) {
                     const float kmin = wave_min(bkey);
                     if (!(kmin < INFINITY)) break;
                     const unsigned long long win = __ballot(bkey == kmin);
                     const int src = __ffsll((long long)win) - 1;
                     const int sid = __shfl(bsol, src);
-                    if (lane == src) bkey = INFINITY;
+                    if (bsol == sid) bkey = INFINITY;  // every lane holding it drops it
                     int slot;
                     if (nsol < kSolidTries) slot = nsol++;
                     else { slot = sspos; sspos = (sspos + 1) % kSolidTries; }
@@ -1698,46 +1740,26 @@ __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLd
     const float cx = 0.5f * (fb[0] + fb[3]), cy = 0.5f * (fb[1] + fb[4]);
     const float bx0 = fminf(X.x, fb[0]), bx1 = fmaxf(X.x, fb[3]), by0 = fminf(X.y, fb[1]), by1 = fmaxf(X.y, fb[4]);
     const float bz0 = fminf(X.z, fb[2]);
-    const float dx = cx - X.x, dy = cy - X.y;
     const int own = sc.fsolid[f];
-    float bkey = INFINITY;
-    int bsol = -1;
-    for (int b0 = 0; b0 < sc.n_solids; b0 += kWave) {
-        const int sid = b0 + lane;
-        if (sid >= sc.n_solids || sid == own) continue;
-        bool listed = false;
-        for (int m = 0; m < nsc; ++m) listed |= scache[m] == sid;
-        if (listed) continue;
-        const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
-        if (!(bx1 > L.x && bx0 < H.x && by1 > L.y && by0 < H.y && bz0 < H.z && bz0 >= L.z)) continue;
-        float t0 = 0.f, t1 = 1.f;
-        if (dx != 0.f) {
-            const float a = (L.x - X.x) / dx, b = (H.x - X.x) / dx;
-            t0 = fmaxf(t0, fminf(a, b));
-            t1 = fminf(t1, fmaxf(a, b));
-        } else if (!(X.x > L.x && X.x < H.x)) {
-            continue;
-        }
-        if (dy != 0.f) {
-            const float a = (L.y - X.y) / dy, b = (H.y - X.y) / dy;
-            t0 = fmaxf(t0, fminf(a, b));
-            t1 = fminf(t1, fmaxf(a, b));
-        } else if (!(X.y > L.y && X.y < H.y)) {
-            continue;
-        }
-        if (!(t0 < t1)) continue;
-        const float key = fminf(t0, 1.f - t1);
-        if (key < bkey) {
-            bkey = key;
-            bsol = sid;
-        }
-    }
+    float bkey;
+    int bsol;
+    scan_solids(
+        sc, X.x, X.y, cx, cy,
+        [&](int sid) -> float {
+            if (sid == own) return INFINITY;
+            for (int m = 0; m < nsc; ++m)
+                if (scache[m] == sid) return INFINITY;
+            const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
+            if (!(bx1 > L.x && bx0 < H.x && by1 > L.y && by0 < H.y && bz0 < H.z && bz0 >= L.z)) return INFINITY;
+            return segment_box_key(X.x, X.y, cx, cy, L, H);
+        },
+        bkey, bsol);
     for (int tr = 0; tr < kScanTries; ++tr) {
         const float kmin = wave_min(bkey);
         if (!(kmin < INFINITY)) break;
         const int src = __ffsll((long long)__ballot(bkey == kmin)) - 1;
         const int sid = __shfl(bsol, src);
-        if (lane == src) bkey = INFINITY;
+        if (bsol == sid) bkey = INFINITY;  // every lane holding it drops it
         int slot;
         if (nsc < kSolidCache) slot = nsc++;
         else { slot = spos; spos = (spos + 1) % kSolidCache; }
