@@ -344,9 +344,9 @@ __device__ int any_hit_wave(const SceneDev &sc, Seg s, bool active, int exA, int
                     cswap(a1, b1, a3, b3);
                     cswap(a1, b1, a2, b2);
                     ref = nh > 0 ? b0 : kNone;
-                    const int pend[3] = {b3, b2, b1};
-                    for (int q = 4 - nh; q < 3 && res == -3; ++q) {
-                        const int farc = pend[q];
+                    // (no array here: a dynamically indexed one would live in scratch memory)
+                    auto push = [&](int farc) {
+                        if (res != -3) return;
                         if (sp < depth) {
                             stk[(sp++) * kWave] = farc;
                         } else {
@@ -363,7 +363,10 @@ __device__ int any_hit_wave(const SceneDev &sc, Seg s, bool active, int exA, int
                             const int h = test_range(sc, s, first, count, exA, exB, eps6, f64, c);
                             if (h >= 0) res = h;
                         }
-                    }
+                    };
+                    if (nh >= 4) push(b3);
+                    if (nh >= 3) push(b2);
+                    if (nh >= 2) push(b1);
                 } else {
                     const int h = test_range(sc, s, leaf_first(ref), leaf_count(ref), exA, exB, eps6, f64, c);
                     if (h >= 0) res = h;
@@ -871,8 +874,9 @@ __device__ bool certify_solid(const SolidLds &S, const HullLds &H, double u, Cnt
     const int lane = lane_id();
     const bool act = lane < ni * nj;
     const int a = act ? lane / nj : 0, b = act ? lane - (lane / nj) * nj : 0;
-    Cnt dummy;
-    const bool good = solid_segment(S, H.hc[a], H.hc[kHullMax + b], u, act ? c : dummy);
+    Cnt tmp;  // (a per-lane choice between two counter objects would force them into scratch)
+    const bool good = solid_segment(S, H.hc[a], H.hc[kHullMax + b], u, tmp);
+    if (act) c.solid_planes += tmp.solid_planes;
     if (reach) *reach = __ballot(act && good) != 0ull;
     return __ballot(act && !good) == 0ull;
 }
@@ -1765,8 +1769,9 @@ __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLd
         else { slot = spos; spos = (spos + 1) % kSolidCache; }
         scache[slot] = sid;
         stage_solid(sc, sid, lds[slot]);
-        Cnt dummy;
-        const bool good = lane < nh && solid_segment(lds[slot], X, corner, gu, lane < nh ? c : dummy);
+        Cnt tmp;
+        const bool good = lane < nh && solid_segment(lds[slot], X, corner, gu, tmp);
+        c.solid_planes += tmp.solid_planes;
         if (__ballot(lane < nh && !good) == 0ull) return true;
     }
     return false;
