@@ -28,17 +28,17 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 non-packed FP32 lane-ops/s
 # (one FMA = one lane-op; 78.6 TFLOP/s counting an FMA as two).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# algorithmic work per counted unit (VALU lane-ops): a node visit tests two child
-# boxes (2 x 14), a segment/triangle test ~43 (Moller-Trumbore 33 + filter 10),
+# algorithmic work per counted unit (VALU lane-ops): a segment/box slab test 14
+# (three slabs: six products, six min/max, the entry/exit compare), a segment/triangle test ~43 (Moller-Trumbore 33 + filter 10),
 # an FP64 recheck ~35 more, one face-plane step of an exact solid test ~25 FP64
 # ops (two plane values, the interval update with an exact product compare;
 # MI355X issues FP64 vector ops at one per lane per clock, the rate the peak
 # below counts).
-OPS_NODE, OPS_TRI, OPS_RECHECK, OPS_SOLID_PLANE = 28, 43, 35, 25
+OPS_BOX, OPS_TRI, OPS_RECHECK, OPS_SOLID_PLANE = 14, 43, 35, 25
 
 
 def lane_ops(st: dict) -> int:
-    return (st["node_visits"] * OPS_NODE + st["tri_tests"] * OPS_TRI + st["rechecks"] * OPS_RECHECK
+    return (st["box_tests"] * OPS_BOX + st["tri_tests"] * OPS_TRI + st["rechecks"] * OPS_RECHECK
             + st["solid_planes"] * OPS_SOLID_PLANE)
 
 WORKLOADS = {
@@ -387,7 +387,7 @@ def main():
             "order": other, "matrix_ms": statistics.median(times),
             "queries_per_s": n_pairs / (statistics.median(times) / 1e3),
             "k_pairs_ms": t_pairs.elapsed_ms(), "identical_bits": bool(torch.equal(M, M2)),
-            "node_visits": so["node_visits"], "tri_tests": so["tri_tests"], "segments": so["segments"],
+            "box_tests": so["box_tests"], "tri_tests": so["tri_tests"], "segments": so["segments"],
             "certified": so["certified"],
             "note": "learned = network inference (in the matrix call) + learned treelet order",
         }

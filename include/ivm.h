@@ -127,8 +127,8 @@ typedef struct ivm_scene_info_t {
 } ivm_scene_info_t;
 
 /* Device-side counters, accumulated by the hot calls (the caller zeroes them).
- * segments: segments traversed; node_visits: internal BVH nodes whose child
- * boxes were tested; tri_tests: segment/triangle tests; rechecks: tests whose
+ * segments: segments traversed; box_tests: segment/box slab tests (treelet
+ * boxes and BVH child boxes); tri_tests: segment/triangle tests; rechecks: tests whose
  * FP32 margin was too small and which were decided in FP64; fallbacks: subtrees
  * scanned linearly because the traversal stack was full; certified: pairs
  * decided blocked by the single-occluder test on sample-hull corners. */
@@ -137,7 +137,7 @@ typedef struct ivm_stats {
     uint64_t pairs_candidate;
     uint64_t pairs_visible;
     uint64_t segments;
-    uint64_t node_visits;
+    uint64_t box_tests;
     uint64_t tri_tests;
     uint64_t rechecks;
     uint64_t fallbacks;

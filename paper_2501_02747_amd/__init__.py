@@ -86,7 +86,7 @@ class ivm_matrix_opts(ctypes.Structure):
     ]
 
 
-STATS_FIELDS = ["pairs_total", "pairs_candidate", "pairs_visible", "segments", "node_visits",
+STATS_FIELDS = ["pairs_total", "pairs_candidate", "pairs_visible", "segments", "box_tests",
                 "tri_tests", "rechecks", "fallbacks", "point_items", "flags", "certified",
                 "subpair_runs", "tiled_pairs", "solid_certified", "traversed", "solid_segments", "solid_planes"]
 STATS_WORDS = 20

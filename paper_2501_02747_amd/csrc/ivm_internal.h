@@ -64,7 +64,7 @@ constexpr int kNoRef = 0x7fffffff;
 struct __align__(16) Node4 {
     float4 lox, loy, loz, hix, hiy, hiz;
     int4 ref;   // >= 0 binary internal node (and its record); < 0 leaf; kNoRef empty
-    int4 pad;
+    int4 pad;   // .x = slots used (2..4), for the box-test counter
 };
 
 __host__ __device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }

@@ -596,6 +596,7 @@ __global__ void k_wide(int T, const Node *nodes, Node4 *nodes4) {
     if (x >= T) return;
     float lo[3][4], hi[3][4];
     int ref[4];
+    int n = 0;  // slots used
     for (int q = 0; q < 4; ++q) {
         ref[q] = kNoRef;
         for (int k = 0; k < 3; ++k) {
@@ -608,7 +609,6 @@ __global__ void k_wide(int T, const Node *nodes, Node4 *nodes4) {
         const int cref[2] = {nd.d.x, nd.d.y};
         const float cb[2][6] = {{nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y},
                                 {nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w}};
-        int n = 0;
         for (int h = 0; h < 2; ++h) {
             if (cref[h] < 0) {  // a leaf child stands for itself
                 ref[n] = cref[h];
@@ -641,7 +641,7 @@ __global__ void k_wide(int T, const Node *nodes, Node4 *nodes4) {
     w.hiy = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
     w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
     w.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
-    w.pad = make_int4(0, 0, 0, 0);
+    w.pad = make_int4(n, 0, 0, 0);
     nodes4[x] = w;
 }
 

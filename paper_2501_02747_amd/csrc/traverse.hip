@@ -186,7 +186,7 @@ __device__ inline bool tri_hit(const Seg &s, float4 A, float4 B, float4 C, float
 }
 
 struct Cnt {
-    unsigned visits = 0, tests = 0, rechecks = 0, fallbacks = 0, traversed = 0, solid_segs = 0, solid_planes = 0;
+    unsigned boxes = 0, tests = 0, rechecks = 0, fallbacks = 0, traversed = 0, solid_segs = 0, solid_planes = 0;
 };
 
 __device__ inline int test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
@@ -225,6 +225,7 @@ __device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr ord
                     if (root == kNone) continue;  // empty treelet: its inverted box must never be entered
                     const float *b = sc.tl_box + 6 * k;
                     float te;
+                    ++c.boxes;
                     if (seg_box(s, b[0], b[1], b[2], b[3], b[4], b[5], te)) {
                         ref = root;
                         break;
@@ -234,7 +235,7 @@ __device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr ord
             }
         }
         if (ref >= 0) {
-            ++c.visits;
+            c.boxes += 2;
             const Node nd = sc.nodes[ref];
             float t0, t1;
             const bool h0 = seg_box(s, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, t0);
@@ -306,6 +307,7 @@ __device__ int any_hit_wave(const SceneDev &sc, Seg s, bool active, int exA, int
                         if (root == kNone) continue;  // empty treelet: its inverted box must never be entered
                         const float *b = sc.tl_box + 6 * k;
                         float te;
+                        ++c.boxes;
                         if (seg_box(s, b[0], b[1], b[2], b[3], b[4], b[5], te)) {
                             ref = root;
                             break;
@@ -318,10 +320,10 @@ __device__ int any_hit_wave(const SceneDev &sc, Seg s, bool active, int exA, int
                 if (ref >= 0) {
                     // a 4-wide record: test the up-to-four children, descend into the
                     // nearest, push the others far to near
-                    ++c.visits;
                     const Node4 nd = sc.nodes4[ref];
                     float a0, a1, a2, a3;
                     int b0 = nd.ref.x, b1 = nd.ref.y, b2 = nd.ref.z, b3 = nd.ref.w;
+                    c.boxes += nd.pad.x;
                     const bool h0 = b0 != kNone && seg_box(s, nd.lox.x, nd.loy.x, nd.loz.x, nd.hix.x, nd.hiy.x, nd.hiz.x, a0);
                     const bool h1 = b1 != kNone && seg_box(s, nd.lox.y, nd.loy.y, nd.loz.y, nd.hix.y, nd.hiy.y, nd.hiz.y, a1);
                     const bool h2 = b2 != kNone && seg_box(s, nd.lox.z, nd.loy.z, nd.loz.z, nd.hix.z, nd.hiy.z, nd.hiz.z, a2);
@@ -549,7 +551,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 __device__ inline void flush_counters(ivm_stats *st, const Cnt &c, unsigned long long segs,
                                       unsigned long long visible, unsigned long long items) {
     if (!st) return;
-    const unsigned long long v = wave_sum_u64(c.visits), t = wave_sum_u64(c.tests);
+    const unsigned long long v = wave_sum_u64(c.boxes), t = wave_sum_u64(c.tests);
     const unsigned long long r = wave_sum_u64(c.rechecks), f = wave_sum_u64(c.fallbacks);
     const unsigned long long sg = wave_sum_u64(segs);
     const unsigned long long tv = wave_sum_u64(c.traversed), ss = wave_sum_u64(c.solid_segs);
@@ -558,7 +560,7 @@ __device__ inline void flush_counters(ivm_stats *st, const Cnt &c, unsigned long
         if (tv) atomicAdd((unsigned long long *)&st->traversed, tv);
         if (ss) atomicAdd((unsigned long long *)&st->solid_segments, ss);
         if (sp) atomicAdd((unsigned long long *)&st->solid_planes, sp);
-        atomicAdd((unsigned long long *)&st->node_visits, v);
+        atomicAdd((unsigned long long *)&st->box_tests, v);
         atomicAdd((unsigned long long *)&st->tri_tests, t);
         atomicAdd((unsigned long long *)&st->rechecks, r);
         atomicAdd((unsigned long long *)&st->fallbacks, f);
@@ -762,6 +764,39 @@ __device__ inline bool solid_segment(const SolidLds &S, float4 P, float4 Q, doub
     return solid_segment(S, P.x * u, P.y * u, P.z * u, Q.x * u, Q.y * u, Q.z * u, c);
 }
 
+// The same test reading solid `sid` from global memory (each lane may test its
+// own solid): a necessary condition checked before staging a candidate.
+__device__ __forceinline__ bool solid_segment_global(const SceneDev &sc, int sid, float4 P, float4 Q, Cnt &c) {
+    const double u = ldexp(1.0, sc.gs);
+    const double px = P.x * u, py = P.y * u, pz = P.z * u, qx = Q.x * u, qy = Q.y * u, qz = Q.z * u;
+    const int4 R = sc.solid[sid];
+    if (R.x <= 0 || !(pz >= (double)R.z && qz >= (double)R.z)) return false;
+    double Ln = 0.0, Ld = 1.0, Un = 1.0, Ud = 1.0;
+    bool pout = false;
+    for (int k = 0; k <= R.x; ++k) {
+        ++c.solid_planes;
+        double va, vb;
+        if (k < R.x) {
+            const int4 pl = sc.splane[sid * kSolidMaxPlanes + k];
+            va = (double)pl.w * (px - (double)pl.x) - (double)pl.z * (py - (double)pl.y);
+            vb = (double)pl.w * (qx - (double)pl.x) - (double)pl.z * (qy - (double)pl.y);
+        } else {
+            va = pz - (double)R.y;
+            vb = qz - (double)R.y;
+        }
+        if (va >= 0.0 && vb >= 0.0) return false;
+        pout |= va > 0.0;
+        if (va >= 0.0) {
+            const double n = va, dd = va - vb;
+            if (prod_less(Ln, dd, n, Ld)) { Ln = n; Ld = dd; }
+        } else if (vb >= 0.0) {
+            const double n = -va, dd = vb - va;
+            if (prod_less(n, Ud, Un, dd)) { Un = n; Ud = dd; }
+        }
+    }
+    return pout && prod_less(Ln, Ud, Un, Ld);
+}
+
 // The sample hulls of a pair staged in LDS: hc[0, 8) facet i, hc[8, 16) facet j;
 // cc[(side * 4 + cluster) * kHullMax + k] the cluster hulls, ccn their sizes.
 struct HullLds {
@@ -807,15 +842,15 @@ __device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u, Cnt &
 // pieces and visit the grid cells under each piece's box (all solids, 64 per
 // step, when there are few of them or the grid is unusable).  key_of(sid) ranks a solid (INFINITY rejects it); each lane
 // keeps its best.  Which solids are found only affects speed.
-template <class KeyOf>
+template <class KeyOf, class Accept>
 __device__ inline void scan_solids(const SceneDev &sc, float ax, float ay, float bx, float by, KeyOf key_of,
-                                   float &bkey, int &bsol) {
+                                   Accept accept, float &bkey, int &bsol) {
     const int lane = lane_id();
     bkey = INFINITY;
     bsol = -1;
     auto consider = [&](int sid) {
         const float key = key_of(sid);
-        if (key < bkey) {
+        if (key < bkey && accept(sid)) {
             bkey = key;
             bsol = sid;
         }
@@ -1227,6 +1262,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             // only solids whose box reaches the segment box; a solid that certifies
             // the pair moves to the front of the wave's list
             unsigned reach_sub = 0u;
+            const float4 Pm = sP[wv][np >> 1], Qm = sQ[wv][nq >> 1];
             for (int m = 0; m < nsol && !early; ++m) {
                 if (!solid_box_reach(sSL[wv][m], lo, hi)) continue;
                 if (!hulls) {
@@ -1260,7 +1296,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                             return INFINITY;
                         return segment_box_key(cpx, cpy, cqx, cqy, L, H);
                     },
+                    // a solid that certifies the pair blocks every admissible segment, so also
+                    // the one between the middle admissible samples (tested for a lane's
+                    // best candidate so far only)
+                    [](int) -> bool { return true; },
                     bkey, bsol);
+                if (bsol >= 0 && !solid_segment_global(sc, bsol, Pm, Qm, c)) bkey = INFINITY;
                 for (int tr = 0; tr < kScanTries && !early; ++tr) {
                     const float kmin = wave_min(bkey);
                     if (!(kmin < INFINITY)) break;
@@ -1740,6 +1781,7 @@ __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLd
     if (nh == 0) return false;
     const double gu = ldexp(1.0, sc.gs);
     const float4 corner = sc.smp[sc.fhull[kHullMax * f + (lane < nh ? lane : 0)]];
+    const float4 corner0 = sc.smp[sc.fhull[kHullMax * f]];
     const float *fb = sc.fbox + 6 * f;
     const float cx = 0.5f * (fb[0] + fb[3]), cy = 0.5f * (fb[1] + fb[4]);
     const float bx0 = fminf(X.x, fb[0]), bx1 = fmaxf(X.x, fb[3]), by0 = fminf(X.y, fb[1]), by1 = fmaxf(X.y, fb[4]);
@@ -1757,7 +1799,10 @@ __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLd
             if (!(bx1 > L.x && bx0 < H.x && by1 > L.y && by0 < H.y && bz0 < H.z && bz0 >= L.z)) return INFINITY;
             return segment_box_key(X.x, X.y, cx, cy, L, H);
         },
+        // a certifying solid blocks the segment to the first hull corner in particular
+        [](int) -> bool { return true; },
         bkey, bsol);
+    if (bsol >= 0 && !solid_segment_global(sc, bsol, X, corner0, c)) bkey = INFINITY;
     for (int tr = 0; tr < kScanTries; ++tr) {
         const float kmin = wave_min(bkey);
         if (!(kmin < INFINITY)) break;

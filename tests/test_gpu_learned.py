@@ -167,7 +167,7 @@ def test_learned_order_keeps_every_bit(oracle_mod, ivm, weights):
     assert (ivm.unpack_bits(Ml, s.n_facets) == Mo).all()
     dl, dp = ivm.stats_dict(st_l), ivm.stats_dict(st_p)
     assert dl["flags"] == 0
-    _log(f"[learned {weights}] visits {dl['node_visits']} vs plain {dp['node_visits']}, "
+    _log(f"[learned {weights}] box tests {dl['box_tests']} vs plain {dp['box_tests']}, "
          f"tests {dl['tri_tests']} vs {dp['tri_tests']}")
 
 
