@@ -146,6 +146,7 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.gridi = (const int *)(ws + L.grid_p + sizeof(float4));
     d.gcell_off = (const int *)(ws + L.grid_off);
     d.gcell_list = (const int *)(ws + L.grid_list);
+    d.gcell_ent = (const float4 *)(ws + L.grid_ent);
     d.n_solids = desc->facet_solid ? desc->n_solids : 0;
     sc.n_items = F * d.W;
     if (launch_build(sc, stream) != hipSuccess) {

@@ -115,6 +115,8 @@ struct SceneDev {
     const int *gridi;          // (G, usable, entries, 0)
     const int *gcell_off;      // G * G + 1: CSR offsets of the cells' solid lists
     const int *gcell_list;     // solid ids, sorted within each cell
+    const float4 *gcell_ent;   // the same entries with the solid's footprint box inline: 2 float4 each,
+                               // (lo.x, lo.y, lo.z, id as int bits), (hi.x, hi.y, hi.z, 0)
 };
 
 // Workspace layout of one scene.
@@ -123,7 +125,7 @@ struct Layout {
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
     size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
     size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4, sol_box;
-    size_t grid_p, grid_cnt, grid_off, grid_list;
+    size_t grid_p, grid_cnt, grid_off, grid_list, grid_ent;
     size_t learned_bytes;
     size_t total;
 };

@@ -79,6 +79,7 @@ Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
         L.grid_cnt = take(2 * ncell * sizeof(int));
         L.grid_off = take((ncell + 1) * sizeof(int));
         L.grid_list = take(((size_t)kGridEntriesPerSolid * Ns + 1024) * sizeof(int));
+        L.grid_ent = take(((size_t)kGridEntriesPerSolid * Ns + 1024) * 2 * sizeof(float4));
     }
     L.cand = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));

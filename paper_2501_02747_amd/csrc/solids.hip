@@ -434,10 +434,11 @@ __global__ __launch_bounds__(1024) void k_grid_extent(int ns, const float4 *sbox
 __device__ inline bool grid_cells(const float4 *gridp, int G, float4 lo, float4 hi, int &cx0, int &cx1, int &cy0,
                                   int &cy1) {
     const float4 gp = gridp[0];
-    cx0 = min(G - 1, max(0, (int)floorf((lo.x - gp.x) / gp.z)));
-    cx1 = min(G - 1, max(0, (int)floorf((hi.x - gp.x) / gp.z)));
-    cy0 = min(G - 1, max(0, (int)floorf((lo.y - gp.y) / gp.w)));
-    cy1 = min(G - 1, max(0, (int)floorf((hi.y - gp.y) / gp.w)));
+    const float icw = 1.0f / gp.z, ich = 1.0f / gp.w;  // the lookup computes cells the same way
+    cx0 = min(G - 1, max(0, (int)floorf((lo.x - gp.x) * icw)));
+    cx1 = min(G - 1, max(0, (int)floorf((hi.x - gp.x) * icw)));
+    cy0 = min(G - 1, max(0, (int)floorf((lo.y - gp.y) * ich)));
+    cy1 = min(G - 1, max(0, (int)floorf((hi.y - gp.y) * ich)));
     return (cx1 - cx0 + 1) * (cy1 - cy0 + 1) <= kGridMaxCellsPerSolid;
 }
 
@@ -481,6 +482,17 @@ __global__ void k_grid_finish(int ncell, const int *off, int *list, int cap, int
         }
         list[k + 1] = x;
     }
+}
+
+// The cell entries with each solid's footprint box inline (one load per entry in
+// the scans instead of an id and then a box).
+__global__ void k_grid_entries(int cap, const int *list, const float4 *sbox, const int *gridi, float4 *ent) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cap || !gridi[1] || e >= gridi[2]) return;
+    const int s = list[e];
+    const float4 lo = sbox[2 * s], hi = sbox[2 * s + 1];
+    ent[2 * e] = make_float4(lo.x, lo.y, lo.z, __int_as_float(s));
+    ent[2 * e + 1] = make_float4(hi.x, hi.y, hi.z, 0.f);
 }
 
 __global__ void k_fill_i32(int *p, int v, int n) {
@@ -532,6 +544,8 @@ hipError_t launch_solids(Scene &sc, hipStream_t s) {
                            (const int *)gridi, (const int *)goff, gcnt + ncell, glist, cap);
         hipLaunchKernelGGL(k_grid_finish, dim3(nblk(ncell, 256)), dim3(256), 0, s, ncell, (const int *)goff, glist,
                            cap, gridi);
+        hipLaunchKernelGGL(k_grid_entries, dim3(nblk(cap, 256)), dim3(256), 0, s, cap, (const int *)glist, sbox,
+                           (const int *)gridi, (float4 *)(ws + L.grid_ent));
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int *)(ws + L.grid_p + sizeof(float4)), 0, 4);
     }

@@ -838,18 +838,18 @@ __device__ bool solid_sides(const SolidLds &S, const HullLds &H, double u, Cnt &
     return outP && outQ;
 }
 
-// Candidate solids under the 2-D segment A -> B: the lanes split it into 64
-// pieces and visit the grid cells under each piece's box (all solids, 64 per
-// step, when there are few of them or the grid is unusable).  key_of(sid) ranks a solid (INFINITY rejects it); each lane
-// keeps its best.  Which solids are found only affects speed.
+// Candidate solids under the 2-D segment A -> B: the `npieces` lanes of a group
+// split it into pieces (this lane takes piece `piece`) and visit the grid cells
+// under each piece's box (all solids, npieces per step, when there are few of
+// them or the grid is unusable).  key_of(sid, lo, hi) ranks a solid from its
+// footprint box (INFINITY rejects it); each lane keeps its best.  Which solids are found only affects speed.
 template <class KeyOf, class Accept>
-__device__ inline void scan_solids(const SceneDev &sc, float ax, float ay, float bx, float by, KeyOf key_of,
-                                   Accept accept, float &bkey, int &bsol) {
-    const int lane = lane_id();
+__device__ inline void scan_solids(const SceneDev &sc, float ax, float ay, float bx, float by, int piece, int npieces,
+                                   KeyOf key_of, Accept accept, float &bkey, int &bsol) {
     bkey = INFINITY;
     bsol = -1;
-    auto consider = [&](int sid) {
-        const float key = key_of(sid);
+    auto consider = [&](int sid, float4 L, float4 H) {
+        const float key = key_of(sid, L, H);
         if (key < bkey && accept(sid)) {
             bkey = key;
             bsol = sid;
@@ -858,42 +858,63 @@ __device__ inline void scan_solids(const SceneDev &sc, float ax, float ay, float
     if (sc.gridi[1] && sc.n_solids > kScanLinearMax) {
         const float4 gp = sc.gridp[0];
         const int G = sc.gridi[0];
-        const float t0 = (float)lane * (1.0f / kWave), t1 = (float)(lane + 1) * (1.0f / kWave);
+        const float icw = 1.0f / gp.z, ich = 1.0f / gp.w;  // (cells are a heuristic filter too)
+        const float inv = 1.0f / (float)npieces;
+        const float t0 = (float)piece * inv, t1 = (float)(piece + 1) * inv;
         const float xa = ax + (bx - ax) * t0, xb = ax + (bx - ax) * t1;
         const float ya = ay + (by - ay) * t0, yb = ay + (by - ay) * t1;
-        const int cx0 = min(G - 1, max(0, (int)floorf((fminf(xa, xb) - gp.x) / gp.z)));
-        const int cx1 = min(G - 1, max(0, (int)floorf((fmaxf(xa, xb) - gp.x) / gp.z)));
-        const int cy0 = min(G - 1, max(0, (int)floorf((fminf(ya, yb) - gp.y) / gp.w)));
-        const int cy1 = min(G - 1, max(0, (int)floorf((fmaxf(ya, yb) - gp.y) / gp.w)));
+        const int cx0 = min(G - 1, max(0, (int)floorf((fminf(xa, xb) - gp.x) * icw)));
+        const int cx1 = min(G - 1, max(0, (int)floorf((fmaxf(xa, xb) - gp.x) * icw)));
+        const int cy0 = min(G - 1, max(0, (int)floorf((fminf(ya, yb) - gp.y) * ich)));
+        const int cy1 = min(G - 1, max(0, (int)floorf((fmaxf(ya, yb) - gp.y) * ich)));
         for (int cy = cy0; cy <= cy1; ++cy)
             for (int cx = cx0; cx <= cx1; ++cx) {
                 const int cell = cy * G + cx;
                 const int e1 = sc.gcell_off[cell + 1];
-                for (int e = sc.gcell_off[cell]; e < e1; ++e) consider(sc.gcell_list[e]);
+                for (int e = sc.gcell_off[cell]; e < e1; ++e) {
+                    const float4 L = sc.gcell_ent[2 * e], H = sc.gcell_ent[2 * e + 1];
+                    consider(__float_as_int(L.w), L, H);
+                }
             }
     } else {
-        for (int b0 = 0; b0 < sc.n_solids; b0 += kWave)
-            if (b0 + lane < sc.n_solids) consider(b0 + lane);
+        for (int b = piece; b < sc.n_solids; b += npieces) consider(b, sc.sbox[2 * b], sc.sbox[2 * b + 1]);
     }
 }
 
-// Key of a solid for the segment A -> B: how near either end its footprint box
-// starts along the segment (INFINITY if the 2-D segment misses the box).
-__device__ inline float segment_box_key(float ax, float ay, float bx, float by, float4 L, float4 H) {
-    const float dx = bx - ax, dy = by - ay;
+// The 2-D segment A -> B with its reciprocal direction, for ranking solids.
+struct Ray2 {
+    float ax, ay, ix, iy;  // ix = 1 / (bx - ax), 0 when the segment has no x extent
+    bool zx, zy;           // no x / y extent
+};
+
+__device__ inline Ray2 make_ray2(float ax, float ay, float bx, float by) {
+    Ray2 r;
+    r.ax = ax;
+    r.ay = ay;
+    r.zx = bx == ax;
+    r.zy = by == ay;
+    r.ix = r.zx ? 0.f : 1.0f / (bx - ax);
+    r.iy = r.zy ? 0.f : 1.0f / (by - ay);
+    return r;
+}
+
+// Key of a solid for the segment: how near either end its footprint box starts
+// along the segment (INFINITY if the 2-D segment misses the box).  A ranking
+// heuristic only: a certificate is always checked exactly afterwards.
+__device__ inline float segment_box_key(const Ray2 &r, float4 L, float4 H) {
     float t0 = 0.f, t1 = 1.f;
-    if (dx != 0.f) {
-        const float a = (L.x - ax) / dx, b = (H.x - ax) / dx;
+    if (!r.zx) {
+        const float a = (L.x - r.ax) * r.ix, b = (H.x - r.ax) * r.ix;
         t0 = fmaxf(t0, fminf(a, b));
         t1 = fminf(t1, fmaxf(a, b));
-    } else if (!(ax > L.x && ax < H.x)) {
+    } else if (!(r.ax > L.x && r.ax < H.x)) {
         return INFINITY;
     }
-    if (dy != 0.f) {
-        const float a = (L.y - ay) / dy, b = (H.y - ay) / dy;
+    if (!r.zy) {
+        const float a = (L.y - r.ay) * r.iy, b = (H.y - r.ay) * r.iy;
         t0 = fmaxf(t0, fminf(a, b));
         t1 = fminf(t1, fmaxf(a, b));
-    } else if (!(ay > L.y && ay < H.y)) {
+    } else if (!(r.ay > L.y && r.ay < H.y)) {
         return INFINITY;
     }
     return t0 < t1 ? fminf(t0, 1.f - t1) : INFINITY;
@@ -1283,18 +1304,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 const float cqz = wave_sum(okq ? q.z : 0.f) / nq;
                 const int own_i = sc.fsolid[i], own_j = sc.fsolid[j];
                 const float zlow = fminf(cpz, cqz);
+                const Ray2 ray = make_ray2(cpx, cpy, cqx, cqy);
                 float bkey;
                 int bsol;
                 scan_solids(
-                    sc, cpx, cpy, cqx, cqy,
-                    [&](int sid) -> float {
+                    sc, cpx, cpy, cqx, cqy, lane, kWave,
+                    [&](int sid, float4 L, float4 H) -> float {
+                        if (!(hi[0] > L.x && lo[0] < H.x && hi[1] > L.y && lo[1] < H.y && zlow < H.z && lo[2] >= L.z))
+                            return INFINITY;
                         if (sid == own_i || sid == own_j) return INFINITY;
                         for (int m = 0; m < nsol; ++m)
                             if (solids[m] == sid) return INFINITY;
-                        const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
-                        if (!(hi[0] > L.x && lo[0] < H.x && hi[1] > L.y && lo[1] < H.y && zlow < H.z && lo[2] >= L.z))
-                            return INFINITY;
-                        return segment_box_key(cpx, cpy, cqx, cqy, L, H);
+                        return segment_box_key(ray, L, H);
                     },
                     // a solid that certifies the pair blocks every admissible segment, so also
                     // the one between the middle admissible samples (tested for a lane's
@@ -1787,17 +1808,17 @@ __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLd
     const float bx0 = fminf(X.x, fb[0]), bx1 = fmaxf(X.x, fb[3]), by0 = fminf(X.y, fb[1]), by1 = fmaxf(X.y, fb[4]);
     const float bz0 = fminf(X.z, fb[2]);
     const int own = sc.fsolid[f];
+    const Ray2 ray = make_ray2(X.x, X.y, cx, cy);
     float bkey;
     int bsol;
     scan_solids(
-        sc, X.x, X.y, cx, cy,
-        [&](int sid) -> float {
+        sc, X.x, X.y, cx, cy, lane, kWave,
+        [&](int sid, float4 L, float4 H) -> float {
+            if (!(bx1 > L.x && bx0 < H.x && by1 > L.y && by0 < H.y && bz0 < H.z && bz0 >= L.z)) return INFINITY;
             if (sid == own) return INFINITY;
             for (int m = 0; m < nsc; ++m)
                 if (scache[m] == sid) return INFINITY;
-            const float4 L = sc.sbox[2 * sid], H = sc.sbox[2 * sid + 1];
-            if (!(bx1 > L.x && bx0 < H.x && by1 > L.y && by0 < H.y && bz0 < H.z && bz0 >= L.z)) return INFINITY;
-            return segment_box_key(X.x, X.y, cx, cy, L, H);
+            return segment_box_key(ray, L, H);
         },
         // a certifying solid blocks the segment to the first hull corner in particular
         [](int) -> bool { return true; },
@@ -1820,6 +1841,69 @@ __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLd
         if (__ballot(lane < nh && !good) == 0ull) return true;
     }
     return false;
+}
+
+// The same certificate for nf = 2..4 facets at once: lane group g (64 / 4 or
+// 64 / 2 lanes, aligned) scans and tests for facet f_g, the hull corners read
+// from global memory.  Returns bit g set when f_g is proven blocked from X;
+// sid_out holds, on the lanes of a certified group, the certifying solid.
+__device__ unsigned certify_point_facets(const SceneDev &sc, int nf, int f0, int f1, int f2, int f3, float4 X,
+                                         const int *scache, int nsc, int &sid_out, Cnt &c) {
+    const int lane = lane_id();
+    const int gs = nf <= 2 ? 32 : 16;               // lanes per group
+    const int g = lane / gs, r = lane - g * gs;
+    const unsigned long long gm = (gs == 32 ? 0xffffffffull : 0xffffull) << (g * gs);
+    const bool live = g < nf;
+    const int f = g == 0 ? f0 : (g == 1 ? f1 : (g == 2 ? f2 : f3));
+    const int fs = live ? f : f0;                    // (idle groups read facet f0's data)
+    const int nh = live ? sc.fhull_n[fs] : 0;
+    const float4 corner = sc.smp[sc.fhull[kHullMax * fs + (r < nh ? r : 0)]];
+    const float4 corner0 = sc.smp[sc.fhull[kHullMax * fs]];
+    const float *fb = sc.fbox + 6 * fs;
+    const float cx = 0.5f * (fb[0] + fb[3]), cy = 0.5f * (fb[1] + fb[4]);
+    const float bx0 = fminf(X.x, fb[0]), bx1 = fmaxf(X.x, fb[3]), by0 = fminf(X.y, fb[1]), by1 = fmaxf(X.y, fb[4]);
+    const float bz0 = fminf(X.z, fb[2]);
+    const int own = sc.fsolid[fs];
+    const Ray2 ray = make_ray2(X.x, X.y, cx, cy);
+    float bkey = INFINITY;
+    int bsol = -1;
+    if (nh > 0)
+        scan_solids(
+            sc, X.x, X.y, cx, cy, r, gs,
+            [&](int sid, float4 L, float4 H) -> float {
+                if (!(bx1 > L.x && bx0 < H.x && by1 > L.y && by0 < H.y && bz0 < H.z && bz0 >= L.z)) return INFINITY;
+                if (sid == own) return INFINITY;
+                for (int m = 0; m < nsc; ++m)
+                    if (scache[m] == sid) return INFINITY;
+                return segment_box_key(ray, L, H);
+            },
+            [](int) -> bool { return true; }, bkey, bsol);
+    // a certifying solid blocks the segment to the first hull corner in particular
+    if (bsol >= 0 && !solid_segment_global(sc, bsol, X, corner0, c)) bkey = INFINITY;
+    bool done = false;  // this lane's group is certified
+    sid_out = -1;
+    unsigned res = 0u;
+    for (int tr = 0; tr < kScanTries; ++tr) {
+        float kmin = bkey;
+        for (int o = gs >> 1; o > 0; o >>= 1) kmin = fminf(kmin, __shfl_xor(kmin, o));
+        const bool has = nh > 0 && !done && kmin < INFINITY;
+        if (!__ballot(has)) break;
+        const unsigned long long eq = __ballot(has && bkey == kmin) & gm;
+        const int src = eq ? __ffsll((long long)eq) - 1 : lane;
+        const int sid = __shfl(bsol, src);
+        if (has && bsol == sid) bkey = INFINITY;  // every lane of the group holding it drops it
+        const bool act = has && r < nh;
+        const bool good = act && solid_segment_global(sc, sid, X, corner, c);
+        const unsigned long long bad = __ballot(act && !good) & gm;
+        if (has && bad == 0ull) {
+            done = true;
+            sid_out = sid;
+        }
+        const unsigned long long dm = __ballot(done && r == 0);
+        for (int q = 0; q < nf; ++q)
+            if ((dm >> (q * gs)) & 1ull) res |= 1u << q;
+    }
+    return res;
 }
 
 template <bool MULTI>
@@ -1953,11 +2037,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const int fl = sidx < sc.S ? sc.sfacet[sidx] : -1;
             unsigned long long left = nm;
             while (left) {
-                const int fc = __shfl(fl, __ffsll((long long)left) - 1);
-                left &= ~__ballot(need && fl == fc);
-                if (certify_point_facet(sc, fc, make_float4(xx, xy, xz, 0.f), sSL[wv], scache, nsc, spos, c)) {
-                    if (fl == fc) need = false;
-                    ++nsolidf;
+                // up to four facets at once, one lane group each
+                int fq0 = -1, fq1 = -1, fq2 = -1, fq3 = -1;
+                int nf = 0;
+                for (; nf < 4 && left; ++nf) {
+                    const int fc = __shfl(fl, __ffsll((long long)left) - 1);
+                    left &= ~__ballot(need && fl == fc);
+                    if (nf == 0) fq0 = fc;
+                    else if (nf == 1) fq1 = fc;
+                    else if (nf == 2) fq2 = fc;
+                    else fq3 = fc;
+                }
+                const float4 Xp = make_float4(xx, xy, xz, 0.f);
+                if (nf == 1) {
+                    if (certify_point_facet(sc, fq0, Xp, sSL[wv], scache, nsc, spos, c)) {
+                        if (fl == fq0) need = false;
+                        ++nsolidf;
+                    }
+                } else {
+                    int sid_g;
+                    const unsigned ok = certify_point_facets(sc, nf, fq0, fq1, fq2, fq3, Xp, scache, nsc, sid_g, c);
+                    const int gs = nf <= 2 ? 32 : 16;
+                    for (int q = 0; q < nf; ++q) {
+                        if (!((ok >> q) & 1u)) continue;
+                        const int fcq = q == 0 ? fq0 : (q == 1 ? fq1 : (q == 2 ? fq2 : fq3));
+                        if (fl == fcq) need = false;
+                        ++nsolidf;
+                        // the certifying solid joins the wave's solid cache
+                        const int sid = __shfl(sid_g, q * gs);
+                        bool cached = false;
+                        for (int m = 0; m < nsc; ++m) cached |= scache[m] == sid;
+                        if (!cached) {
+                            int slot;
+                            if (nsc < kSolidCache) slot = nsc++;
+                            else { slot = spos; spos = (spos + 1) % kSolidCache; }
+                            scache[slot] = sid;
+                            stage_solid(sc, sid, sSL[wv][slot]);
+                        }
+                    }
                 }
             }
             nm = __ballot(need);
