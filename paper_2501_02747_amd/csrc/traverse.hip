@@ -1915,6 +1915,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ int sMiss[kWavesPerBlock][2 * kWave];
     __shared__ SolidLds sSL[kWavesPerBlock][kSolidCache];
     __shared__ int sList[kWavesPerBlock][kCache + kSolidCache];
+    // probe queue [0, np): probe sample, the facet's other missing samples of the
+    // chunk (bits from the chunk's first sample); then [np, np + nexp): facets whose
+    // probe was blocked, with the blocking triangle in place of the sample
+    __shared__ int sProbe[kWavesPerBlock][2 * kWave];
+    __shared__ unsigned long long sPMask[kWavesPerBlock][2 * kWave];
+    __shared__ int sPBase[kWavesPerBlock][2 * kWave];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
@@ -1934,6 +1940,72 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     int cur_job = 0;
     float xx = 0.f, xy = 0.f, xz = 0.f;
     uint64_t *out = nullptr;
+    int np = 0, nexp = 0;
+    const bool probing = !o.exhaustive;
+    // Runs the traversals the queues call for, from X: full batches of misses;
+    // the other missing samples of a facet whose probe was blocked (less those
+    // the probe's blocking triangle also blocks) into the miss queue; batches of
+    // up to 64 probes, one sample per facet, where a clear probe shows its facet
+    // visible at once.  `fin` empties the queues.
+    auto pump = [&](const SceneDev &S, bool fin) __attribute__((always_inline)) {
+        while (true) {
+            const bool do_miss = nmiss >= kWave || (fin && nmiss > 0 && nexp == 0);
+            if (!do_miss && nexp > 0) {
+                const int e = np + nexp - 1;
+                const unsigned long long m = sPMask[wv][e];
+                const int base = sPBase[wv][e], h = sProbe[wv][e];
+                --nexp;
+                bool keep = (m >> lane) & 1ull;
+                if (keep) {
+                    const float4 P3 = S.smp[base + lane];
+                    const Seg sg3 = make_seg(xx, xy, xz, P3.x, P3.y, P3.z);
+                    ++c.tests;
+                    keep = !tri_hit(sg3, S.tri[3 * h], S.tri[3 * h + 1], S.tri[3 * h + 2], o.eps6, f64, c.rechecks);
+                }
+                const unsigned long long km = __ballot(keep);
+                if (keep) miss[nmiss + __popcll(km & lt)] = base + lane;
+                nmiss += __popcll(km);
+                wave_sync();
+                continue;
+            }
+            if (!do_miss && !(np >= kWave || (fin && np > 0))) break;
+            const int k = min(kWave, do_miss ? nmiss : np);
+            const bool act = lane < k;
+            const int q = (do_miss ? nmiss : np) - (act ? k - lane : 1);
+            const int s2 = do_miss ? miss[q] : sProbe[wv][q];
+            const unsigned long long pm = do_miss || !act ? 0ull : sPMask[wv][q];
+            const int pb = do_miss ? 0 : sPBase[wv][q];
+            const int f = S.sfacet[s2];
+            const float4 P = S.smp[s2];
+            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+            if (act) ++c.traversed;
+            const int hit = any_hit_wave(S, sg, act, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c,
+                                         kAbortSameKey, f);
+            const bool clear = hit == -1;
+            if (do_miss) nmiss -= k;
+            else np -= k;
+            wave_sync();
+            mark_visible(out, clear, f);
+            remember_blockers(cache, ncache, cpos, __ballot(hit >= 0), hit);
+            if (S.n_solids > 0) remember_solid_ids(S, scache, nsc, spos, sSL[wv], kSolidCache, hit >= 0, hit);
+            if (!do_miss) {
+                // (a facet cut by a chunk boundary has two probes: a clear one settles both)
+                bool vis = clear;
+                for (unsigned long long cm = __ballot(clear); cm; cm &= cm - 1)
+                    vis |= __shfl(f, __ffsll((long long)cm) - 1) == f;
+                const bool blk = act && hit >= 0 && !vis && pm != 0ull;
+                const unsigned long long bm = __ballot(blk);
+                if (blk) {
+                    const int pos = np + __popcll(bm & lt);
+                    sProbe[wv][pos] = hit;
+                    sPMask[wv][pos] = pm;
+                    sPBase[wv][pos] = pb;
+                }
+                nexp = __popcll(bm);
+                wave_sync();
+            }
+        }
+    };
     for (long long it = it0; it <= it1; ++it) {
         const bool more = it < it1;
         long long key = -1;
@@ -1957,23 +2029,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             chunk = rem - side * nch;
             key = ((long long)js << 32) | (long long)(2 * n + side);
         }
-        // drain the queue when the point changes (or at the end)
-        while (nmiss > 0 && key != cur) {
-            const PointJob &CJ = MULTI ? many[cur_job] : one;
-            const int k = min(kWave, nmiss);
-            const int sidx = miss[nmiss - (lane < k ? k - lane : 1)];
-            const int f = CJ.sc.sfacet[sidx];
-            const float4 P = CJ.sc.smp[sidx];
-            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
-            if (lane < k) ++c.traversed;
-            const int hit = any_hit_wave(CJ.sc, sg, lane < k, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6,
-                                         f64, c, kAbortSameKey, f);
-            const bool clear = hit == -1;
-            nmiss -= k;
-            wave_sync();
-            mark_visible(out, clear, f);
-            remember_blockers(cache, ncache, cpos, __ballot(hit >= 0), hit);
-        }
+        // drain the queues when the point changes (or at the end)
+        if (key != cur && (np > 0 || nmiss > 0)) pump(MULTI ? many[cur_job].sc : one.sc, true);
         if (!more) break;
         const PointJob &J = MULTI ? many[js] : one;
         const SceneDev &sc = J.sc;
@@ -2080,26 +2137,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             nm = __ballot(need);
         }
         if (nm) ++items;
-        if (need) miss[nmiss + __popcll(nm & lt)] = sidx;
-        nmiss += __popcll(nm);
-        wave_sync();
-        // full traversal batches
-        while (nmiss >= kWave) {
-            const int k = kWave;
-            const int s2 = miss[nmiss - k + lane];
-            const int f = sc.sfacet[s2];
-            const float4 P = sc.smp[s2];
-            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
-            ++c.traversed;
-            const int hit = any_hit_wave(sc, sg, true, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c,
-                                         kAbortSameKey, f);
-            const bool clear = hit == -1;
-            nmiss -= k;
-            wave_sync();
-            mark_visible(out, clear, f);
-            remember_blockers(cache, ncache, cpos, __ballot(hit >= 0), hit);
-            if (sc.n_solids > 0) remember_solid_ids(sc, scache, nsc, spos, sSL[wv], kSolidCache, hit >= 0, hit);
+        if (probing) {
+            // one probe per facet left with misses: its middle missing sample
+            // (np < 64 here, and a chunk adds at most 64)
+            const int fl = sidx < sc.S ? sc.sfacet[sidx] : -1;
+            for (unsigned long long left = nm; left;) {
+                const int fc = __shfl(fl, __ffsll((long long)left) - 1);
+                const unsigned long long mf = __ballot(need && fl == fc);
+                left &= ~mf;
+                if (need && fl == fc && __popcll(mf & lt) == (__popcll(mf) >> 1)) {
+                    sProbe[wv][np] = sidx;
+                    sPMask[wv][np] = mf & ~(1ull << lane);
+                    sPBase[wv][np] = chunk * kWave;
+                }
+                ++np;
+            }
+        } else {
+            if (need) miss[nmiss + __popcll(nm & lt)] = sidx;
+            nmiss += __popcll(nm);
         }
+        wave_sync();
+        pump(sc, false);
     }
     flush_counters(st, c, segs, 0, items);
     if (st && lane == 0 && nsolidf) atomicAdd((unsigned long long *)&st->solid_certified, nsolidf);
