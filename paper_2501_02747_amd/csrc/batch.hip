@@ -34,7 +34,7 @@ namespace {
 inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t batch_bytes(int n) {
-    return al(sizeof(PairJob) * (size_t)n) + al(sizeof(PointJob) * (size_t)n) + al(sizeof(uint32_t) * (size_t)(n + 1)) +
+    return al(sizeof(PairJob) * (size_t)n) + al(sizeof(PointJob) * (size_t)n) + al(sizeof(uint32_t) * (size_t)(2 * n + 2)) +
            256;
 }
 
@@ -125,7 +125,7 @@ ivm_status ivm_batch_create(int32_t n_items, const ivm_batch_item *items, const 
     b->d_qjobs = (PointJob *)ws;
     ws += al(sizeof(PointJob) * (size_t)n_items);
     b->d_base = (uint32_t *)ws;
-    ws += al(sizeof(uint32_t) * (size_t)(n_items + 1));
+    ws += al(sizeof(uint32_t) * (size_t)(2 * n_items + 2));
     b->d_queue = (uint32_t *)ws;
     b->o = batch_opts(opts);
     b->stats = d_stats;

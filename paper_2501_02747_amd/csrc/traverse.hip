@@ -1158,6 +1158,78 @@ __device__ inline void set_rects(Rects &R, unsigned todo, const int *pco, const 
     R.n = nr;
 }
 
+__constant__ uint8_t kIdentOrder[kTreelets] = {0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13, 14, 15,
+                                               16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
+
+// The first admissible sample of facet a towards facet b (orient(b, x) > 0),
+// taken from the middle of a's list onwards (wrapping).
+__device__ inline bool probe_sample(const SceneDev &sc, int a, int b, float4 &x) {
+    const int a0 = sc.soff[a], n = min(sc.soff[a + 1] - a0, kWave);
+    const double *pl = sc.fplane + 6 * b;
+    for (int t = 0, k = n >> 1; t < n; ++t, k = k + 1 == n ? 0 : k + 1) {
+        x = sc.smp[a0 + k];
+        if (orient(pl, x.x, x.y, x.z) > 0.0) return true;
+    }
+    return false;
+}
+
+// Visibility probes: one admissible segment per candidate pair, 64 pairs per
+// traversal (one per lane, treelets in index order).  A clear probe proves its
+// pair visible (both bits of M); k_pairs then skips the pair.  A blocked probe
+// decides nothing.  Each wave takes 64 consecutive candidates of one scene; in
+// the MULTI form pbase[] is the exclusive prefix of the scenes' candidate
+// totals rounded up to multiples of 64.
+template <bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJob *many, const uint32_t *pbase,
+                                                        int n_jobs, uint32_t *queue, TraverseOpts o, ivm_stats *st) {
+    __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    int *stk = &sStack[wv][lane];
+    const bool f64 = o.fp64_only != 0;
+    Cnt c;
+    unsigned long long segs = 0, nvis = 0;
+    const uint32_t total = MULTI ? pbase[n_jobs] : (one.prefix[one.n_items] + kWave - 1) / kWave * kWave;
+    while (true) {
+        uint32_t g0 = 0;
+        if (lane == 0) g0 = atomicAdd(queue, (uint32_t)kWave);
+        g0 = __shfl(g0, 0);
+        if (g0 >= total) break;
+        int js = 0;
+        if (MULTI) {
+            int lo = 0, hi = n_jobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pbase[mid] <= g0) lo = mid;
+                else hi = mid - 1;
+            }
+            js = lo;
+        }
+        const PairJob &J = MULTI ? many[js] : one;
+        const SceneDev &sc = J.sc;
+        const uint32_t gl = g0 - (MULTI ? pbase[js] : 0u) + (uint32_t)lane;
+        bool act = sc.F >= 2 && gl < J.prefix[J.n_items];
+        int i = 0, j = 0;
+        float4 P = make_float4(0.f, 0.f, 0.f, 0.f), Q = P;
+        if (act) {
+            decode_pair(sc, J.cand, J.prefix, J.n_items, gl, i, j);
+            act = probe_sample(sc, i, j, P) && probe_sample(sc, j, i, Q);
+        }
+        const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
+        if (act) {
+            ++segs;
+            ++c.traversed;
+        }
+        const int hit = any_hit_wave(sc, sg, act, i, j, kIdentOrder, kTreelets, stk, o.stack_depth, o.eps6, f64, c,
+                                     0, 0);
+        if (act && hit == -1) {
+            atomicOr((unsigned long long *)&J.M[(size_t)i * sc.W + (j >> 6)], 1ull << (j & 63));
+            atomicOr((unsigned long long *)&J.M[(size_t)j * sc.W + (i >> 6)], 1ull << (i & 63));
+            ++nvis;
+        }
+    }
+    flush_counters(st, c, segs, wave_sum_u64(nvis), 0);
+}
+
 // MULTI: the queue index runs over the concatenated candidates of n_jobs scenes
 // (base[] = exclusive prefix of their candidate totals); otherwise over `one`.
 template <bool MULTI>
@@ -1231,6 +1303,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         int i, j;
         decode_pair(sc, J.cand, J.prefix, J.n_items, gl, i, j);
+        if ((J.M[(size_t)i * sc.W + (j >> 6)] >> (j & 63)) & 1ull) continue;  // a probe found it visible
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
         const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
         const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
@@ -1697,14 +1770,20 @@ hipError_t launch_cull_scan(Scene &scn, uint64_t *M, ivm_stats *stats, hipStream
     return hipGetLastError();
 }
 
+// base[0, n]: exclusive prefix of the scenes' candidate totals; base[n + 1, 2n + 1]:
+// the same with each total rounded up to a multiple of 64 (the probe queue).
 __global__ void k_job_base(const PairJob *jobs, int n, uint32_t *base) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    uint32_t run = 0;
+    uint32_t run = 0, prun = 0;
     for (int k = 0; k < n; ++k) {
         base[k] = run;
-        run += jobs[k].sc.F >= 2 ? jobs[k].prefix[jobs[k].n_items] : 0u;
+        base[n + 1 + k] = prun;
+        const uint32_t cnt = jobs[k].sc.F >= 2 ? jobs[k].prefix[jobs[k].n_items] : 0u;
+        run += cnt;
+        prun += (cnt + kWave - 1) / kWave * kWave;
     }
     base[n] = run;
+    base[2 * n + 1] = prun;
 }
 
 hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, hipStream_t s) {
@@ -1715,6 +1794,9 @@ hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, 
 hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue,
                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
     PairJob none{};
+    if (!o.exhaustive)
+        hipLaunchKernelGGL(k_probe_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs,
+                           d_base + n_jobs + 1, n_jobs, d_queue + 1, o, stats);
     hipLaunchKernelGGL(k_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base, n_jobs, d_queue, o,
                        stats);
     return hipGetLastError();
@@ -1735,6 +1817,10 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
     }
     const PairJob job = make_pair_job(scn, M, learned);
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
+    if (!o.exhaustive)
+        hipLaunchKernelGGL(k_probe_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job,
+                           (const PairJob *)nullptr, (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue) + 1, o,
+                           stats);
     hipLaunchKernelGGL(k_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PairJob *)nullptr,
                        (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue), o, stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1746,8 +1832,6 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
 // Tx/Rx points and line of sight
 // ---------------------------------------------------------------------------
 
-__constant__ uint8_t kIdentOrder[kTreelets] = {0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13, 14, 15,
-                                               16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
 
 // Items are (job, snapshot, side, chunk of 64 consecutive samples); each wave
 // walks a contiguous range of global items so consecutive items share the Tx
