@@ -123,7 +123,7 @@ struct SceneDev {
 struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
-    size_t ffirst, cand, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
+    size_t ffirst, cand, done, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
     size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4, sol_box;
     size_t grid_p, grid_cnt, grid_off, grid_list, grid_ent;
     size_t learned_bytes;
@@ -177,6 +177,7 @@ struct PairJob {
     int n_items;
     uint64_t *M;
     const uint64_t *learned;  // per-candidate learned order, or nullptr
+    uint64_t *done;           // F * W: pairs the probe kernel proved blocked
 };
 
 // One scene's share of a (possibly multi-scene) Tx/Rx point launch.

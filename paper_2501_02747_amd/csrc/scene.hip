@@ -82,6 +82,7 @@ Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
         L.grid_ent = take(((size_t)kGridEntriesPerSolid * Ns + 1024) * 2 * sizeof(float4));
     }
     L.cand = take(items * sizeof(uint64_t));
+    L.done = take(items * sizeof(uint64_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
     L.queue = take(256);

@@ -591,6 +591,7 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 }
 
 constexpr int kCache = 4;  // recent blockers tested before a traversal
+constexpr int kProbeRounds = 2;  // probe passes over the candidate pairs before the pair kernel
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
 constexpr int kScanMaxSolids = 4096;  // scenes with at most this many solids scan them all per pair
 constexpr int kScanTries = 4;         // solids from the scan tried per pair
@@ -1162,32 +1163,77 @@ __constant__ uint8_t kIdentOrder[kTreelets] = {0,  1,  2,  3,  4,  5,  6,  7,  8
                                                16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
 
 // The first admissible sample of facet a towards facet b (orient(b, x) > 0),
-// taken from the middle of a's list onwards (wrapping).
-__device__ inline bool probe_sample(const SceneDev &sc, int a, int b, float4 &x) {
+// taken from position n/2 of a's list (round 0) or its mirror n - 1 - n/2
+// (round 1) onwards, wrapping.
+__device__ inline bool probe_sample(const SceneDev &sc, int a, int b, int round, float4 &x) {
     const int a0 = sc.soff[a], n = min(sc.soff[a + 1] - a0, kWave);
     const double *pl = sc.fplane + 6 * b;
-    for (int t = 0, k = n >> 1; t < n; ++t, k = k + 1 == n ? 0 : k + 1) {
+    for (int t = 0, k = round ? n - 1 - (n >> 1) : n >> 1; t < n; ++t, k = k + 1 == n ? 0 : k + 1) {
         x = sc.smp[a0 + k];
         if (orient(pl, x.x, x.y, x.z) > 0.0) return true;
     }
     return false;
 }
 
+// Value of face plane k of verified solid K at x (sample units); k = planes is the top.
+__device__ inline double solid_plane_global(const SceneDev &sc, int K, int k, int npl, int top, double x, double y,
+                                            double z) {
+    if (k < npl) {
+        const int4 pl = sc.splane[K * kSolidMaxPlanes + k];
+        return (double)pl.w * (x - (double)pl.x) - (double)pl.z * (y - (double)pl.y);
+    }
+    return z - (double)top;
+}
+
+// The whole-pair solid certificate for one lane's pair (i, j) and solid K, all
+// steps on this lane: each facet's sample hull strictly outside one face plane,
+// and every segment between hull corners through the open prism (the same
+// conditions as the wave-wide form, hull corners read from global memory).
+__device__ bool certify_pair_lane(const SceneDev &sc, int K, int i, int j, Cnt &c) {
+    const int4 R = sc.solid[K];
+    const int npl = R.x, ni = sc.fhull_n[i], nj = sc.fhull_n[j];
+    if (npl <= 0 || ni == 0 || nj == 0) return false;
+    const double u = ldexp(1.0, sc.gs);
+    for (int side = 0; side < 2; ++side) {
+        const int f = side ? j : i, nh = side ? nj : ni;
+        bool out = false;
+        for (int k = 0; k <= npl && !out; ++k) {
+            bool all = true;
+            for (int a = 0; a < nh && all; ++a) {
+                const float4 x = sc.smp[sc.fhull[kHullMax * f + a]];
+                ++c.solid_planes;
+                all = solid_plane_global(sc, K, k, npl, R.y, x.x * u, x.y * u, x.z * u) > 0.0;
+            }
+            out = all;
+        }
+        if (!out) return false;
+    }
+    for (int a = 0; a < ni; ++a) {
+        const float4 P = sc.smp[sc.fhull[kHullMax * i + a]];
+        for (int b = 0; b < nj; ++b)
+            if (!solid_segment_global(sc, K, P, sc.smp[sc.fhull[kHullMax * j + b]], c)) return false;
+    }
+    return true;
+}
+
 // Visibility probes: one admissible segment per candidate pair, 64 pairs per
 // traversal (one per lane, treelets in index order).  A clear probe proves its
-// pair visible (both bits of M); k_pairs then skips the pair.  A blocked probe
-// decides nothing.  Each wave takes 64 consecutive candidates of one scene; in
+// pair visible (both bits of M); a blocked one tries the whole-pair certificate
+// with the verified solid of the triangle that blocked it, and a certified pair
+// is marked done.  Round 1 probes the pairs round 0 left undecided with other
+// samples.  k_pairs skips pairs decided either way.  Each wave takes 64 consecutive candidates of one scene; in
 // the MULTI form pbase[] is the exclusive prefix of the scenes' candidate
 // totals rounded up to multiples of 64.
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJob *many, const uint32_t *pbase,
-                                                        int n_jobs, uint32_t *queue, TraverseOpts o, ivm_stats *st) {
+                                                        int n_jobs, uint32_t *queue, int round, TraverseOpts o,
+                                                        ivm_stats *st) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     int *stk = &sStack[wv][lane];
     const bool f64 = o.fp64_only != 0;
     Cnt c;
-    unsigned long long segs = 0, nvis = 0;
+    unsigned long long segs = 0, nvis = 0, ncert = 0;
     const uint32_t total = MULTI ? pbase[n_jobs] : (one.prefix[one.n_items] + kWave - 1) / kWave * kWave;
     while (true) {
         uint32_t g0 = 0;
@@ -1212,7 +1258,8 @@ __global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJ
         float4 P = make_float4(0.f, 0.f, 0.f, 0.f), Q = P;
         if (act) {
             decode_pair(sc, J.cand, J.prefix, J.n_items, gl, i, j);
-            act = probe_sample(sc, i, j, P) && probe_sample(sc, j, i, Q);
+            if (round > 0) act = !(((J.M[(size_t)i * sc.W + (j >> 6)] | J.done[(size_t)i * sc.W + (j >> 6)]) >> (j & 63)) & 1ull);
+            act = act && probe_sample(sc, i, j, round, P) && probe_sample(sc, j, i, round, Q);
         }
         const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
         if (act) {
@@ -1226,8 +1273,17 @@ __global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJ
             atomicOr((unsigned long long *)&J.M[(size_t)j * sc.W + (i >> 6)], 1ull << (i & 63));
             ++nvis;
         }
+        if (act && hit >= 0 && sc.n_solids > 0) {
+            const int K = sc.fsolid[__float_as_int(sc.tri[3 * hit].w)];
+            if (K >= 0 && certify_pair_lane(sc, K, i, j, c)) {
+                atomicOr((unsigned long long *)&J.done[(size_t)i * sc.W + (j >> 6)], 1ull << (j & 63));
+                ++ncert;
+            }
+        }
     }
     flush_counters(st, c, segs, wave_sum_u64(nvis), 0);
+    const unsigned long long nc = wave_sum_u64(ncert);
+    if (st && lane == 0 && nc) atomicAdd((unsigned long long *)&st->solid_certified, nc);
 }
 
 // MULTI: the queue index runs over the concatenated candidates of n_jobs scenes
@@ -1271,6 +1327,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     int nsol = 0, sspos = 0;
     int cur_js = -1;
     uint32_t g_next = 0, g_end = 0;
+    // decode state: the previous pair's candidate word and its bits from that pair on
+    int d_item = 0;
+    unsigned long long d_m = 0ull;
+    uint32_t d_gl = 0xffffffffu;
     const uint32_t nwaves_all = gridDim.x * (uint32_t)kWavesPerBlock;
     const uint32_t chunk = total / nwaves_all > kLargePerWave ? (uint32_t)kPairChunkLarge : (uint32_t)kPairChunk;
     while (true) {
@@ -1300,10 +1360,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (js != cur_js) {
             cur_js = js;
             ncache = cpos = nsol = sspos = 0;
+            d_gl = 0xffffffffu;
         }
-        int i, j;
-        decode_pair(sc, J.cand, J.prefix, J.n_items, gl, i, j);
-        if ((J.M[(size_t)i * sc.W + (j >> 6)] >> (j & 63)) & 1ull) continue;  // a probe found it visible
+        // consecutive candidates of one word: the next set bit (a binary search
+        // over the prefix only when the word is used up or the chunk jumps)
+        if (gl == d_gl + 1u && (d_m & (d_m - 1ull)) != 0ull) {
+            d_m &= d_m - 1ull;
+        } else {
+            d_item = find_item(J.prefix, J.n_items, gl);
+            d_m = J.cand[d_item];
+            for (uint32_t q = J.prefix[d_item]; q < gl; ++q) d_m &= d_m - 1ull;
+        }
+        d_gl = gl;
+        const int i = d_item / sc.W, j = (d_item - i * sc.W) * 64 + (__ffsll((long long)d_m) - 1);
+        if (((J.M[(size_t)i * sc.W + (j >> 6)] | J.done[(size_t)i * sc.W + (j >> 6)]) >> (j & 63)) & 1ull)
+            continue;  // decided by the probe kernel
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
         const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
         const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
@@ -1747,6 +1818,7 @@ PairJob make_pair_job(Scene &scn, uint64_t *M, bool learned) {
     j.n_items = scn.n_items;
     j.M = M;
     j.learned = learned && L.learned_bytes ? (const uint64_t *)(ws + L.learned) : nullptr;
+    j.done = (uint64_t *)(ws + L.done);
     return j;
 }
 
@@ -1761,6 +1833,7 @@ hipError_t launch_cull_scan(Scene &scn, uint64_t *M, ivm_stats *stats, hipStream
     const int n_items = scn.n_items;
     hipError_t e;
     if ((e = launch_fill_u64(M, 0ull, (size_t)sc.F * sc.W, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64((uint64_t *)(ws + L.done), 0ull, (size_t)sc.F * sc.W, s)) != hipSuccess) return e;
     if ((e = launch_fill_u32((uint32_t *)(ws + L.queue), 0u, 64, s)) != hipSuccess) return e;
     const unsigned blocks = (unsigned)((n_items + 3) / 4);
     hipLaunchKernelGGL(k_cull, dim3(blocks > 65535u ? 65535u : (blocks ? blocks : 1u)), dim3(256), 0, s, sc, cand,
@@ -1794,9 +1867,9 @@ hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, 
 hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue,
                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
     PairJob none{};
-    if (!o.exhaustive)
+    for (int round = 0; round < kProbeRounds && !o.exhaustive; ++round)
         hipLaunchKernelGGL(k_probe_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs,
-                           d_base + n_jobs + 1, n_jobs, d_queue + 1, o, stats);
+                           d_base + n_jobs + 1, n_jobs, d_queue + 1 + round, round, o, stats);
     hipLaunchKernelGGL(k_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base, n_jobs, d_queue, o,
                        stats);
     return hipGetLastError();
@@ -1817,10 +1890,10 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
     }
     const PairJob job = make_pair_job(scn, M, learned);
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
-    if (!o.exhaustive)
+    for (int round = 0; round < kProbeRounds && !o.exhaustive; ++round)
         hipLaunchKernelGGL(k_probe_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job,
-                           (const PairJob *)nullptr, (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue) + 1, o,
-                           stats);
+                           (const PairJob *)nullptr, (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue) + 1 + round,
+                           round, o, stats);
     hipLaunchKernelGGL(k_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PairJob *)nullptr,
                        (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue), o, stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
