@@ -62,7 +62,7 @@ def _parse():
     ap.add_argument("--order", default="plain", choices=["plain", "index", "reversed", "learned"])
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--exhaustive", action="store_true",
-                    help="ablation: every admissible segment searched on its own (no caches or certificates)")
+                    help="ablation: every admissible segment searched on its own (no probes, caches or certificates)")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--stack", type=int, default=0)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)

@@ -170,11 +170,12 @@ typedef struct ivm_matrix_opts {
                                +inf sends every test to FP64 */
     int32_t no_tile;        /* 1: never decide a pair from its near-field tile alone */
     int32_t exhaustive;     /* 1: give every admissible segment its own BVH search: no
-                               blocker caches, no bundle certificates, no near-field
-                               tile (a measurement baseline) */
+                               probes, no blocker or solid caches, no bundle or point
+                               certificates, no near-field tile (a measurement baseline) */
     hipEvent_t *timing_events; /* optional (NULL = none): two caller-created events the
                                   call records on its stream immediately before and
-                                  after its traversal kernel */
+                                  after its traversal kernels (the matrix: both probe
+                                  rounds and the pair kernel; the table: the point kernel) */
 } ivm_matrix_opts;
 
 #define IVM_MAX_STACK 24
