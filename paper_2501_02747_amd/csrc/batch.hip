@@ -51,8 +51,27 @@ hipError_t record(ivm_batch *b, hipStream_t s) {
             return e;
         }
     }
-    if ((e = launch_job_base(b->d_pjobs, b->n, b->d_base, s)) != hipSuccess) return e;
     if ((e = launch_fill_u32(b->d_queue, 0u, 64, s)) != hipSuccess) return e;
+    // probe rounds over all scenes at once, each followed by every scene's
+    // compaction of its undecided pairs; then the pair kernel over those
+    auto undecided_all = [&]() -> hipError_t {
+        for (int k = 0; k < b->n; ++k) {
+            const ivm_batch_item &it = b->items[k];
+            Scene &sc = it.scene->s;
+            hipError_t r;
+            if (sc.dev.F >= 2 && (r = launch_undecided(sc, it.d_M, s)) != hipSuccess) return r;
+        }
+        return hipSuccess;
+    };
+    const int rounds = b->o.exhaustive ? 0 : kProbeRounds;
+    for (int round = 0; round < rounds; ++round) {
+        if ((e = launch_job_base(b->d_pjobs, b->n, b->d_base, round > 0, s)) != hipSuccess) return e;
+        if ((e = launch_probe_jobs(b->d_pjobs, b->d_base, b->n, b->d_queue, round, b->o, b->stats, s)) != hipSuccess)
+            return e;
+        if ((e = undecided_all()) != hipSuccess) return e;
+    }
+    if (rounds == 0 && (e = undecided_all()) != hipSuccess) return e;
+    if ((e = launch_job_base(b->d_pjobs, b->n, b->d_base, true, s)) != hipSuccess) return e;
     if ((e = launch_pair_jobs(b->d_pjobs, b->d_base, b->n, b->d_queue, b->o, b->stats, s)) != hipSuccess) return e;
     for (int k = 0; k < b->n; ++k) {
         const ivm_batch_item &it = b->items[k];

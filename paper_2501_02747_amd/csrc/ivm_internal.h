@@ -123,7 +123,7 @@ struct SceneDev {
 struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
-    size_t ffirst, cand, done, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
+    size_t ffirst, cand, done, und, uprefix, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
     size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4, sol_box;
     size_t grid_p, grid_cnt, grid_off, grid_list, grid_ent;
     size_t learned_bytes;
@@ -178,6 +178,8 @@ struct PairJob {
     uint64_t *M;
     const uint64_t *learned;  // per-candidate learned order, or nullptr
     uint64_t *done;           // F * W: pairs the probe kernel proved blocked
+    const uint64_t *und;      // F * W: candidates still undecided after the probes
+    const uint32_t *uprefix;  // exclusive prefix of their counts (n_items + 1)
 };
 
 // One scene's share of a (possibly multi-scene) Tx/Rx point launch.
@@ -216,9 +218,13 @@ hipError_t model_adam(Model &m, float lr, hipStream_t s);
 size_t model_workspace_bytes(int max_batch);
 void model_bind(Model &m, void *ws, int max_batch, int precision);
 hipError_t launch_cull_scan(Scene &sc, uint64_t *M, ivm_stats *stats, hipStream_t s);
+constexpr int kProbeRounds = 2;  // probe passes over the candidate pairs before the pair kernel
+hipError_t launch_undecided(Scene &scn, uint64_t *M, hipStream_t s);
+hipError_t launch_probe_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue, int round,
+                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s);
 hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue,
                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s);
-hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, hipStream_t s);
+hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, bool undecided, hipStream_t s);
 hipError_t launch_points_prep(Scene &sc, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
                               hipStream_t s);
 hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_items, const TraverseOpts &o,

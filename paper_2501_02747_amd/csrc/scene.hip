@@ -83,6 +83,8 @@ Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
     }
     L.cand = take(items * sizeof(uint64_t));
     L.done = take(items * sizeof(uint64_t));
+    L.und = take(items * sizeof(uint64_t));
+    L.uprefix = take((items + 1) * sizeof(uint32_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
     L.queue = take(256);

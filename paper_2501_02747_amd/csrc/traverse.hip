@@ -591,13 +591,12 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 }
 
 constexpr int kCache = 4;  // recent blockers tested before a traversal
-constexpr int kProbeRounds = 2;  // probe passes over the candidate pairs before the pair kernel
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
 constexpr int kScanMaxSolids = 4096;  // scenes with at most this many solids scan them all per pair
 constexpr int kScanTries = 4;         // solids from the scan tried per pair
 constexpr int kScanLinearMax = 256;   // up to this many solids a scan reads them all instead of the grid
 constexpr int kScanMaxSolidsPoint = 4096;  // the same scan per (point, facet) in the Tx/Rx kernel
-constexpr int kPairChunk = 16;  // consecutive candidate pairs taken by a wave at a time (small jobs)
+constexpr int kPairChunk = 4;   // consecutive undecided pairs taken by a wave at a time (small jobs)
 constexpr int kPairChunkLarge = 32;       // ... when a wave has many pairs to do (better reuse)
 constexpr uint32_t kLargePerWave = 2048;  // candidate pairs per wave above which chunks are large
 
@@ -1220,8 +1219,8 @@ __device__ bool certify_pair_lane(const SceneDev &sc, int K, int i, int j, Cnt &
 // traversal (one per lane, treelets in index order).  A clear probe proves its
 // pair visible (both bits of M); a blocked one tries the whole-pair certificate
 // with the verified solid of the triangle that blocked it, and a certified pair
-// is marked done.  Round 1 probes the pairs round 0 left undecided with other
-// samples.  k_pairs skips pairs decided either way.  Each wave takes 64 consecutive candidates of one scene; in
+// is marked done.  Round 0 runs over the candidate pairs, round 1 over the pairs
+// round 0 left undecided (und / uprefix), with other samples.  Each wave takes 64 consecutive candidates of one scene; in
 // the MULTI form pbase[] is the exclusive prefix of the scenes' candidate
 // totals rounded up to multiples of 64.
 template <bool MULTI>
@@ -1234,7 +1233,8 @@ __global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJ
     const bool f64 = o.fp64_only != 0;
     Cnt c;
     unsigned long long segs = 0, nvis = 0, ncert = 0;
-    const uint32_t total = MULTI ? pbase[n_jobs] : (one.prefix[one.n_items] + kWave - 1) / kWave * kWave;
+    const uint32_t total =
+        MULTI ? pbase[n_jobs] : ((round ? one.uprefix : one.prefix)[one.n_items] + kWave - 1) / kWave * kWave;
     while (true) {
         uint32_t g0 = 0;
         if (lane == 0) g0 = atomicAdd(queue, (uint32_t)kWave);
@@ -1253,13 +1253,14 @@ __global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJ
         const PairJob &J = MULTI ? many[js] : one;
         const SceneDev &sc = J.sc;
         const uint32_t gl = g0 - (MULTI ? pbase[js] : 0u) + (uint32_t)lane;
-        bool act = sc.F >= 2 && gl < J.prefix[J.n_items];
+        const uint64_t *cw = round ? J.und : J.cand;
+        const uint32_t *pf = round ? J.uprefix : J.prefix;
+        bool act = sc.F >= 2 && gl < pf[J.n_items];
         int i = 0, j = 0;
         float4 P = make_float4(0.f, 0.f, 0.f, 0.f), Q = P;
         if (act) {
-            decode_pair(sc, J.cand, J.prefix, J.n_items, gl, i, j);
-            if (round > 0) act = !(((J.M[(size_t)i * sc.W + (j >> 6)] | J.done[(size_t)i * sc.W + (j >> 6)]) >> (j & 63)) & 1ull);
-            act = act && probe_sample(sc, i, j, round, P) && probe_sample(sc, j, i, round, Q);
+            decode_pair(sc, cw, pf, J.n_items, gl, i, j);
+            act = probe_sample(sc, i, j, round, P) && probe_sample(sc, j, i, round, Q);
         }
         const Seg sg = make_seg(P.x, P.y, P.z, Q.x, Q.y, Q.z);
         if (act) {
@@ -1308,7 +1309,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     // go to scratch memory
     __shared__ int sList[kWavesPerBlock][kCache + kSolidTries + kCache + 10];
     const int wv = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t total = MULTI ? base[n_jobs] : one.prefix[one.n_items];
+    const uint32_t total = MULTI ? base[n_jobs] : one.uprefix[one.n_items];
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
     Rects &R = sR[wv];
@@ -1360,21 +1361,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (js != cur_js) {
             cur_js = js;
             ncache = cpos = nsol = sspos = 0;
+            d_m = 0ull;  // (d_gl + 1 wraps to 0, the new scene's first pair: an empty word forces a full decode)
             d_gl = 0xffffffffu;
         }
         // consecutive candidates of one word: the next set bit (a binary search
         // over the prefix only when the word is used up or the chunk jumps)
+        // (the pairs the probe kernel left undecided)
         if (gl == d_gl + 1u && (d_m & (d_m - 1ull)) != 0ull) {
             d_m &= d_m - 1ull;
         } else {
-            d_item = find_item(J.prefix, J.n_items, gl);
-            d_m = J.cand[d_item];
-            for (uint32_t q = J.prefix[d_item]; q < gl; ++q) d_m &= d_m - 1ull;
+            d_item = find_item(J.uprefix, J.n_items, gl);
+            d_m = J.und[d_item];
+            for (uint32_t q = J.uprefix[d_item]; q < gl; ++q) d_m &= d_m - 1ull;
         }
         d_gl = gl;
-        const int i = d_item / sc.W, j = (d_item - i * sc.W) * 64 + (__ffsll((long long)d_m) - 1);
-        if (((J.M[(size_t)i * sc.W + (j >> 6)] | J.done[(size_t)i * sc.W + (j >> 6)]) >> (j & 63)) & 1ull)
-            continue;  // decided by the probe kernel
+        const int jbit = __ffsll((long long)d_m) - 1;
+        const int i = d_item / sc.W, j = (d_item - i * sc.W) * 64 + jbit;
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
         const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
         const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
@@ -1501,7 +1503,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             continue;
         }
         unsigned long long lcode = 0;
-        if (o.order_mode == IVM_ORDER_LEARNED && J.learned) lcode = J.learned[gl];
+        if (o.order_mode == IVM_ORDER_LEARNED && J.learned)  // indexed by the pair's rank among all candidates
+            lcode = J.learned[J.prefix[d_item] + (uint32_t)__popcll(J.cand[d_item] & ((1ull << jbit) - 1ull))];
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
         // near-field tile (the miss queue's storage doubles as the walk frontier)
         // (only for bundles meeting few treelets: a long bundle would overflow the tile anyway)
@@ -1819,6 +1822,8 @@ PairJob make_pair_job(Scene &scn, uint64_t *M, bool learned) {
     j.M = M;
     j.learned = learned && L.learned_bytes ? (const uint64_t *)(ws + L.learned) : nullptr;
     j.done = (uint64_t *)(ws + L.done);
+    j.und = (const uint64_t *)(ws + L.und);
+    j.uprefix = (const uint32_t *)(ws + L.uprefix);
     return j;
 }
 
@@ -1843,15 +1848,42 @@ hipError_t launch_cull_scan(Scene &scn, uint64_t *M, ivm_stats *stats, hipStream
     return hipGetLastError();
 }
 
-// base[0, n]: exclusive prefix of the scenes' candidate totals; base[n + 1, 2n + 1]:
-// the same with each total rounded up to a multiple of 64 (the probe queue).
-__global__ void k_job_base(const PairJob *jobs, int n, uint32_t *base) {
+// The candidates no probe has decided: und = cand & ~(M | done), word by word,
+// and their counts (scanned into uprefix afterwards).
+__global__ void k_undecided(int n_items, const uint64_t *cand, const uint64_t *M, const uint64_t *done, uint64_t *und,
+                            uint32_t *counts) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < n_items) {
+        const uint64_t u = cand[w] & ~(M[w] | done[w]);
+        und[w] = u;
+        counts[w] = (uint32_t)__popcll(u);
+    }
+    if (w == 0) counts[n_items] = 0;
+}
+
+hipError_t launch_undecided(Scene &scn, uint64_t *M, hipStream_t s) {
+    char *ws = (char *)scn.ws;
+    const Layout &L = scn.lay;
+    const int n = scn.n_items;
+    uint32_t *up = (uint32_t *)(ws + L.uprefix);
+    hipLaunchKernelGGL(k_undecided, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, n, (const uint64_t *)(ws + L.cand),
+                       (const uint64_t *)M, (const uint64_t *)(ws + L.done), (uint64_t *)(ws + L.und), up);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return exclusive_scan_u32(up, n + 1, (uint32_t *)(ws + L.scan_tmp), s);
+}
+
+// base[0, n]: exclusive prefix of the scenes' candidate totals (all candidates, or
+// the undecided ones); base[n + 1, 2n + 1]: the same with each total rounded up to
+// a multiple of 64 (the probe queue).
+__global__ void k_job_base(const PairJob *jobs, int n, uint32_t *base, int undecided) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     uint32_t run = 0, prun = 0;
     for (int k = 0; k < n; ++k) {
         base[k] = run;
         base[n + 1 + k] = prun;
-        const uint32_t cnt = jobs[k].sc.F >= 2 ? jobs[k].prefix[jobs[k].n_items] : 0u;
+        const uint32_t cnt =
+            jobs[k].sc.F >= 2 ? (undecided ? jobs[k].uprefix : jobs[k].prefix)[jobs[k].n_items] : 0u;
         run += cnt;
         prun += (cnt + kWave - 1) / kWave * kWave;
     }
@@ -1859,17 +1891,22 @@ __global__ void k_job_base(const PairJob *jobs, int n, uint32_t *base) {
     base[2 * n + 1] = prun;
 }
 
-hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, hipStream_t s) {
-    hipLaunchKernelGGL(k_job_base, dim3(1), dim3(64), 0, s, d_jobs, n_jobs, d_base);
+hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, bool undecided, hipStream_t s) {
+    hipLaunchKernelGGL(k_job_base, dim3(1), dim3(64), 0, s, d_jobs, n_jobs, d_base, undecided ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue, int round,
+                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
+    PairJob none{};
+    hipLaunchKernelGGL(k_probe_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base + n_jobs + 1,
+                       n_jobs, d_queue + 1 + round, round, o, stats);
     return hipGetLastError();
 }
 
 hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue,
                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
     PairJob none{};
-    for (int round = 0; round < kProbeRounds && !o.exhaustive; ++round)
-        hipLaunchKernelGGL(k_probe_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs,
-                           d_base + n_jobs + 1, n_jobs, d_queue + 1 + round, round, o, stats);
     hipLaunchKernelGGL(k_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base, n_jobs, d_queue, o,
                        stats);
     return hipGetLastError();
@@ -1890,10 +1927,15 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
     }
     const PairJob job = make_pair_job(scn, M, learned);
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
-    for (int round = 0; round < kProbeRounds && !o.exhaustive; ++round)
+    // probe rounds, each followed by the compaction of the still-undecided pairs
+    // (the exhaustive baseline runs no probe and takes every candidate)
+    for (int round = 0; round < kProbeRounds && !o.exhaustive; ++round) {
         hipLaunchKernelGGL(k_probe_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job,
                            (const PairJob *)nullptr, (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue) + 1 + round,
                            round, o, stats);
+        if ((e = launch_undecided(scn, M, s)) != hipSuccess) return e;
+    }
+    if (o.exhaustive && (e = launch_undecided(scn, M, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PairJob *)nullptr,
                        (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue), o, stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
