@@ -760,7 +760,15 @@ __device__ bool solid_segment(const SolidLds &S, double px, double py, double pz
     return pout && prod_less(Ln, Ud, Un, Ld);
 }
 
+// (ends in metres) A segment can be strictly inside the prism somewhere only if its
+// box meets the open footprint box, both ends are at or above the base and the
+// lower end is below the top: a necessary condition in exact FP32 comparisons
+// (the footprint box is the vertices' box) that spares the FP64 steps.
 __device__ inline bool solid_segment(const SolidLds &S, float4 P, float4 Q, double u, Cnt &c) {
+    const float4 lo = S.lo, hi = S.hi;
+    if (fmaxf(P.x, Q.x) <= lo.x || fminf(P.x, Q.x) >= hi.x || fmaxf(P.y, Q.y) <= lo.y || fminf(P.y, Q.y) >= hi.y ||
+        fminf(P.z, Q.z) < lo.z || fminf(P.z, Q.z) >= hi.z)
+        return false;
     return solid_segment(S, P.x * u, P.y * u, P.z * u, Q.x * u, Q.y * u, Q.z * u, c);
 }
 

@@ -56,3 +56,34 @@ def test_batch_matches_single_scene_calls_on_every_replay(oracle_mod):
             assert torch.equal(batch.counts[k], r[4]), (rep, k, "counts")
     d = ivm.stats_dict(st)
     assert d["pairs_total"] == 3 * sum(s.n_facets * (s.n_facets - 1) // 2 for s in scenes)
+
+
+@pytest.mark.parametrize("exhaustive", [False, True])
+def test_batch_of_many_tiny_scenes(oracle_mod, exhaustive):
+    """Twelve tiny urban scenes plus a one-facet and a two-facet scene in one
+    batch: scene boundaries fall inside the waves' chunks of pairs and probes,
+    and every matrix still equals the single-scene call and the oracle."""
+    import torch
+    import paper_2501_02747_amd as ivm
+    _log(f"[batch] many tiny scenes, exhaustive={exhaustive}")
+    scenes = [sg.gen_c1(40 + k) for k in range(12)]
+    one = sg.gen_plates([[[0, 0, 0], [4, 0, 0], [0, 4, 0]]], tx=[[1, 1, 3]], rx=[[2, 2, 7]])
+    two = sg.gen_plates([[[0, 0, 0], [4, 0, 0], [0, 4, 0]], [[0, 0, 10], [0, 4, 0], [4, 0, 0]]],
+                        tx=[[1, 1, 3]], rx=[[2, 2, 7]])
+    scenes[4:4] = [one]
+    scenes[9:9] = [two]
+    gs = [ivm.GpuScene.from_scene(s).check() for s in scenes]
+    txs = [torch.as_tensor(s.tx).cuda() for s in scenes]
+    rxs = [torch.as_tensor(s.rx).cuda() for s in scenes]
+    opts = ivm.make_opts(exhaustive=exhaustive)
+    batch = ivm.Batch(gs, txs, rxs, opts=opts)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch.run(stream)
+    stream.synchronize()
+    for k, (g, s) in enumerate(zip(gs, scenes)):
+        M = ivm.ivm_intervisibility_matrix(g, opts)
+        torch.cuda.synchronize()
+        assert torch.equal(batch.M[k], M), k
+        Mo, _ = oracle_mod.Oracle(s).matrix()
+        assert (ivm.unpack_bits(batch.M[k], s.n_facets) == Mo).all(), k
