@@ -246,7 +246,9 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
 /* ---- learned occluder ordering ---------------------------------------------
  * A small network scores, for a facet pair, how likely each of the 32 treelets is
  * to hold an occluder; IVM_ORDER_LEARNED visits the treelets in that order.  The
- * exact tests still decide every bit, so the order never changes a result.
+ * exact tests still decide every bit, so the order never changes a result.  The
+ * matrix call runs the network on the pairs its visibility probes leave
+ * undecided, right before the pair kernel.
  * Network: 24 -> 128 -> 128 -> 128 -> 32, ReLU on hidden layers, linear scores;
  * loss: mean binary cross-entropy with logits; optimiser: Adam (beta1 0.9,
  * beta2 0.999, eps 1e-8, bias-corrected).  Parameters are one FP32 array of

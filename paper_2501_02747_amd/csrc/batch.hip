@@ -45,8 +45,6 @@ hipError_t record(ivm_batch *b, hipStream_t s) {
         Scene &sc = it.scene->s;
         if (sc.dev.F >= 2) {
             if ((e = launch_cull_scan(sc, it.d_M, b->stats, s)) != hipSuccess) return e;
-            if (b->o.order_mode == IVM_ORDER_LEARNED && sc.model && sc.lay.learned_bytes)
-                if ((e = launch_learned_order(sc, *sc.model, s)) != hipSuccess) return e;
         } else if ((e = launch_fill_u64(it.d_M, 0ull, (size_t)sc.dev.F * sc.dev.W, s)) != hipSuccess) {
             return e;
         }
@@ -71,6 +69,12 @@ hipError_t record(ivm_batch *b, hipStream_t s) {
         if ((e = undecided_all()) != hipSuccess) return e;
     }
     if (rounds == 0 && (e = undecided_all()) != hipSuccess) return e;
+    for (int k = 0; k < b->n; ++k) {  // the learned treelet order of each scene's undecided pairs
+        Scene &sc = b->items[k].scene->s;
+        if (sc.dev.F >= 2 && b->o.order_mode == IVM_ORDER_LEARNED && sc.model && sc.lay.learned_bytes &&
+            (e = launch_learned_order(sc, *sc.model, s)) != hipSuccess)
+            return e;
+    }
     if ((e = launch_job_base(b->d_pjobs, b->n, b->d_base, true, s)) != hipSuccess) return e;
     if ((e = launch_pair_jobs(b->d_pjobs, b->d_base, b->n, b->d_queue, b->o, b->stats, s)) != hipSuccess) return e;
     for (int k = 0; k < b->n; ++k) {

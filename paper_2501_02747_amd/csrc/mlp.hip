@@ -395,8 +395,9 @@ hipError_t launch_learned_order(Scene &scn, const Model &m, hipStream_t s) {
     char *ws = (char *)scn.ws;
     const Layout &L = scn.lay;
     const int blocks = device_cu_count() * 8;
-    hipLaunchKernelGGL(k_learned, dim3(blocks), dim3(64), 0, s, scn.dev, (const uint64_t *)(ws + L.cand),
-                       (const uint32_t *)(ws + L.prefix), scn.n_items, (const float *)m.params,
+    // over the pairs the probes left undecided (the ones the pair kernel visits)
+    hipLaunchKernelGGL(k_learned, dim3(blocks), dim3(64), 0, s, scn.dev, (const uint64_t *)(ws + L.und),
+                       (const uint32_t *)(ws + L.uprefix), scn.n_items, (const float *)m.params,
                        (uint64_t *)(ws + L.learned));
     return hipGetLastError();
 }

@@ -1511,8 +1511,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             continue;
         }
         unsigned long long lcode = 0;
-        if (o.order_mode == IVM_ORDER_LEARNED && J.learned)  // indexed by the pair's rank among all candidates
-            lcode = J.learned[J.prefix[d_item] + (uint32_t)__popcll(J.cand[d_item] & ((1ull << jbit) - 1ull))];
+        if (o.order_mode == IVM_ORDER_LEARNED && J.learned) lcode = J.learned[gl];  // (per undecided pair)
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
         // near-field tile (the miss queue's storage doubles as the walk frontier)
         // (only for bundles meeting few treelets: a long bundle would overflow the tile anyway)
@@ -1928,11 +1927,7 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
     hipError_t e;
     if (sc.F < 2) return launch_fill_u64(M, 0ull, (size_t)sc.F * sc.W, s);
     if ((e = launch_cull_scan(scn, M, stats, s)) != hipSuccess) return e;
-    bool learned = false;
-    if (o.order_mode == IVM_ORDER_LEARNED && L.learned_bytes && scn.model) {
-        if ((e = launch_learned_order(scn, *scn.model, s)) != hipSuccess) return e;
-        learned = true;
-    }
+    const bool learned = o.order_mode == IVM_ORDER_LEARNED && L.learned_bytes && scn.model;
     const PairJob job = make_pair_job(scn, M, learned);
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
     // probe rounds, each followed by the compaction of the still-undecided pairs
@@ -1944,6 +1939,8 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
         if ((e = launch_undecided(scn, M, s)) != hipSuccess) return e;
     }
     if (o.exhaustive && (e = launch_undecided(scn, M, s)) != hipSuccess) return e;
+    // the learned treelet order of the undecided pairs (network inference)
+    if (learned && (e = launch_learned_order(scn, *scn.model, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PairJob *)nullptr,
                        (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue), o, stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
