@@ -185,49 +185,9 @@ __global__ void k_sample_prep(ivm_scene_desc d, int *ibox, int *status) {
     if (bad) atomicOr(status, bad);
 }
 
-// Convex hull (Andrew's monotone chain, strict turns) of the samples listed in
-// `list` (global indices), projected on the two axes orthogonal to the normal's
-// largest component.  The sample grid makes every cross product an exact FP64
-// integer.  Writes up to kHullMax global sample indices; returns the hull size,
-// or 0 if it is larger (or the list is empty or too long).
-__device__ int sample_hull(const float *samples, const int *list, int ns, int drop, int *out) {
-    if (ns <= 0 || ns > kMaxSamplesPerFacet) return 0;
-    const int ax = drop == 0 ? 1 : 0, ay = drop == 2 ? 1 : 2;
-    int idx[kMaxSamplesPerFacet];
-    for (int m = 0; m < ns; ++m) idx[m] = list[m];
-    auto U = [&](int g) { return (double)samples[3 * g + ax]; };
-    auto V = [&](int g) { return (double)samples[3 * g + ay]; };
-    for (int m = 1; m < ns; ++m) {  // insertion sort by (u, v)
-        int x = idx[m];
-        int k = m - 1;
-        while (k >= 0 && (U(idx[k]) > U(x) || (U(idx[k]) == U(x) && V(idx[k]) > V(x)))) {
-            idx[k + 1] = idx[k];
-            --k;
-        }
-        idx[k + 1] = x;
-    }
-    int h[2 * kMaxSamplesPerFacet + 1];
-    int n = 0;
-    auto turn = [&](int o, int a, int b) {
-        return (U(a) - U(o)) * (V(b) - V(o)) - (V(a) - V(o)) * (U(b) - U(o));
-    };
-    for (int m = 0; m < ns; ++m) {  // lower hull
-        while (n >= 2 && turn(h[n - 2], h[n - 1], idx[m]) <= 0.0) --n;
-        h[n++] = idx[m];
-    }
-    for (int m = ns - 2, lo = n + 1; m >= 0; --m) {  // upper hull
-        while (n >= lo && turn(h[n - 2], h[n - 1], idx[m]) <= 0.0) --n;
-        h[n++] = idx[m];
-    }
-    if (n > 1) --n;  // the last point repeats the first; duplicates collapse
-    if (n > kHullMax) return 0;
-    for (int m = 0; m < n; ++m) out[m] = h[m];
-    return n;
-}
 
 __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane, float *fbox, int *soff,
-                             float4 *smp, int *sfacet, int *ibox, int *status, int *fhull, int *fhull_n,
-                             int *scluster, int *fchull, int *fchull_n) {
+                             float4 *smp, int *sfacet, int *ibox, int *status, int *fhull_n, int *scluster) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.n_facets) return;
     int bad = 0;
@@ -299,9 +259,7 @@ __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane
         in_plane = o == 0.0;
     }
     const bool hull_ok = !(bad & kStDegenerate) && in_plane && ns > 0 && ns <= kMaxSamplesPerFacet;
-    int list[kMaxSamplesPerFacet];
-    for (int m = 0; m < ns && m < kMaxSamplesPerFacet; ++m) list[m] = s0 + m;
-    fhull_n[f] = hull_ok ? sample_hull(d.samples, list, ns, drop, fhull + kHullMax * f) : 0;
+    fhull_n[f] = hull_ok ? 1 : 0;  // a request: k_facet_hulls computes the hulls and their sizes
     // quadrant clusters: split the samples at their centroid along both in-plane axes
     // (exact: u * ns and the sum of u are FP64 integers on the sample grid)
     const int ax = drop == 0 ? 1 : 0, ay = drop == 2 ? 1 : 2;
@@ -310,16 +268,81 @@ __global__ void k_facet_prep(ivm_scene_desc d, const int *ffirst, double *fplane
         su += (double)d.samples[3 * s + ax];
         sv += (double)d.samples[3 * s + ay];
     }
-    for (int cl = 0; cl < 4; ++cl) {
-        int nc = 0;
-        for (int s = s0; s < s1; ++s) {
-            const int c = ((double)d.samples[3 * s + ax] * ns > su ? 1 : 0) + ((double)d.samples[3 * s + ay] * ns > sv ? 2 : 0);
-            if (cl == 0) scluster[s] = c;
-            if (c == cl && nc < kMaxSamplesPerFacet) list[nc++] = s;
-        }
-        fchull_n[4 * f + cl] = hull_ok ? sample_hull(d.samples, list, nc, drop, fchull + (4 * f + cl) * kHullMax) : 0;
-    }
+    for (int s = s0; s < s1; ++s)
+        scluster[s] = ((double)d.samples[3 * s + ax] * ns > su ? 1 : 0) + ((double)d.samples[3 * s + ay] * ns > sv ? 2 : 0);
     if (bad) atomicOr(status, bad);
+}
+
+// Convex hulls of each facet's samples and of its four quadrant clusters, in the
+// plane that drops the normal's largest axis, one wave per facet (four per
+// block): lane m holds sample m's in-plane coordinates and ranks itself in
+// (u, v) order (ties by list position), then one lane per hull runs Andrew's
+// monotone chain over the ordered points in LDS (strict turns only, so
+// collinear and repeated points drop out).  The sample grid makes every cross
+// product an exact FP64 integer.  A hull with more than kHullMax points, or a
+// facet whose request flag is clear, gets size 0 (unavailable).  Each wave uses
+// only its own LDS rows, so waves synchronise on their own.
+__global__ __launch_bounds__(256) void k_facet_hulls(ivm_scene_desc d, const double *fplane, const int *soff,
+                                                     const int *scluster, int *fhull, int *fhull_n, int *fchull,
+                                                     int *fchull_n) {
+    __shared__ float sU[4][kMaxSamplesPerFacet], sV[4][kMaxSamplesPerFacet];
+    __shared__ unsigned char sOrd[4][5][kMaxSamplesPerFacet];
+    __shared__ unsigned char sH[4][5][2 * kMaxSamplesPerFacet + 1];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int f = blockIdx.x * 4 + wv;
+    if (f >= d.n_facets) return;  // (wave-uniform)
+    const bool want = fhull_n[f] != 0;
+    const int s0 = soff[f], ns = want ? soff[f + 1] - s0 : 0;
+    const double *nrm = fplane + 6 * f + 3;
+    const double an0 = fabs(nrm[0]), an1 = fabs(nrm[1]), an2 = fabs(nrm[2]);
+    const int drop = (an0 >= an1 && an0 >= an2) ? 0 : (an1 >= an2 ? 1 : 2);
+    const int ax = drop == 0 ? 1 : 0, ay = drop == 2 ? 1 : 2;
+    const bool act = lane < ns;
+    const float u = act ? d.samples[3 * (s0 + lane) + ax] : 0.f;
+    const float v = act ? d.samples[3 * (s0 + lane) + ay] : 0.f;
+    const int cl = act ? scluster[s0 + lane] : -1;
+    sU[wv][lane] = u;
+    sV[wv][lane] = v;
+    int r = 0, rc = 0;
+    for (int k = 0; k < ns; ++k) {
+        const float uk = __shfl(u, k), vk = __shfl(v, k);
+        const int ck = __shfl(cl, k);
+        const bool before = uk < u || (uk == u && (vk < v || (vk == v && k < lane)));
+        r += before;
+        rc += before && ck == cl;
+    }
+    if (act) {
+        sOrd[wv][0][r] = (unsigned char)lane;
+        sOrd[wv][1 + cl][rc] = (unsigned char)lane;
+    }
+    int ncl[4];
+    for (int c = 0; c < 4; ++c) ncl[c] = __popcll(__ballot(act && cl == c));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 5) {
+        const int n = lane == 0 ? ns : ncl[lane - 1];
+        const unsigned char *o = sOrd[wv][lane];
+        unsigned char *h = sH[wv][lane];
+        auto U = [&](int m) { return (double)sU[wv][m]; };
+        auto V = [&](int m) { return (double)sV[wv][m]; };
+        auto turn = [&](int a, int b, int c) { return (U(b) - U(a)) * (V(c) - V(a)) - (V(b) - V(a)) * (U(c) - U(a)); };
+        int k = 0;
+        for (int m = 0; m < n; ++m) {  // lower hull
+            while (k >= 2 && turn(h[k - 2], h[k - 1], o[m]) <= 0.0) --k;
+            h[k++] = o[m];
+        }
+        for (int m = n - 2, lo = k + 1; m >= 0; --m) {  // upper hull
+            while (k >= lo && turn(h[k - 2], h[k - 1], o[m]) <= 0.0) --k;
+            h[k++] = o[m];
+        }
+        if (k > 1) --k;  // the last point repeats the first
+        if (n <= 0 || k > kHullMax) k = 0;
+        int *out = lane == 0 ? fhull + kHullMax * f : fchull + (4 * f + lane - 1) * kHullMax;
+        for (int m = 0; m < k; ++m) out[m] = s0 + h[m];
+        if (lane == 0) fhull_n[f] = k;
+        else fchull_n[4 * f + lane - 1] = k;
+    }
 }
 
 // Exactness budget (see ivm.h) from the integer boxes.
@@ -746,8 +769,11 @@ hipError_t launch_build(Scene &sc, hipStream_t s) {
     if (F > 0)
         hipLaunchKernelGGL(k_facet_prep, dim3(nblk(F, 128)), dim3(128), 0, s, d, ffirst, (double *)(ws + L.fplane),
                            (float *)(ws + L.fbox), (int *)(ws + L.soff), (float4 *)(ws + L.smp),
-                           (int *)(ws + L.sfacet), ibox, status, (int *)(ws + L.fhull), (int *)(ws + L.fhull_n),
-                           (int *)(ws + L.scluster), (int *)(ws + L.fchull), (int *)(ws + L.fchull_n));
+                           (int *)(ws + L.sfacet), ibox, status, (int *)(ws + L.fhull_n), (int *)(ws + L.scluster));
+    if (F > 0)
+        hipLaunchKernelGGL(k_facet_hulls, dim3(nblk(F, 4)), dim3(256), 0, s, d, (const double *)(ws + L.fplane),
+                           (const int *)(ws + L.soff), (const int *)(ws + L.scluster), (int *)(ws + L.fhull),
+                           (int *)(ws + L.fhull_n), (int *)(ws + L.fchull), (int *)(ws + L.fchull_n));
     hipLaunchKernelGGL(k_budget, dim3(1), dim3(64), 0, s, d, ibox, (double *)(ws + L.extent), status);
     if (T > 0) {
         uint32_t *keys = (uint32_t *)(ws + L.keys), *vals = (uint32_t *)(ws + L.vals);
