@@ -17,9 +17,13 @@ no code.  Each function says which passage of the paper it follows.
   pruning keeps every valid path.
 * ``mlp_*``: FP64 reference of the occluder-ordering network (forward, BCE,
   backward, Adam) and a finite-difference check.
+* ``visibility_ranges``: ray creation and suppression points along a sampled
+  trajectory, the visibility ranges between them and their coherence times
+  (Section III-C; Section III-D, eqs. 8 and 9), in sequential FP64 steps.
 """
 from __future__ import annotations
 
+import bisect
 import ctypes
 import os
 import subprocess
@@ -531,3 +535,91 @@ def mlp_fd_check(p, X, Y, n_probe: int = 20, h: float = 1e-6, seed: int = 0) -> 
             an = g[k][idx]
             worst = max(worst, abs(fd - an) / max(1e-8, abs(fd) + abs(an)))
     return worst
+
+
+# ---------------------------------------------------------------------------
+# Visibility ranges and coherence time along a trajectory (Section III-C: the
+# visibility change nodes of the inter-visibility table of a mobile Tx / Rx;
+# Section III-D: eq. 8, T_c,l = d_l / v_l per visibility range, the smaller of
+# the Tx-side and Rx-side values when both move, eq. 9, the mean over ranges)
+# ---------------------------------------------------------------------------
+
+def visibility_ranges(tx_vis: np.ndarray, rx_vis: np.ndarray, los: np.ndarray, tx: np.ndarray,
+                      rx: np.ndarray, dt: float) -> Dict[str, object]:
+    """Snapshots n = 0..N-1 at times n * dt; snapshot n's visibility holds until
+    snapshot n + 1 and the last snapshot ends the trajectory.
+
+    events[n] (n >= 1, zero for n = 0): facets that became visible from the
+    Tx (ray creation), facets no longer visible from the Tx (suppression), the
+    same two counts for the Rx, and the LoS change (+1 created, -1 suppressed).
+    A side's range ends where its visible set or the LoS changes.  A side range
+    [a, e) (the last one ends at N - 1) has route distance d = sum of the
+    position steps from snapshot a to e, duration tau = (e - a) dt, velocity
+    v = d / tau and coherence time d / v (eq. 8); a side that does not move in
+    it (d = 0) sets no limit (+inf).  The combined ranges start at every change
+    of either side; each takes the smaller coherence time of the two side
+    ranges that contain it, and the mean of the finite ones is eq. 9 (+inf when
+    none is finite).  dist[l] is each side's route distance over combined range
+    l (from its first snapshot to the next range's, or to N - 1).  Returns
+    events int32[N][5], starts int32[L], tc float64[L], dist float64[L][2],
+    mean float64."""
+    tv = np.asarray(tx_vis, bool)
+    rv = np.asarray(rx_vis, bool)
+    lo = np.asarray(los, bool)
+    N = tv.shape[0]
+    P = {0: np.asarray(tx, np.float64), 1: np.asarray(rx, np.float64)}
+    events = np.zeros((N, 5), np.int32)
+    change = np.zeros((N, 2), bool)
+    for n in range(1, N):
+        for s, vis in ((0, tv), (1, rv)):
+            events[n, 2 * s] = int(np.sum(vis[n] & ~vis[n - 1]))
+            events[n, 2 * s + 1] = int(np.sum(~vis[n] & vis[n - 1]))
+        events[n, 4] = int(lo[n]) - int(lo[n - 1])
+        for s in (0, 1):
+            change[n, s] = events[n, 2 * s] != 0 or events[n, 2 * s + 1] != 0 or events[n, 4] != 0
+    starts = [0] + [n for n in range(1, N) if change[n, 0] or change[n, 1]]
+    L = len(starts)
+    tc = [float('inf')] * L
+
+    def step(s, n):  # route distance from snapshot n - 1 to snapshot n
+        d = P[s][n] - P[s][n - 1]
+        return float(np.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]))
+
+    def side_time(d, a, e):
+        tau = (e - a) * dt
+        if not d > 0.0:
+            return float('inf')
+        v = d / tau
+        return d / v
+
+    for s in (0, 1):
+        # this side's ranges: [bounds[r], bounds[r + 1]), the last one to snapshot N - 1
+        bounds = [0] + [n for n in range(1, N) if change[n, s]]
+        for r, a in enumerate(bounds):
+            last = r + 1 == len(bounds)
+            e = N - 1 if last else bounds[r + 1]
+            d = 0.0
+            for n in range(a + 1, e + 1):
+                d += step(s, n)
+            t = side_time(d, a, e)
+            hi = N if last else e  # the combined ranges starting in [a, hi) lie inside this one
+            for l in range(bisect.bisect_left(starts, a), bisect.bisect_left(starts, hi)):
+                tc[l] = min(tc[l], t)
+    dist = np.zeros((L, 2), np.float64)
+    for l in range(L):
+        e = starts[l + 1] if l + 1 < L else N - 1
+        for s in (0, 1):
+            d = 0.0
+            for n in range(starts[l] + 1, e + 1):
+                d += step(s, n)
+            dist[l, s] = d
+    finite = [t for t in tc if t != float('inf')]
+    mean = float('inf')
+    if finite:
+        acc = 0.0
+        for t in finite:
+            acc += t
+        mean = acc / len(finite)
+    return {"events": events, "starts": np.asarray(starts, np.int32), "tc": np.asarray(tc, np.float64),
+            "dist": dist, "mean": mean}
+
