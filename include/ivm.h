@@ -243,6 +243,38 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
                                      int64_t *d_offsets, int32_t *d_paths, size_t paths_cap,
                                      hipStream_t stream);
 
+/* Ray creation and suppression points along one trajectory, the visibility
+ * ranges between them and their coherence times (Section III-C: the visibility
+ * change nodes of the inter-visibility table of a mobile transmitter or
+ * receiver; Section III-D, eq. 8: T_c,l = d_l / v_l; eq. 9: their mean).
+ * Inputs are the outputs of ivm_txrx_visibility_table for n_snap >= 1
+ * snapshots taken dt seconds apart (d_tx_vis, d_rx_vis uint64[N][W], d_los
+ * uint8[N]) and the positions float[N][3] in metres; snapshot n's visibility
+ * holds until snapshot n + 1 and the last snapshot ends the trajectory.
+ * Outputs (caller-owned device memory, capacity N ranges):
+ *   d_events int32[N][5]: for n >= 1 the facets that became visible from the
+ *     Tx (ray creation), the facets no longer visible from it (suppression),
+ *     the same for the Rx, and the LoS change (+1, -1 or 0); row 0 is zero;
+ *   d_n_ranges int32[1]: L, the number of visibility ranges; a range starts at
+ *     snapshot 0 and at every snapshot where either side's visible set or the
+ *     LoS changes; d_range_start int32[L] its first snapshot;
+ *   d_range_tc double[L]: the coherence time (seconds) of each range: for each
+ *     side, its own range containing it (bounded by that side's changes) has
+ *     route distance d (the position steps from its first snapshot to the
+ *     next range's, or to N - 1), duration tau = snapshots x dt, velocity
+ *     v = d / tau and time d / v; the range takes the smaller of the two, and
+ *     a side that does not move (d = 0) sets no limit (+inf when neither moves);
+ *   d_range_dist double[L][2]: each side's route distance over the range;
+ *   d_tc_mean double[1]: the mean of the finite range times (+inf if none).
+ * The counts and ranges are exact; the FP64 distances and times are summed in
+ * snapshot order without contraction.  Asynchronous on `stream`.
+ * Errors: IVM_ERR_INVALID_ARGUMENT (NULL pointers, n_snap < 1, dt not a
+ * positive finite number), IVM_ERR_HIP. */
+ivm_status ivm_visibility_ranges(const ivm_scene *scene, int32_t n_snap, const uint64_t *d_tx_vis,
+                                 const uint64_t *d_rx_vis, const uint8_t *d_los, const float *d_tx, const float *d_rx,
+                                 double dt, int32_t *d_events, int32_t *d_range_start, double *d_range_tc,
+                                 double *d_range_dist, int32_t *d_n_ranges, double *d_tc_mean, hipStream_t stream);
+
 /* ---- learned occluder ordering ---------------------------------------------
  * A small network scores, for a facet pair, how likely each of the 32 treelets is
  * to hold an occluder; IVM_ORDER_LEARNED visits the treelets in that order.  The
