@@ -393,6 +393,35 @@ def main():
         }
         progress(f"{other} order: {statistics.median(times):.2f} ms, identical bits "
                  f"{out['compare_order']['identical_bits']}")
+    # visibility ranges and coherence times along the trajectory (after the table;
+    # outside the step), timed the same way
+    times = []
+    for k in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rr = ivm.ivm_visibility_ranges(g, tv, rv, los, tx, rx, scene.snapshot_dt, read_count=False)
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+    L = int(rr[4].item())
+    out["ranges"] = {"gpu_ms": statistics.median(times), "n_ranges": L, "tc_mean_s": float(rr[5].item()),
+                     "snapshot_dt_s": scene.snapshot_dt}
+    cache = os.path.join(ROOT, "tests", "golden", "cache", f"{scene.name}_seed{scene.seed}.npz")
+    if not args.no_verify and os.path.exists(cache):
+        import oracle
+        z = np.load(cache, allow_pickle=False)
+        tvo = np.unpackbits(z["tx_vis"], axis=1)[:, :F].astype(bool)
+        rvo = np.unpackbits(z["rx_vis"], axis=1)[:, :F].astype(bool)
+        t0 = time.perf_counter()
+        ro = oracle.visibility_ranges(tvo, rvo, z["los"], scene.tx, scene.rx, scene.snapshot_dt)
+        out["ranges"]["oracle_ms"] = 1e3 * (time.perf_counter() - t0)
+        gtc = rr[2][:L].cpu().numpy()
+        fin = ~np.isinf(ro["tc"])
+        out["ranges"]["matches_oracle"] = bool(
+            (rr[0].cpu().numpy() == ro["events"]).all() and rr[1][:L].cpu().numpy().tolist() == ro["starts"].tolist()
+            and (np.isinf(gtc) == ~fin).all() and np.allclose(gtc[fin], ro["tc"][fin], rtol=1e-12, atol=0))
+    progress(f"visibility ranges: {statistics.median(times):.3f} ms, L = {L}")
     if not args.no_verify:
         progress("verifying against the oracle")
         counts_now = counts

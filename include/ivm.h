@@ -266,14 +266,20 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
  *     a side that does not move (d = 0) sets no limit (+inf when neither moves);
  *   d_range_dist double[L][2]: each side's route distance over the range;
  *   d_tc_mean double[1]: the mean of the finite range times (+inf if none).
+ * d_workspace: caller-owned device scratch of at least
+ *   ivm_visibility_ranges_workspace_size(n_snap) bytes, 256-byte aligned;
+ *   its contents on entry do not matter and calls sharing it must not overlap.
  * The counts and ranges are exact; the FP64 distances and times are summed in
  * snapshot order without contraction.  Asynchronous on `stream`.
- * Errors: IVM_ERR_INVALID_ARGUMENT (NULL pointers, n_snap < 1, dt not a
- * positive finite number), IVM_ERR_HIP. */
+ * Errors: IVM_ERR_INVALID_ARGUMENT (NULL pointers, misaligned workspace,
+ * n_snap < 1, dt not a positive finite number), IVM_ERR_WORKSPACE (workspace
+ * too small), IVM_ERR_HIP. */
+ivm_status ivm_visibility_ranges_workspace_size(int32_t n_snap, size_t *bytes);
 ivm_status ivm_visibility_ranges(const ivm_scene *scene, int32_t n_snap, const uint64_t *d_tx_vis,
                                  const uint64_t *d_rx_vis, const uint8_t *d_los, const float *d_tx, const float *d_rx,
-                                 double dt, int32_t *d_events, int32_t *d_range_start, double *d_range_tc,
-                                 double *d_range_dist, int32_t *d_n_ranges, double *d_tc_mean, hipStream_t stream);
+                                 double dt, void *d_workspace, size_t workspace_bytes, int32_t *d_events,
+                                 int32_t *d_range_start, double *d_range_tc, double *d_range_dist, int32_t *d_n_ranges,
+                                 double *d_tc_mean, hipStream_t stream);
 
 /* ---- learned occluder ordering ---------------------------------------------
  * A small network scores, for a facet pair, how likely each of the 32 treelets is

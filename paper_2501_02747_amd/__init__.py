@@ -37,6 +37,7 @@ EXPORTED = [
     "ivm_status_string", "ivm_scene_workspace_size", "ivm_build_scene", "ivm_scene_status",
     "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
     "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups", "ivm_visibility_ranges",
+    "ivm_visibility_ranges_workspace_size",
     "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
@@ -125,7 +126,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_image_tree_candidates.restype = i32
     lib.ivm_image_tree_candidates.argtypes = [P, P, i32, P, P, P, i32, P, P, P, sz, P]
     lib.ivm_visibility_ranges.restype = i32
-    lib.ivm_visibility_ranges.argtypes = [P, i32, P, P, P, P, P, ctypes.c_double, P, P, P, P, P, P, P]
+    lib.ivm_visibility_ranges.argtypes = [P, i32, P, P, P, P, P, ctypes.c_double, P, sz, P, P, P, P, P, P, P]
+    lib.ivm_visibility_ranges_workspace_size.restype = i32
+    lib.ivm_visibility_ranges_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
     lib.ivm_triangle_groups.restype = i32
     lib.ivm_triangle_groups.argtypes = [P, P, P]
     lib.ivm_model_workspace_size.restype = i32
@@ -407,10 +410,13 @@ def ivm_image_tree_candidates(scene: GpuScene, M, tx_vis, rx_vis, los, max_order
     return counts, offsets, paths
 
 
-def ivm_visibility_ranges(scene: GpuScene, tx_vis, rx_vis, los, tx, rx, dt: float, stream=None):
+def ivm_visibility_ranges(scene: GpuScene, tx_vis, rx_vis, los, tx, rx, dt: float, stream=None,
+                          read_count: bool = True):
     """Ray creation / suppression counts int32 [N, 5], visibility range starts
     int32 [L], coherence times float64 [L], route distances float64 [L, 2] and
-    the mean time (a float): device tensors, L read back after a stream sync."""
+    the mean time (a float): device tensors, L read back after a stream sync.
+    With read_count=False nothing is synchronised and the full-capacity tensors
+    come back with L and the mean as one-element device tensors."""
     import torch
     N = int(tx_vis.shape[0])
     dev = scene.device
@@ -421,9 +427,14 @@ def ivm_visibility_ranges(scene: GpuScene, tx_vis, rx_vis, los, tx, rx, dt: floa
     nr = torch.empty((1,), dtype=torch.int32, device=dev)
     mean = torch.empty((1,), dtype=torch.float64, device=dev)
     lib = load_library()
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.ivm_visibility_ranges_workspace_size(N, ctypes.byref(nbytes)), "ivm_visibility_ranges_workspace_size")
+    ws = torch.empty((nbytes.value + 255) // 256 * 32, dtype=torch.float64, device=dev)  # 256-B aligned
     _check(lib.ivm_visibility_ranges(scene.handle, N, _ptr(tx_vis), _ptr(rx_vis), _ptr(los), _ptr(tx), _ptr(rx),
-                                     float(dt), _ptr(events), _ptr(starts), _ptr(tc), _ptr(dist), _ptr(nr),
-                                     _ptr(mean), _stream(stream)), "ivm_visibility_ranges")
+                                     float(dt), _ptr(ws), ws.numel() * 8, _ptr(events), _ptr(starts), _ptr(tc),
+                                     _ptr(dist), _ptr(nr), _ptr(mean), _stream(stream)), "ivm_visibility_ranges")
+    if not read_count:
+        return events, starts, tc, dist, nr, mean
     if stream is not None:
         stream.synchronize()
     L = int(nr.item())

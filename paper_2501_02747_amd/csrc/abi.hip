@@ -256,16 +256,24 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
     return IVM_OK;
 }
 
+ivm_status ivm_visibility_ranges_workspace_size(int32_t n_snap, size_t *bytes) {
+    if (!bytes || n_snap < 1) return IVM_ERR_INVALID_ARGUMENT;
+    *bytes = ranges_workspace_bytes(n_snap);
+    return IVM_OK;
+}
+
 ivm_status ivm_visibility_ranges(const ivm_scene *scene, int32_t n_snap, const uint64_t *d_tx_vis,
                                  const uint64_t *d_rx_vis, const uint8_t *d_los, const float *d_tx, const float *d_rx,
-                                 double dt, int32_t *d_events, int32_t *d_range_start, double *d_range_tc,
-                                 double *d_range_dist, int32_t *d_n_ranges, double *d_tc_mean, hipStream_t stream) {
+                                 double dt, void *d_workspace, size_t workspace_bytes, int32_t *d_events,
+                                 int32_t *d_range_start, double *d_range_tc, double *d_range_dist, int32_t *d_n_ranges,
+                                 double *d_tc_mean, hipStream_t stream) {
     if (!scene || n_snap < 1 || !(dt > 0.0) || !std::isfinite(dt)) return IVM_ERR_INVALID_ARGUMENT;
     if (!d_tx_vis || !d_rx_vis || !d_los || !d_tx || !d_rx || !d_events || !d_range_start || !d_range_tc ||
-        !d_range_dist || !d_n_ranges || !d_tc_mean)
+        !d_range_dist || !d_n_ranges || !d_tc_mean || !d_workspace || ((uintptr_t)d_workspace & 255u))
         return IVM_ERR_INVALID_ARGUMENT;
-    if (launch_ranges(scene->s.dev, n_snap, d_tx_vis, d_rx_vis, d_los, d_tx, d_rx, dt, d_events, d_range_start,
-                      d_range_tc, d_range_dist, d_n_ranges, d_tc_mean, stream) != hipSuccess)
+    if (workspace_bytes < ranges_workspace_bytes(n_snap)) return IVM_ERR_WORKSPACE;
+    if (launch_ranges(scene->s.dev, n_snap, d_tx_vis, d_rx_vis, d_los, d_tx, d_rx, dt, d_workspace, d_events,
+                      d_range_start, d_range_tc, d_range_dist, d_n_ranges, d_tc_mean, stream) != hipSuccess)
         return IVM_ERR_HIP;
     return IVM_OK;
 }

@@ -218,8 +218,9 @@ hipError_t model_adam(Model &m, float lr, hipStream_t s);
 size_t model_workspace_bytes(int max_batch);
 void model_bind(Model &m, void *ws, int max_batch, int precision);
 hipError_t launch_cull_scan(Scene &sc, uint64_t *M, ivm_stats *stats, hipStream_t s);
+size_t ranges_workspace_bytes(int N);
 hipError_t launch_ranges(const SceneDev &sc, int N, const uint64_t *tv, const uint64_t *rv, const uint8_t *los,
-                         const float *tx, const float *rx, double dt, int *events, int *starts, double *tc,
+                         const float *tx, const float *rx, double dt, void *ws, int *events, int *starts, double *tc,
                          double *dist, int *n_ranges, double *mean, hipStream_t s);
 constexpr int kProbeRounds = 2;  // probe passes over the candidate pairs before the pair kernel
 hipError_t launch_undecided(Scene &scn, uint64_t *M, hipStream_t s);

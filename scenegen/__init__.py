@@ -77,6 +77,7 @@ class Scene:
     sample_offsets i32[F+1]    CSR offsets into samples
     samples        f32[S][3]   metres, multiples of 2^-(g+k)
     tx, rx         f32[N][3]   Tx / Rx positions per snapshot (sample grid)
+    snapshot_dt    seconds between consecutive snapshots of a trajectory
     """
     name: str
     seed: int
@@ -91,6 +92,7 @@ class Scene:
     facet_building: np.ndarray
     tx: np.ndarray
     rx: np.ndarray
+    snapshot_dt: float = 0.01
 
     @property
     def n_facets(self) -> int:
