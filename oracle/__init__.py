@@ -20,6 +20,8 @@ no code.  Each function says which passage of the paper it follows.
 * ``visibility_ranges``: ray creation and suppression points along a sampled
   trajectory, the visibility ranges between them and their coherence times
   (Section III-C; Section III-D, eqs. 8 and 9), in sequential FP64 steps.
+* ``interface_relations``: the interface relation of each visible facet pair
+  (parallel or perpendicular planes, Section II-B, Table I) in exact integers.
 """
 from __future__ import annotations
 
@@ -622,4 +624,50 @@ def visibility_ranges(tx_vis: np.ndarray, rx_vis: np.ndarray, los: np.ndarray, t
         mean = acc / len(finite)
     return {"events": events, "starts": np.asarray(starts, np.int32), "tc": np.asarray(tc, np.float64),
             "dist": dist, "mean": mean}
+
+
+# ---------------------------------------------------------------------------
+# Interface relations of the inter-visibility matrix (Section II-B, Table I:
+# reference face, aim face and whether their planes are parallel (PAR) or
+# perpendicular (PER); the horizontal view holds relations between vertical
+# faces, a vertical view those involving horizontal faces)
+# ---------------------------------------------------------------------------
+
+def facet_normals_int(scene) -> List[Tuple[int, int, int]]:
+    """The normal (b - a) x (c - a) of each facet's first triangle in vertex-grid
+    units, as exact Python integers (the plane triple of the visible-side rule)."""
+    su = 1 << scene.g
+    V = [[int(round(float(x) * su)) for x in v] for v in np.asarray(scene.vertices, np.float64)]
+    tv = np.asarray(scene.tri_vertices)
+    tf = np.asarray(scene.tri_facet)
+    out = []
+    for f in range(scene.n_facets):
+        t = int(np.searchsorted(tf, f))
+        a, b, c = (V[int(tv[t, m])] for m in range(3))
+        e1 = [b[k] - a[k] for k in range(3)]
+        e2 = [c[k] - a[k] for k in range(3)]
+        out.append((e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]))
+    return out
+
+
+def interface_relations(scene, M: np.ndarray) -> Dict[str, np.ndarray]:
+    """par[i, j] / per[i, j]: M[i, j] and the two facets' planes are parallel
+    (normals' cross product zero) / perpendicular (dot product zero); cls[f]:
+    0 vertical facet (normal z = 0), 1 horizontal (normal x = y = 0), 2 other."""
+    nrm = facet_normals_int(scene)
+    F = len(nrm)
+    M = np.asarray(M, bool)
+    par = np.zeros((F, F), bool)
+    per = np.zeros((F, F), bool)
+    for i in range(F):
+        a = nrm[i]
+        for j in range(F):
+            if not M[i, j]:
+                continue
+            b = nrm[j]
+            cross = (a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0])
+            par[i, j] = cross == (0, 0, 0)
+            per[i, j] = a[0] * b[0] + a[1] * b[1] + a[2] * b[2] == 0
+    cls = np.array([0 if n[2] == 0 else (1 if n[0] == 0 and n[1] == 0 else 2) for n in nrm], np.int8)
+    return {"par": par, "per": per, "cls": cls}
 
