@@ -422,6 +422,19 @@ def main():
             (rr[0].cpu().numpy() == ro["events"]).all() and rr[1][:L].cpu().numpy().tolist() == ro["starts"].tolist()
             and (np.isinf(gtc) == ~fin).all() and np.allclose(gtc[fin], ro["tc"][fin], rtol=1e-12, atol=0))
     progress(f"visibility ranges: {statistics.median(times):.3f} ms, L = {L}")
+    # interface relations (PAR / PER) of the visible pairs of the matrix
+    times = []
+    for k in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        par, per, fcls = ivm.ivm_interface_relations(g, M)
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+    out["relations"] = {"gpu_ms": statistics.median(times),
+                        "par_pairs": int(ivm.unpack_bits(par, F).sum()) // 2,
+                        "per_pairs": int(ivm.unpack_bits(per, F).sum()) // 2}
     if not args.no_verify:
         progress("verifying against the oracle")
         counts_now = counts

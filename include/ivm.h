@@ -243,6 +243,19 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
                                      int64_t *d_offsets, int32_t *d_paths, size_t paths_cap,
                                      hipStream_t stream);
 
+/* Interface relations of the visible facet pairs (Section II-B, Table I: the
+ * reference face and the aim face are parallel, PAR, or perpendicular, PER).
+ * d_M is a matrix from ivm_intervisibility_matrix; d_par and d_per are
+ * uint64[F][W] in its layout, bit (i, j) set when M[i][j] and the planes of
+ * facets i and j are parallel / perpendicular (exact integer tests on the
+ * normals of the facets' first triangles); d_facet_class is int8[F]: 0 for a
+ * vertical facet, 1 horizontal, 2 other (relations between vertical facets
+ * belong to the horizontal view, the others to a vertical view).  All
+ * caller-owned device memory; asynchronous on `stream`.
+ * Errors: IVM_ERR_INVALID_ARGUMENT, IVM_ERR_HIP. */
+ivm_status ivm_interface_relations(const ivm_scene *scene, const uint64_t *d_M, uint64_t *d_par, uint64_t *d_per,
+                                   int8_t *d_facet_class, hipStream_t stream);
+
 /* Ray creation and suppression points along one trajectory, the visibility
  * ranges between them and their coherence times (Section III-C: the visibility
  * change nodes of the inter-visibility table of a mobile transmitter or

@@ -37,7 +37,7 @@ EXPORTED = [
     "ivm_status_string", "ivm_scene_workspace_size", "ivm_build_scene", "ivm_scene_status",
     "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
     "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups", "ivm_visibility_ranges",
-    "ivm_visibility_ranges_workspace_size",
+    "ivm_visibility_ranges_workspace_size", "ivm_interface_relations",
     "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
@@ -127,6 +127,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_image_tree_candidates.argtypes = [P, P, i32, P, P, P, i32, P, P, P, sz, P]
     lib.ivm_visibility_ranges.restype = i32
     lib.ivm_visibility_ranges.argtypes = [P, i32, P, P, P, P, P, ctypes.c_double, P, sz, P, P, P, P, P, P, P]
+    lib.ivm_interface_relations.restype = i32
+    lib.ivm_interface_relations.argtypes = [P, P, P, P, P, P]
     lib.ivm_visibility_ranges_workspace_size.restype = i32
     lib.ivm_visibility_ranges_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
     lib.ivm_triangle_groups.restype = i32
@@ -408,6 +410,18 @@ def ivm_image_tree_candidates(scene: GpuScene, M, tx_vis, rx_vis, los, max_order
                                            _stream(stream))
     _check(st, "ivm_image_tree_candidates")
     return counts, offsets, paths
+
+
+def ivm_interface_relations(scene: GpuScene, M, stream=None):
+    """(par, per) int64 [F, W] bit matrices in M's layout and the facet classes int8 [F]."""
+    import torch
+    par = torch.empty_like(M)
+    per = torch.empty_like(M)
+    cls = torch.empty((max(scene.F, 1),), dtype=torch.int8, device=scene.device)
+    lib = load_library()
+    _check(lib.ivm_interface_relations(scene.handle, _ptr(M), _ptr(par), _ptr(per), _ptr(cls), _stream(stream)),
+           "ivm_interface_relations")
+    return par, per, cls[:scene.F]
 
 
 def ivm_visibility_ranges(scene: GpuScene, tx_vis, rx_vis, los, tx, rx, dt: float, stream=None,

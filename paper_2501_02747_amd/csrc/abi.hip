@@ -256,6 +256,13 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
     return IVM_OK;
 }
 
+ivm_status ivm_interface_relations(const ivm_scene *scene, const uint64_t *d_M, uint64_t *d_par, uint64_t *d_per,
+                                   int8_t *d_facet_class, hipStream_t stream) {
+    if (!scene || !d_M || !d_par || !d_per || !d_facet_class) return IVM_ERR_INVALID_ARGUMENT;
+    if (launch_relations(scene->s.dev, d_M, d_par, d_per, d_facet_class, stream) != hipSuccess) return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
 ivm_status ivm_visibility_ranges_workspace_size(int32_t n_snap, size_t *bytes) {
     if (!bytes || n_snap < 1) return IVM_ERR_INVALID_ARGUMENT;
     *bytes = ranges_workspace_bytes(n_snap);

@@ -218,6 +218,8 @@ hipError_t model_adam(Model &m, float lr, hipStream_t s);
 size_t model_workspace_bytes(int max_batch);
 void model_bind(Model &m, void *ws, int max_batch, int precision);
 hipError_t launch_cull_scan(Scene &sc, uint64_t *M, ivm_stats *stats, hipStream_t s);
+hipError_t launch_relations(const SceneDev &sc, const uint64_t *M, uint64_t *par, uint64_t *per, int8_t *cls,
+                            hipStream_t s);
 size_t ranges_workspace_bytes(int N);
 hipError_t launch_ranges(const SceneDev &sc, int N, const uint64_t *tv, const uint64_t *rv, const uint8_t *los,
                          const float *tx, const float *rx, double dt, void *ws, int *events, int *starts, double *tc,
