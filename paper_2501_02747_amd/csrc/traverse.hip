@@ -2061,8 +2061,10 @@ __device__ unsigned certify_point_facets(const SceneDev &sc, int nf, int f0, int
     const int f = g == 0 ? f0 : (g == 1 ? f1 : (g == 2 ? f2 : f3));
     const int fs = live ? f : f0;                    // (idle groups read facet f0's data)
     const int nh = live ? sc.fhull_n[fs] : 0;
-    const float4 corner = sc.smp[sc.fhull[kHullMax * fs + (r < nh ? r : 0)]];
-    const float4 corner0 = sc.smp[sc.fhull[kHullMax * fs]];
+    // (hull entries exist only for nh > 0: no index is read otherwise)
+    const float4 none = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 corner = nh > 0 ? sc.smp[sc.fhull[kHullMax * fs + (r < nh ? r : 0)]] : none;
+    const float4 corner0 = nh > 0 ? sc.smp[sc.fhull[kHullMax * fs]] : none;
     const float *fb = sc.fbox + 6 * fs;
     const float cx = 0.5f * (fb[0] + fb[3]), cy = 0.5f * (fb[1] + fb[4]);
     const float bx0 = fminf(X.x, fb[0]), bx1 = fmaxf(X.x, fb[3]), by0 = fminf(X.y, fb[1]), by1 = fmaxf(X.y, fb[4]);
