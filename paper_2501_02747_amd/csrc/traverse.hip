@@ -590,7 +590,7 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
     j = (item - i * sc.W) * 64 + bit;
 }
 
-constexpr int kCache = 4;  // recent blockers tested before a traversal
+constexpr int kCache = 2;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
 constexpr int kScanMaxSolids = 4096;  // scenes with at most this many solids scan them all per pair
 constexpr int kScanTries = 4;         // solids from the scan tried per pair
