@@ -37,6 +37,32 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_BOX, OPS_TRI, OPS_RECHECK, OPS_SOLID_PLANE = 14, 43, 35, 25
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_pairs_urban_grid_c2.txt")
+
+
+def profiled_traffic(config: str):
+    """HBM bytes of one matrix call's pair kernels (two probe rounds and the pair
+    kernel) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the
+    urban-grid workload, or None when it is another workload or the traversal
+    source has changed since the counters were taken."""
+    import hashlib
+    import re
+    if config != "c2" or not os.path.exists(PROFILE):
+        return None
+    text = open(PROFILE).read()
+    m = re.search(r"sha256: ([0-9a-f]{64})", text)
+    src = os.path.join(ROOT, "paper_2501_02747_amd", "csrc", "traverse.hip")
+    if not m or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
+        return None
+    mib = {}
+    for name in ("k_pairs<false>", "k_probe_pairs<false>"):
+        r = re.search(re.escape(name) + r"\s+fetch\s+([0-9.]+) MiB\s+write\s+([0-9.]+) MiB", text)
+        if not r:
+            return None
+        mib[name] = float(r.group(1)) + float(r.group(2))
+    return int((mib["k_pairs<false>"] + 2 * mib["k_probe_pairs<false>"]) * 2 ** 20)
+
+
 def lane_ops(st: dict) -> int:
     return (st["box_tests"] * OPS_BOX + st["tri_tests"] * OPS_TRI + st["rechecks"] * OPS_RECHECK
             + st["solid_planes"] * OPS_SOLID_PLANE)
@@ -359,7 +385,8 @@ def main():
         "stats_matrix": sm,
         "stats_table": sp,
         "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
-                     "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": ach / VALU_PEAK_TOPS, "traffic": profiled_traffic(args.config),
+                     "traffic_unit": "HBM bytes per matrix call (FETCH_SIZE + WRITE_SIZE, from profiles/)",
                      "kernel": "k_probe_pairs + k_pairs (one timed region)", "ops_per_launch": ops_pairs},
         "roofline_points": {"bound": "alu", "achieved": ach_p, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
                             "frac": ach_p / VALU_PEAK_TOPS, "kernel": "k_points"},
