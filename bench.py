@@ -462,6 +462,34 @@ def main():
     out["relations"] = {"gpu_ms": statistics.median(times),
                         "par_pairs": int(ivm.unpack_bits(par, F).sum()) // 2,
                         "per_pairs": int(ivm.unpack_bits(per, F).sum()) // 2}
+    # image-tree candidate counts of orders up to 4 (the orders timed in Section IV-C)
+    # over every snapshot of the table, outside the step
+    times = []
+    for k in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c4 = ivm.ivm_image_tree_candidates(g, M, tv, rv, los, 4)
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+    c4np = c4.cpu().numpy()
+    out["candidates_order4"] = {"gpu_ms": statistics.median(times), "snapshots": int(c4np.shape[0]),
+                                "walks_per_order": [int(x) for x in c4np[:, 1:].sum(0)]}
+    if not args.no_verify and os.path.exists(cache):
+        import oracle
+        z = np.load(cache, allow_pickle=False)
+        pick = np.arange(0, int(z["los"].shape[0]), 10) if z["los"].shape[0] == c4np.shape[0] else np.arange(0)
+        if len(pick):
+            Mo = np.unpackbits(z["M"], axis=1)[:, :F].astype(bool)
+            tvo = np.unpackbits(z["tx_vis"], axis=1)[pick, :F].astype(bool)
+            rvo = np.unpackbits(z["rx_vis"], axis=1)[pick, :F].astype(bool)
+            t0 = time.perf_counter()
+            co4 = oracle.candidates_matmul(Mo, tvo, rvo, z["los"][pick], 4)
+            out["candidates_order4"]["oracle_ms_sample"] = 1e3 * (time.perf_counter() - t0)
+            out["candidates_order4"]["oracle_sample"] = f"every 10th snapshot ({len(pick)})"
+            out["candidates_order4"]["matches_oracle"] = bool((c4np[pick] == co4).all())
+    progress(f"candidates up to order 4: {statistics.median(times):.3f} ms")
     if not args.no_verify:
         progress("verifying against the oracle")
         counts_now = counts

@@ -228,15 +228,20 @@ ivm_status ivm_txrx_visibility_table(ivm_scene *scene, const ivm_matrix_opts *op
                                      uint64_t *d_rx_vis, uint8_t *d_los, ivm_stats *d_stats,
                                      hipStream_t stream);
 
-/* Image-tree reflection candidates up to max_order (1..2) per snapshot: walks
+/* Image-tree reflection candidates up to max_order (1..4) per snapshot: walks
  * f1 -> ... -> fk with tx_vis(f1), M[f_m][f_m+1] and rx_vis(fk) (Section III-B,
- * Table II: transmitter -> reference face -> aim face).  d_counts is
- * int64[N][max_order + 1] with column 0 = line of sight.  If d_paths is NULL
+ * Table II: transmitter -> reference face -> aim face; orders 3 and 4 are the
+ * iteration of Section II-C to the orders timed in Section IV-C).  d_M need not
+ * be symmetric.  d_counts is int64[N][max_order + 1] with column 0 = line of
+ * sight; counts are exact (orders 3 and 4 need F <= 40960 and an LDS of about
+ * 4 F bytes per block, else IVM_ERR_INVALID_ARGUMENT).  If d_paths is NULL
  * only counts are produced (asynchronous).  Otherwise d_offsets (int64[N *
  * max_order + 1]) receives CSR offsets of the lists (snapshot-major, order-minor)
  * and d_paths the k-tuples as int32 in lexicographic order; this mode
  * synchronises the stream once to check paths_cap (in int32 elements) and
- * returns IVM_ERR_CAPACITY, with valid counts and offsets, when it is too small. */
+ * returns IVM_ERR_CAPACITY, with valid counts and offsets, when it is too small.
+ * Lists of orders 3 and 4 grow as |tx| d^2 and |tx| d^3 for rows of d set bits:
+ * they are meant for small scenes; counts scale to full-size tables. */
 ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int32_t n_snap,
                                      const uint64_t *d_tx_vis, const uint64_t *d_rx_vis,
                                      const uint8_t *d_los, int32_t max_order, int64_t *d_counts,

@@ -245,8 +245,12 @@ def candidates_enum(M: np.ndarray, tx_vis: np.ndarray, rx_vis: np.ndarray, los: 
 
 def candidates_matmul(M: np.ndarray, tx_vis: np.ndarray, rx_vis: np.ndarray, los: np.ndarray,
                       K: int) -> np.ndarray:
-    """Same counts by integer vector-matrix products: c_k = t^T M^(k-1) r."""
-    Mi = np.asarray(M, np.int64)
+    """Same counts by integer vector-matrix products: c_k = t^T M^(k-1) r.
+    M may be a dense boolean array or a scipy sparse matrix (for large F; the
+    product is the same integer product, taken as M^T w^T)."""
+    import scipy.sparse as sps
+    sparse = sps.issparse(M)
+    Mi = sps.csr_matrix(M, dtype=np.int64) if sparse else np.asarray(M, np.int64)
     t = np.asarray(tx_vis, np.int64)
     r = np.asarray(rx_vis, np.int64)
     N = t.shape[0]
@@ -255,7 +259,7 @@ def candidates_matmul(M: np.ndarray, tx_vis: np.ndarray, rx_vis: np.ndarray, los
     w = t.copy()
     for k in range(1, K + 1):
         counts[:, k] = (w * r).sum(1)
-        w = w @ Mi
+        w = np.asarray(Mi.T @ w.T).T if sparse else w @ Mi
     return counts
 
 

@@ -231,11 +231,12 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
                                      const uint64_t *d_tx_vis, const uint64_t *d_rx_vis, const uint8_t *d_los,
                                      int32_t max_order, int64_t *d_counts, int64_t *d_offsets, int32_t *d_paths,
                                      size_t paths_cap, hipStream_t stream) {
-    if (!scene || n_snap < 0 || max_order < 1 || max_order > 2) return IVM_ERR_INVALID_ARGUMENT;
+    if (!scene || n_snap < 0 || max_order < 1 || max_order > 4) return IVM_ERR_INVALID_ARGUMENT;
     if (n_snap > 0 && (!d_M || !d_tx_vis || !d_rx_vis || !d_los || !d_counts)) return IVM_ERR_INVALID_ARGUMENT;
     if (d_paths && !d_offsets) return IVM_ERR_INVALID_ARGUMENT;
     const SceneDev &d = scene->s.dev;
     if (n_snap == 0) return IVM_OK;
+    if (max_order >= 3 && !candidates_high_fits(d.F)) return IVM_ERR_INVALID_ARGUMENT;
     if (launch_candidates_count(d, d_M, n_snap, d_tx_vis, d_rx_vis, d_los, max_order, d_counts, stream) != hipSuccess)
         return IVM_ERR_HIP;
     if (!d_paths) {

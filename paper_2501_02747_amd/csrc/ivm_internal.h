@@ -198,6 +198,11 @@ hipError_t launch_matrix(Scene &sc, const TraverseOpts &o, uint64_t *M, ivm_stat
                          const uint8_t *learned_order, hipStream_t s);
 hipError_t launch_points(Scene &sc, const TraverseOpts &o, int N, const float *tx, const float *rx,
                          uint64_t *txv, uint64_t *rxv, uint8_t *los, ivm_stats *stats, hipStream_t s);
+// Orders 3 and 4 of the candidate counts keep two F-entry vectors in LDS: the
+// largest F they accept (F^4 < 2^63 keeps the int64 counts exact), and whether
+// the device's LDS per block holds them for F facets.
+constexpr int kCandHighMaxF = 40960;
+bool candidates_high_fits(int F);
 hipError_t launch_candidates_count(const SceneDev &d, const uint64_t *M, int N, const uint64_t *txv,
                                    const uint64_t *rxv, const uint8_t *los, int K, int64_t *counts,
                                    hipStream_t s);

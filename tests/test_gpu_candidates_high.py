@@ -1,0 +1,200 @@
+"""GPU parity of the image-tree candidates of orders 3 and 4 (the iteration of
+Section II-C to the orders timed in Section IV-C) against the oracle's walk
+enumeration and integer products, through the C ABI.  Counts and lists are
+integers: the bar is exact equality.  Inputs are seeded tables or oracle
+matrices and tables of seeded scenes; no expected value comes from the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ivm():
+    import torch
+    import paper_2501_02747_amd as ivm
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    ivm.load_library()
+    return ivm
+
+
+def _plate_row_scene(ivm, F):
+    """F small plates on a line: a valid scene with exactly F facets (W = ceil(F/64))."""
+    x = np.arange(F, dtype=np.float32)
+    V = np.stack([np.stack([x, 0 * x, 0 * x], 1), np.stack([x + 0.5, 0 * x, 0 * x], 1),
+                  np.stack([x + 0.5, 0 * x + 0.5, 0 * x], 1), np.stack([x, 0 * x + 0.5, 0 * x], 1)], 1)
+    base = 4 * np.arange(F, dtype=np.int32)[:, None]
+    T = np.stack([np.concatenate([base, base + 1, base + 2], 1), np.concatenate([base, base + 2, base + 3], 1)], 1)
+    TF = np.repeat(np.arange(F, dtype=np.int32), 2)
+    SM = np.stack([x + 0.25, 0 * x + 0.25, 0 * x], 1)
+    OFF = np.arange(F + 1, dtype=np.int32)
+    return ivm.GpuScene(V.reshape(-1, 3), T.reshape(-1, 3), TF, OFF, SM, 2, 2).check()
+
+
+def _upload(ivm, M, tv, rv, los):
+    import torch
+    return (torch.as_tensor(ivm.pack_bits(M)).cuda(), torch.as_tensor(ivm.pack_bits(tv)).cuda(),
+            torch.as_tensor(ivm.pack_bits(rv)).cuda(), torch.as_tensor(np.asarray(los, np.uint8)).cuda())
+
+
+def _check_lists(off, paths, lists, N, K):
+    off = off.cpu().numpy()
+    paths = paths.cpu().numpy()
+    for n in range(N):
+        for k in range(1, K + 1):
+            a, b = off[n * K + k - 1], off[n * K + k]
+            got = [tuple(int(x) for x in paths[p:p + k]) for p in range(a, b, k)]
+            assert got == lists[n][k - 1], (n, k)
+
+
+@pytest.mark.parametrize("F,sym,seed", [(23, True, 0), (70, False, 1), (130, True, 2), (191, False, 3)])
+def test_orders_3_4_random_tables(oracle_mod, ivm, F, sym, seed):
+    """Seeded random tables, symmetric and one-sided matrices, ragged F (padding
+    words), an empty and a full snapshot: counts and lexicographic lists of
+    orders 1-4 equal the oracle's enumeration; max_order 3 equals the first
+    columns of max_order 4."""
+    import torch
+    _log(f"[orders 3-4 random] F={F} sym={sym} seed={seed}")
+    rng = np.random.default_rng(100 + seed)
+    N = 9
+    dens = min(0.3, 10.0 / F)
+    M = rng.random((F, F)) < dens
+    if sym:
+        M = M | M.T
+    np.fill_diagonal(M, False)
+    tv = rng.random((N, F)) < 0.15
+    rv = rng.random((N, F)) < 0.15
+    tv[0] = False                 # nothing visible from Tx
+    tv[1] = True                  # everything visible from both sides
+    rv[1] = True
+    los = rng.random(N) < 0.5
+    g = _plate_row_scene(ivm, F)
+    dM, dtv, drv, dlos = _upload(ivm, M, tv, rv, los)
+    # (the oracle enumerates the all-visible snapshot, |F| d^3 walks, on the small F only)
+    rows = [n for n in range(N) if n != 1 or F < 100]
+    for K in (3, 4):
+        counts, off, paths = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, K, lists=True)
+        torch.cuda.synchronize()
+        co = oracle_mod.candidates_matmul(M, tv, rv, los, K)
+        assert (counts.cpu().numpy() == co).all(), K
+        sel = np.array(rows)
+        ce, L = oracle_mod.candidates_enum(M, tv[sel], rv[sel], los[sel], K)
+        assert (ce == co[sel]).all()
+        off_np = off.cpu().numpy()
+        paths_np = paths.cpu().numpy()
+        for i, n in enumerate(rows):
+            for k in range(1, K + 1):
+                a, b = off_np[n * K + k - 1], off_np[n * K + k]
+                got = [tuple(int(x) for x in paths_np[p:p + k]) for p in range(a, b, k)]
+                assert got == L[i][k - 1], (n, k)
+        if K == 3:
+            c3 = counts.cpu().numpy()
+        else:
+            assert (counts.cpu().numpy()[:, :4] == c3).all()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_orders_3_4_oracle_tables_c1(oracle_mod, ivm, seed):
+    """The oracle's own matrix and tables of the tiny urban scene (42 facets, 10
+    snapshots) as inputs: counts and lists of orders 1-4 equal the oracle's
+    enumeration."""
+    import torch
+    _log(f"[orders 3-4 c1] seed={seed}")
+    s = sg.gen_c1(seed)
+    orc = oracle_mod.Oracle(s)
+    M, _ = orc.matrix()
+    tv, rv, los = orc.txrx(s.tx, s.rx)
+    g = ivm.GpuScene.from_scene(s).check()
+    dM, dtv, drv, dlos = _upload(ivm, M, tv, rv, los)
+    counts, off, paths = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 4, lists=True)
+    torch.cuda.synchronize()
+    N = s.tx.shape[0]
+    ce, L = oracle_mod.candidates_enum(M, tv, rv, los, 4)
+    assert (counts.cpu().numpy() == ce).all()
+    _check_lists(off, paths, L, N, 4)
+
+
+def test_parallel_mirrors_end_to_end(oracle_mod, ivm):
+    """Two parallel mirrors with Tx and Rx between them: exactly two walks of
+    every order (the closed form the oracle is pinned to), from the GPU's own
+    matrix, tables and candidates."""
+    import torch
+    s = sg.gen_plates([
+        [[0, -40, -40], [0, 80, 0], [0, 0, 80]],
+        [[10, -40, -40], [0, 0, 80], [0, 80, 0]],
+    ], tx=[[3, -2, 1]], rx=[[6, 5, -1]])
+    g = ivm.GpuScene.from_scene(s).check()
+    M = ivm.ivm_intervisibility_matrix(g)
+    tv, rv, los = ivm.ivm_txrx_visibility_table(g, torch.as_tensor(s.tx).cuda(), torch.as_tensor(s.rx).cuda())
+    counts, off, paths = ivm.ivm_image_tree_candidates(g, M, tv, rv, los, 4, lists=True)
+    torch.cuda.synchronize()
+    assert g.status() == 0
+    assert counts.cpu().numpy()[0].tolist() == [1, 2, 2, 2, 2]
+    _check_lists(off, paths, [[[(0,), (1,)], [(0, 1), (1, 0)], [(0, 1, 0), (1, 0, 1)],
+                               [(0, 1, 0, 1), (1, 0, 1, 0)]]], 1, 4)
+
+
+def test_orders_3_4_full_size(oracle_mod, ivm):
+    """Counts of orders 1-4 at full size: 2000 facets x 200 snapshots (the urban
+    grid's size, a dense symmetric table) and 20000 facets x 12 snapshots (the
+    large city's size: an LDS of 80 KB per block), against the oracle's integer
+    products."""
+    import torch
+    import scipy.sparse as sps
+    _log("[orders 3-4 full] F=2000 N=200")
+    rng = np.random.default_rng(2000)
+    F, N = 2000, 200
+    M = rng.random((F, F)) < 0.02
+    M = M | M.T
+    np.fill_diagonal(M, False)
+    tv = rng.random((N, F)) < 0.03
+    rv = rng.random((N, F)) < 0.03
+    los = rng.random(N) < 0.3
+    g = _plate_row_scene(ivm, F)
+    dM, dtv, drv, dlos = _upload(ivm, M, tv, rv, los)
+    counts = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 4)
+    torch.cuda.synchronize()
+    assert (counts.cpu().numpy() == oracle_mod.candidates_matmul(M, tv, rv, los, 4)).all()
+
+    _log("[orders 3-4 full] F=20000 N=12")
+    F, N, deg = 20000, 12, 20
+    rows = np.repeat(np.arange(F), deg)
+    cols = rng.integers(0, F, F * deg)
+    S = sps.coo_matrix((np.ones(F * deg, np.int8), (rows, cols)), shape=(F, F)).tocsr()
+    S = ((S + S.T) > 0).tolil()
+    S.setdiag(0)
+    S = S.tocsr()
+    S.eliminate_zeros()
+    Md = S.toarray().astype(bool)
+    tv = rng.random((N, F)) < 0.01
+    rv = rng.random((N, F)) < 0.01
+    los = rng.random(N) < 0.3
+    g = _plate_row_scene(ivm, F)
+    dM, dtv, drv, dlos = _upload(ivm, Md, tv, rv, los)
+    del Md
+    for K in (3, 4):
+        counts = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, K)
+        torch.cuda.synchronize()
+        assert (counts.cpu().numpy() == oracle_mod.candidates_matmul(S, tv, rv, los, K)).all(), K
+
+
+def test_order_above_4_rejected(ivm):
+    import torch
+    g = _plate_row_scene(ivm, 10)
+    lib = ivm.load_library()
+    z = torch.zeros((10, 1), dtype=torch.int64, device="cuda")
+    los = torch.zeros(1, dtype=torch.uint8, device="cuda")
+    counts = torch.zeros((1, 6), dtype=torch.int64, device="cuda")
+    st = lib.ivm_image_tree_candidates(g.handle, z.data_ptr(), 1, z.data_ptr(), z.data_ptr(), los.data_ptr(), 5,
+                                       counts.data_ptr(), None, None, 0, None)
+    assert st == ivm.IVM_ERR_INVALID_ARGUMENT

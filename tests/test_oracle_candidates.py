@@ -30,6 +30,32 @@ def test_enum_equals_matmul_random(oracle_mod, seed):
                 assert all(M[w[m], w[m + 1]] for m in range(k))
 
 
+@pytest.mark.parametrize("seed", [3, 4])
+def test_enum_equals_matmul_one_sided(oracle_mod, seed):
+    """Walks follow M[f_m][f_m+1] as given: a matrix that is not symmetric (a
+    directed cycle 0 -> 1 -> 2 -> 0 among random rows) gives the same counts by
+    enumeration and by products, dense and sparse; on the bare cycle with every
+    facet visible from both sides there are exactly F walks of every order."""
+    import scipy.sparse as sps
+    rng = np.random.default_rng(seed)
+    F, N, K = 19, 6, 4
+    M = rng.random((F, F)) < 0.2
+    np.fill_diagonal(M, False)
+    assert (M != M.T).any()
+    tv = rng.random((N, F)) < 0.4
+    rv = rng.random((N, F)) < 0.4
+    los = rng.random(N) < 0.5
+    c_enum, _ = oracle_mod.candidates_enum(M, tv, rv, los, K)
+    assert (c_enum == oracle_mod.candidates_matmul(M, tv, rv, los, K)).all()
+    assert (c_enum == oracle_mod.candidates_matmul(sps.csr_matrix(M), tv, rv, los, K)).all()
+    C = np.zeros((3, 3), bool)
+    C[0, 1] = C[1, 2] = C[2, 0] = True
+    one = np.ones((1, 3), bool)
+    counts, lists = oracle_mod.candidates_enum(C, one, one, np.zeros(1, bool), K)
+    assert counts[0].tolist() == [0, 3, 3, 3, 3]
+    assert lists[0][2] == [(0, 1, 2), (1, 2, 0), (2, 0, 1)]
+
+
 def _parallel_plates():
     # two large plates facing each other across x in [0, 10]; Tx and Rx between them
     return sg.gen_plates([
