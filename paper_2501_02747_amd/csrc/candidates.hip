@@ -62,6 +62,7 @@ __global__ __launch_bounds__(256) void k_cand_count(int F, int W, const uint64_t
 }
 
 constexpr int kHighThreads = 512;
+constexpr int kLanesPerRow = 8, kRowsPerWave = 64 / kLanesPerRow;
 
 // LDS of k_cand_high for F facets: u as 16-bit halves of uint32 words (LDS
 // atomics are 32-bit; a count never exceeds F < 2^16, so halves never carry),
@@ -91,30 +92,35 @@ __global__ __launch_bounds__(kHighThreads) void k_cand_high(int F, int W, const 
     unsigned *u = (unsigned *)lds;
     unsigned short *v = (unsigned short *)(lds + 4 * (size_t)Fh);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = kHighThreads / 64;
+    const int grp = lane / kLanesPerRow, sub = lane % kLanesPerRow;
     for (int n = blockIdx.x; n < N; n += gridDim.x) {
         const uint64_t *t = txv + (size_t)n * W, *r = rxv + (size_t)n * W;
         for (int i = tid; i < Fh; i += kHighThreads) u[i] = 0u;
         __syncthreads();
-        // one pass over the rows: v[g], and the rows of Tx-visible facets pushed into u
-        for (int g = wv; g < F; g += nw) {
-            const uint64_t *row = M + (size_t)g * W;
-            const bool in_t = (t[g >> 6] >> (g & 63)) & 1ull;
+        // one pass over the rows: v[g], and the rows of Tx-visible facets pushed into
+        // u.  Eight lanes share a row, so a wave keeps eight rows' loads in flight.
+        for (int g0 = wv * kRowsPerWave; g0 < F; g0 += nw * kRowsPerWave) {
+            const int g = g0 + grp;
             unsigned c = 0;
-            for (int w = lane; w < W; w += 64) {
-                const uint64_t m = row[w];
-                c += (unsigned)__popcll(m & r[w]);
-                if (in_t) {
-                    uint64_t b = m;
-                    while (b) {
-                        const int h = w * 64 + __ffsll((long long)b) - 1;
-                        b &= b - 1;
-                        if (h >= F) break;
-                        atomicAdd(&u[h >> 1], 1u << (16 * (h & 1)));
+            if (g < F) {
+                const uint64_t *row = M + (size_t)g * W;
+                const bool in_t = (t[g >> 6] >> (g & 63)) & 1ull;
+                for (int w = sub; w < W; w += kLanesPerRow) {
+                    const uint64_t m = row[w];
+                    c += (unsigned)__popcll(m & r[w]);
+                    if (in_t) {
+                        uint64_t b = m;
+                        while (b) {
+                            const int h = w * 64 + __ffsll((long long)b) - 1;
+                            b &= b - 1;
+                            if (h >= F) break;
+                            atomicAdd(&u[h >> 1], 1u << (16 * (h & 1)));
+                        }
                     }
                 }
             }
-            c = (unsigned)wsum(c);
-            if (lane == 0) v[g] = (unsigned short)c;
+            for (int o = kLanesPerRow / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
+            if (g < F && sub == 0) v[g] = (unsigned short)c;
         }
         __syncthreads();
         unsigned long long c1 = 0, c2 = 0, c3 = 0, c4 = 0;
@@ -127,12 +133,14 @@ __global__ __launch_bounds__(kHighThreads) void k_cand_high(int F, int W, const 
             if ((t[g >> 6] >> (g & 63)) & 1ull) c2 += vg;
         }
         if (K >= 4)
-            for (int g = wv; g < F; g += nw) {
-                const unsigned ug = (u[g >> 1] >> (16 * (g & 1))) & 0xffffu;  // (wave-uniform)
+            for (int g0 = wv * kRowsPerWave; g0 < F; g0 += nw * kRowsPerWave) {
+                const int g = g0 + grp;
+                if (g >= F) continue;
+                const unsigned ug = (u[g >> 1] >> (16 * (g & 1))) & 0xffffu;
                 if (ug == 0u) continue;
                 const uint64_t *row = M + (size_t)g * W;
                 unsigned long long sv = 0;
-                for (int w = lane; w < W; w += 64) {
+                for (int w = sub; w < W; w += kLanesPerRow) {
                     uint64_t b = row[w];
                     while (b) {
                         const int h = w * 64 + __ffsll((long long)b) - 1;
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(kHighThreads) void k_cand_high(int F, int W, const 
                         sv += v[h];
                     }
                 }
-                c4 += (unsigned long long)ug * sv;  // (each lane its share; summed below)
+                c4 += (unsigned long long)ug * sv;  // (each lane its words' share; summed below)
             }
         c1 = block_sum_u64(c1, red);
         c2 = block_sum_u64(c2, red);
