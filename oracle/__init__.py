@@ -22,6 +22,9 @@ no code.  Each function says which passage of the paper it follows.
   (Section III-C; Section III-D, eqs. 8 and 9), in sequential FP64 steps.
 * ``interface_relations``: the interface relation of each visible facet pair
   (parallel or perpendicular planes, Section II-B, Table I) in exact integers.
+* ``edge_visibility`` / ``diffraction_counts``: building edges seen from Tx/Rx
+  positions and the first-order diffraction candidates Tx -> edge -> Rx
+  (Section III-B), with the same exact predicates as the face tables.
 """
 from __future__ import annotations
 
@@ -675,3 +678,36 @@ def interface_relations(scene, M: np.ndarray) -> Dict[str, np.ndarray]:
     cls = np.array([0 if n[2] == 0 else (1 if n[0] == 0 and n[1] == 0 else 2) for n in nrm], np.int8)
     return {"par": par, "per": per, "cls": cls}
 
+
+# ---------------------------------------------------------------------------
+# Edge visibility for first-order diffraction (Section III-B: the receiver's
+# diffracting edge is found the way a reflecting face is; edges are visibility
+# nodes next to faces, Section I and Section II-A)
+# ---------------------------------------------------------------------------
+
+def edge_visibility(orc: "Oracle", X: np.ndarray, edge_facets: np.ndarray, edge_samples: np.ndarray,
+                    s: int) -> np.ndarray:
+    """bool [N][E]: edge e, where facets fa and fb meet, is visible from the
+    point x iff x lies strictly on the visible side of fa or of fb (an edge is
+    seen where one of its faces is) and the segment from x to one of the edge's
+    s sample points meets no triangle of a facet other than fa and fb."""
+    X = np.asarray(X, np.float64).reshape(-1, 3)
+    E = int(edge_facets.shape[0])
+    out = np.zeros((X.shape[0], E), bool)
+    for n in range(X.shape[0]):
+        for e in range(E):
+            fa, fb = int(edge_facets[e, 0]), int(edge_facets[e, 1])
+            front = orc.orient(fa, X[n]) > 0 or (fb >= 0 and orc.orient(fb, X[n]) > 0)
+            if not front:
+                continue
+            for j in range(s):
+                if orc.segment_clear(X[n], edge_samples[e * s + j], fa, fb):
+                    out[n, e] = True
+                    break
+    return out
+
+
+def diffraction_counts(tx_edges: np.ndarray, rx_edges: np.ndarray) -> np.ndarray:
+    """First-order diffraction candidates Tx -> edge -> Rx per snapshot: the
+    edges visible from both ends."""
+    return (np.asarray(tx_edges, bool) & np.asarray(rx_edges, bool)).sum(1).astype(np.int64)

@@ -78,6 +78,10 @@ class Scene:
     samples        f32[S][3]   metres, multiples of 2^-(g+k)
     tx, rx         f32[N][3]   Tx / Rx positions per snapshot (sample grid)
     snapshot_dt    seconds between consecutive snapshots of a trajectory
+    edge_facets    i32[E][2]   the two facets meeting at each building edge (a
+                               vertical corner or a roof rim segment)
+    edge_samples   f32[E*s][3] s points per edge at (j + 1/2) / s of its length
+                               (sample grid; s = samples_per_edge)
     """
     name: str
     seed: int
@@ -93,6 +97,9 @@ class Scene:
     tx: np.ndarray
     rx: np.ndarray
     snapshot_dt: float = 0.01
+    edge_facets: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 2), np.int32))
+    edge_samples: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.float32))
+    samples_per_edge: int = 0
 
     @property
     def n_facets(self) -> int:
@@ -138,6 +145,11 @@ class SceneBuilder:
         self.offsets: List[int] = [0]
         self.kind: List[int] = []
         self.building: List[int] = []
+        # building edges: (a, b) in vertex units and the two facets meeting there
+        self.edges: List[Tuple[Tuple[int, int, int], Tuple[int, int, int], int, int]] = []
+
+    def add_edge(self, a, b, fa: int, fb: int) -> None:
+        self.edges.append((tuple(int(c) for c in a), tuple(int(c) for c in b), int(fa), int(fb)))
 
     @property
     def n_facets(self) -> int:
@@ -239,9 +251,28 @@ class SceneBuilder:
         parts.append(((x0, y0, 0), (0, 0, h), (0, d, 0), KIND_WALL))  # west, -x
         parts.append(((x1, y0, 0), (0, d, 0), (0, 0, h), KIND_WALL))  # east, +x
         parts.append(((x0, y0, h), (w, 0, 0), (0, d, 0), KIND_ROOF))  # roof, +z
+        pid = {}
         for m, (v0, U, V, kind) in enumerate(parts):
             if m not in omit:
-                ids.append(self.add_rect(v0, U, V, n, kind, building))
+                pid[m] = self.add_rect(v0, U, V, n, kind, building)
+                ids.append(pid[m])
+        # edges where two present facets meet: four vertical corners, the roof rim
+        south, north = list(range(split_x)), list(range(split_x, 2 * split_x))
+        west, east, roof = 2 * split_x, 2 * split_x + 1, 2 * split_x + 2
+
+        def edge(a, b, m1, m2):
+            if m1 in pid and m2 in pid:
+                self.add_edge(a, b, pid[m1], pid[m2])
+
+        edge((x0, y0, 0), (x0, y0, h), south[0], west)
+        edge((x1, y0, 0), (x1, y0, h), south[-1], east)
+        edge((x0, y1, 0), (x0, y1, h), north[0], west)
+        edge((x1, y1, 0), (x1, y1, h), north[-1], east)
+        for s in range(split_x):
+            edge((x0 + s * pw, y0, h), (x0 + (s + 1) * pw, y0, h), south[s], roof)
+            edge((x0 + s * pw, y1, h), (x0 + (s + 1) * pw, y1, h), north[s], roof)
+        edge((x0, y0, h), (x0, y1, h), west, roof)
+        edge((x1, y0, h), (x1, y1, h), east, roof)
         return ids
 
     def build(self, name: str, seed: int, tx_s=None, rx_s=None) -> Scene:
@@ -253,6 +284,14 @@ class SceneBuilder:
         lim = 1 << 24
         if np.abs(verts).max(initial=0) >= lim or np.abs(smp).max(initial=0) >= lim:
             raise ValueError("coordinate does not fit FP32 exactly")
+        # edge samples at (2j + 1) / (2 s) of each edge, s = 2^(k-1) (the facet sample
+        # spacing along a side): integers in sample units
+        s_e = self.vs // 2
+        esmp = [tuple(a[i] * self.vs + (b[i] - a[i]) * (2 * j + 1) for i in range(3))
+                for (a, b, _, _) in self.edges for j in range(s_e)]
+        esmp = np.asarray(esmp, dtype=np.int64).reshape(-1, 3)
+        if np.abs(esmp).max(initial=0) >= lim:
+            raise ValueError("edge sample does not fit FP32 exactly")
         tx_s = np.zeros((0, 3), np.int64) if tx_s is None else np.asarray(tx_s, np.int64).reshape(-1, 3)
         rx_s = np.zeros((0, 3), np.int64) if rx_s is None else np.asarray(rx_s, np.int64).reshape(-1, 3)
         return Scene(
@@ -266,6 +305,9 @@ class SceneBuilder:
             facet_building=np.asarray(self.building, dtype=np.int32),
             tx=(tx_s.astype(np.float64) * sscale).astype(np.float32),
             rx=(rx_s.astype(np.float64) * sscale).astype(np.float32),
+            edge_facets=np.asarray([(fa, fb) for (_, _, fa, fb) in self.edges], dtype=np.int32).reshape(-1, 2),
+            edge_samples=(esmp.astype(np.float64) * sscale).astype(np.float32),
+            samples_per_edge=s_e if self.edges else 0,
         )
 
 
@@ -477,6 +519,7 @@ def gen_c3(seed: int = 3, n_snap: int = 10000, cells: int = 50, n_buildings: int
         rad = rng.randint(10 * su, 30 * su)
         poly = _convex_polygon(rng, ccx, ccy, kk, rad, snap)
         h = rng.randint(10 * su, 60 * su)
+        walls, rim = [], []
         for m in range(len(poly)):
             ax, ay = poly[m]
             bx, by = poly[(m + 1) % len(poly)]
@@ -487,9 +530,18 @@ def gen_c3(seed: int = 3, n_snap: int = 10000, cells: int = 50, n_buildings: int
             while L / npan > max_panel and gcd % (npan * 2) == 0:
                 npan *= 2
             px, py = dx // npan, dy // npan
+            panels = []
             for s in range(npan):
-                b.add_rect((ax + s * px, ay + s * py, 0), (px, py, 0), (0, 0, h), n, KIND_WALL, bid)
-        b.add_roof_polygon(poly, h, n, bid)
+                panels.append(b.add_rect((ax + s * px, ay + s * py, 0), (px, py, 0), (0, 0, h), n, KIND_WALL, bid))
+                rim.append(((ax + s * px, ay + s * py, h), (ax + (s + 1) * px, ay + (s + 1) * py, h), panels[-1]))
+            walls.append(panels)
+        roof = b.add_roof_polygon(poly, h, n, bid)
+        # building edges: the vertical corner at each polygon vertex, the roof rim over every panel
+        for m in range(len(poly)):
+            ax, ay = poly[m]
+            b.add_edge((ax, ay, 0), (ax, ay, h), walls[m - 1][-1], walls[m][0])
+        for a, bb, f in rim:
+            b.add_edge(a, bb, f, roof)
     tx = _corridor_drive(rng, cells, half, ss, n_snap)
     rx = _corridor_drive(rng, cells, half, ss, n_snap)
     return b.build("c3", seed, tx, rx)
