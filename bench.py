@@ -490,6 +490,41 @@ def main():
             out["candidates_order4"]["oracle_sample"] = f"every 10th snapshot ({len(pick)})"
             out["candidates_order4"]["matches_oracle"] = bool((c4np[pick] == co4).all())
     progress(f"candidates up to order 4: {statistics.median(times):.3f} ms")
+    # building edges seen from Tx and Rx and the first-order diffraction candidates
+    # Tx -> edge -> Rx (Section III-B), over the first 1000 snapshots at most
+    E = int(scene.edge_facets.shape[0])
+    if E:
+        ne = min(N, 1000)
+        ef = torch.as_tensor(scene.edge_facets).cuda()
+        es = torch.as_tensor(scene.edge_samples).cuda()
+        times = []
+        for k in range(args.warmup + args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            te, re_, dc = ivm.ivm_edge_visibility(g, ef, es, scene.samples_per_edge, tx[:ne], rx[:ne])
+            e1.record()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(e0.elapsed_time(e1))
+        gte, gre = ivm.unpack_bits(te, E), ivm.unpack_bits(re_, E)
+        out["edges"] = {"gpu_ms": statistics.median(times), "snapshots": ne, "edges": E,
+                        "samples_per_edge": int(scene.samples_per_edge),
+                        "tx_edges_mean": float(gte.sum(1).mean()), "rx_edges_mean": float(gre.sum(1).mean()),
+                        "diffraction_candidates": int(dc.sum().item())}
+        if not args.no_verify:
+            import oracle
+            orc_e = oracle.Oracle(scene)
+            pick = np.array(sorted({0, ne // 2, ne - 1}))
+            t0 = time.perf_counter()
+            ot = oracle.edge_visibility(orc_e, scene.tx[pick], scene.edge_facets, scene.edge_samples,
+                                        scene.samples_per_edge)
+            orr = oracle.edge_visibility(orc_e, scene.rx[pick], scene.edge_facets, scene.edge_samples,
+                                         scene.samples_per_edge)
+            out["edges"]["oracle_ms_per_point"] = 1e3 * (time.perf_counter() - t0) / (2 * len(pick))
+            out["edges"]["oracle_sample"] = f"snapshots {pick.tolist()}, both ends"
+            out["edges"]["matches_oracle"] = bool((gte[pick] == ot).all() and (gre[pick] == orr).all() and (
+                dc.cpu().numpy()[pick] == oracle.diffraction_counts(ot, orr)).all())
+        progress(f"edge visibility: {statistics.median(times):.3f} ms for {ne} snapshots")
     if not args.no_verify:
         progress("verifying against the oracle")
         counts_now = counts

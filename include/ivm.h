@@ -261,6 +261,25 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
 ivm_status ivm_interface_relations(const ivm_scene *scene, const uint64_t *d_M, uint64_t *d_par, uint64_t *d_per,
                                    int8_t *d_facet_class, hipStream_t stream);
 
+/* Edge visibility for first-order diffraction (Section III-B: the receiver's
+ * diffracting edge is found the way a reflecting face is; edges are visibility
+ * nodes next to faces).  Edge e is where facets d_edge_facets[e] = (fa, fb) meet
+ * (int32[E][2]; fb = -1 for an edge of one facet); it has samples_per_edge
+ * (1..64) sample points d_edge_samples[e * s + j] (float[E * s][3], on the
+ * sample grid inside the scene's box).  Bit e of d_tx_edges[n] (uint64[N][We],
+ * We = ceil(E / 64), padding zero) is set iff d_tx[n] lies strictly on the
+ * visible side of fa or of fb and the segment from d_tx[n] to one of the edge's
+ * samples meets no triangle of a facet other than fa and fb; the same for
+ * d_rx_edges.  d_diffraction (int64[N], may be NULL) receives the number of
+ * edges seen from both ends, the first-order diffraction candidates
+ * Tx -> edge -> Rx.  Off-grid positions or samples and bad facet ids are
+ * reported by ivm_scene_status.  opts may be NULL.  Errors:
+ * IVM_ERR_INVALID_ARGUMENT, IVM_ERR_HIP. */
+ivm_status ivm_edge_visibility(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_edges,
+                               int32_t samples_per_edge, const int32_t *d_edge_facets, const float *d_edge_samples,
+                               int32_t n_snap, const float *d_tx, const float *d_rx, uint64_t *d_tx_edges,
+                               uint64_t *d_rx_edges, int64_t *d_diffraction, hipStream_t stream);
+
 /* Ray creation and suppression points along one trajectory, the visibility
  * ranges between them and their coherence times (Section III-C: the visibility
  * change nodes of the inter-visibility table of a mobile transmitter or

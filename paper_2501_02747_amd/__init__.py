@@ -37,7 +37,7 @@ EXPORTED = [
     "ivm_status_string", "ivm_scene_workspace_size", "ivm_build_scene", "ivm_scene_status",
     "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
     "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups", "ivm_visibility_ranges",
-    "ivm_visibility_ranges_workspace_size", "ivm_interface_relations",
+    "ivm_visibility_ranges_workspace_size", "ivm_interface_relations", "ivm_edge_visibility",
     "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
@@ -129,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_visibility_ranges.argtypes = [P, i32, P, P, P, P, P, ctypes.c_double, P, sz, P, P, P, P, P, P, P]
     lib.ivm_interface_relations.restype = i32
     lib.ivm_interface_relations.argtypes = [P, P, P, P, P, P]
+    lib.ivm_edge_visibility.restype = i32
+    lib.ivm_edge_visibility.argtypes = [P, ctypes.POINTER(ivm_matrix_opts), i32, i32, P, P, i32, P, P, P, P, P, P]
     lib.ivm_visibility_ranges_workspace_size.restype = i32
     lib.ivm_visibility_ranges_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
     lib.ivm_triangle_groups.restype = i32
@@ -410,6 +412,24 @@ def ivm_image_tree_candidates(scene: GpuScene, M, tx_vis, rx_vis, los, max_order
                                            _stream(stream))
     _check(st, "ivm_image_tree_candidates")
     return counts, offsets, paths
+
+
+def ivm_edge_visibility(scene: GpuScene, edge_facets, edge_samples, samples_per_edge: int, tx, rx,
+                        opts: Optional[ivm_matrix_opts] = None, stream=None):
+    """edge_facets int32 [E, 2], edge_samples float32 [E * s, 3], tx / rx float32
+    [N, 3] (device tensors).  Returns (tx_edges, rx_edges) int64 [N, ceil(E/64)]
+    bit rows and the diffraction candidate counts int64 [N]."""
+    import torch
+    N, E = int(tx.shape[0]), int(edge_facets.shape[0])
+    We = (E + 63) // 64
+    te = torch.empty((N, max(We, 1)), dtype=torch.int64, device=scene.device)
+    re_ = torch.empty((N, max(We, 1)), dtype=torch.int64, device=scene.device)
+    cnt = torch.empty((max(N, 1),), dtype=torch.int64, device=scene.device)
+    _check(load_library().ivm_edge_visibility(
+        scene.handle, ctypes.byref(opts) if opts is not None else None, E, samples_per_edge, _ptr(edge_facets),
+        _ptr(edge_samples), N, _ptr(tx), _ptr(rx), _ptr(te), _ptr(re_), _ptr(cnt), _stream(stream)),
+        "ivm_edge_visibility")
+    return te[:, :We], re_[:, :We], cnt[:N]
 
 
 def ivm_interface_relations(scene: GpuScene, M, stream=None):

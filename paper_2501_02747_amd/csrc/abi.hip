@@ -264,6 +264,26 @@ ivm_status ivm_interface_relations(const ivm_scene *scene, const uint64_t *d_M, 
     return IVM_OK;
 }
 
+ivm_status ivm_edge_visibility(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_edges,
+                               int32_t samples_per_edge, const int32_t *d_edge_facets, const float *d_edge_samples,
+                               int32_t n_snap, const float *d_tx, const float *d_rx, uint64_t *d_tx_edges,
+                               uint64_t *d_rx_edges, int64_t *d_diffraction, hipStream_t stream) {
+    if (!scene || n_edges < 0 || n_snap < 0 || samples_per_edge < 1 || samples_per_edge > 64)
+        return IVM_ERR_INVALID_ARGUMENT;
+    if ((long long)n_edges * samples_per_edge > 0x7fffffffLL) return IVM_ERR_INVALID_ARGUMENT;
+    if (opts && (opts->order_mode < IVM_ORDER_PLAIN || opts->order_mode > IVM_ORDER_REVERSED))
+        return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap > 0 && (!d_tx || !d_rx)) return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap > 0 && n_edges > 0 && (!d_edge_facets || !d_edge_samples || !d_tx_edges || !d_rx_edges))
+        return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap == 0) return IVM_OK;
+    const TraverseOpts o = make_opts(opts);
+    if (launch_edges(scene->s, o, n_snap, n_edges, samples_per_edge, d_edge_facets, d_edge_samples, d_tx, d_rx,
+                     d_tx_edges, d_rx_edges, d_diffraction, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
 ivm_status ivm_visibility_ranges_workspace_size(int32_t n_snap, size_t *bytes) {
     if (!bytes || n_snap < 1) return IVM_ERR_INVALID_ARGUMENT;
     *bytes = ranges_workspace_bytes(n_snap);

@@ -240,6 +240,11 @@ hipError_t launch_points_prep(Scene &sc, int N, const float *tx, const float *rx
                               hipStream_t s);
 hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_items, const TraverseOpts &o,
                              ivm_stats *stats, hipStream_t s);
+// Edge visibility from Tx/Rx positions (first-order diffraction) and the
+// per-snapshot counts of edges seen from both ends (counts may be null).
+hipError_t launch_edges(Scene &scn, const TraverseOpts &o, int N, int E, int s, const int *efac, const float *esmp,
+                        const float *tx, const float *rx, uint64_t *txe, uint64_t *rxe, int64_t *counts,
+                        hipStream_t st);
 hipError_t launch_los(Scene &sc, const TraverseOpts &o, int N, const float *tx, const float *rx, uint8_t *los,
                       hipStream_t s);
 PairJob make_pair_job(Scene &sc, uint64_t *M, bool learned);

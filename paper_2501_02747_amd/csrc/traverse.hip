@@ -2440,6 +2440,112 @@ hipError_t launch_los(Scene &scn, const TraverseOpts &o, int N, const float *tx,
     return hipGetLastError();
 }
 
+// Edge visibility for first-order diffraction (Section III-B: the receiver's
+// diffracting edge is found the way a reflecting face is).  Edge e, where facets
+// fa and fb meet, is seen from X when X lies strictly on the visible side of fa
+// or of fb and the segment from X to one of the edge's s sample points meets no
+// triangle outside fa and fb.  One lane per (snapshot, side, edge, sample): G
+// consecutive lanes (G = s rounded up to a power of two) hold the samples of one
+// edge, so a wave covers 64 / G edges of one point; a ballot over the group sets
+// the edge's bit.
+__global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int s, int G, int We, const int *efac,
+                                                  const float *esmp, const float *tx, const float *rx,
+                                                  uint64_t *txe, uint64_t *rxe, TraverseOpts o) {
+    __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int per_wave = kWave / G;
+    const long long nb = (E + per_wave - 1) / per_wave;
+    const long long q = (long long)blockIdx.x * kWavesPerBlock + wv;
+    if (q >= 2LL * N * nb) return;  // (wave-uniform)
+    const int n = (int)(q / (2 * nb)), side = (int)((q / nb) & 1);
+    const int e = (int)(q % nb) * per_wave + lane / G, j = lane % G;
+    const float *X = (side ? rx : tx) + 3 * (size_t)n;
+    bool clear = false;
+    if (e < E && j < s) {
+        const int fa = efac[2 * e], fb = efac[2 * e + 1];
+        if (fa >= 0 && fa < sc.F && fb >= -1 && fb < sc.F && fb != fa) {
+            const bool front = orient(sc.fplane + 6 * (size_t)fa, X[0], X[1], X[2]) > 0.0 ||
+                               (fb >= 0 && orient(sc.fplane + 6 * (size_t)fb, X[0], X[1], X[2]) > 0.0);
+            if (front) {
+                const float *p = esmp + 3 * ((size_t)e * s + j);
+                const Seg sg = make_seg(X[0], X[1], X[2], p[0], p[1], p[2]);
+                Cnt c;
+                clear = any_hit(sc, sg, fa, fb, kIdentOrder, kTreelets, &sStack[wv][lane], o.stack_depth, o.eps6,
+                                o.fp64_only != 0, c) < 0;
+            }
+        }
+    }
+    const unsigned long long bal = __ballot(clear);
+    if (j == 0 && e < E) {
+        const unsigned long long gm = (G == kWave ? ~0ull : ((1ull << G) - 1ull)) << lane;
+        if (bal & gm) atomicOr((unsigned long long *)((side ? rxe : txe) + (size_t)n * We + (e >> 6)), 1ull << (e & 63));
+    }
+}
+
+// Edge inputs: facet ids in range and distinct, every sample on the sample grid
+// and inside the scene's box (so the exactness budget of the scene covers it).
+__global__ void k_check_edges(SceneDev sc, int E, int s, const int *efac, const float *esmp) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= E * s) return;
+    const int e = id / s;
+    int bad = 0;
+    if (id % s == 0) {
+        const int fa = efac[2 * e], fb = efac[2 * e + 1];
+        if (!(fa >= 0 && fa < sc.F && fb >= -1 && fb < sc.F && fb != fa)) bad |= kStInvalid;
+    }
+    const double sscale = ldexp(1.0, sc.gs);
+    for (int k = 0; k < 3; ++k) {
+        const double y = (double)esmp[3 * (size_t)id + k] * sscale;
+        if (!(fabs(y) < 16777216.0) || y != floor(y) || y < sc.extent[k] || y > sc.extent[3 + k]) bad |= kStGrid;
+    }
+    if (bad) atomicOr(sc.status, bad);
+}
+
+// First-order diffraction candidates per snapshot: popcount(tx edges & rx edges).
+__global__ __launch_bounds__(256) void k_edge_counts(int N, int We, const uint64_t *txe, const uint64_t *rxe,
+                                                     int64_t *counts) {
+    const int lane = threadIdx.x & 63;
+    const int n = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (n >= N) return;  // (wave-uniform)
+    unsigned long long c = 0;
+    for (int w = lane; w < We; w += 64) c += __popcll(txe[(size_t)n * We + w] & rxe[(size_t)n * We + w]);
+    c = wave_sum_u64(c);
+    if (lane == 0) counts[n] = (int64_t)c;
+}
+
+hipError_t launch_edges(Scene &scn, const TraverseOpts &o, int N, int E, int s, const int *efac, const float *esmp,
+                        const float *tx, const float *rx, uint64_t *txe, uint64_t *rxe, int64_t *counts,
+                        hipStream_t st) {
+    const SceneDev &sc = scn.dev;
+    const int We = (E + 63) / 64;
+    hipError_t e;
+    if (N > 0 && We > 0) {
+        if ((e = launch_fill_u64(txe, 0ull, (size_t)N * We, st)) != hipSuccess) return e;
+        if ((e = launch_fill_u64(rxe, 0ull, (size_t)N * We, st)) != hipSuccess) return e;
+    }
+    if (N > 0 && E > 0) {
+        hipLaunchKernelGGL(k_check_points, dim3((2 * N + 255) / 256), dim3(256), 0, st, sc, N, tx, rx);
+        const long long items = (long long)E * s;
+        hipLaunchKernelGGL(k_check_edges, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, sc, E, s, efac,
+                           esmp);
+        int G = 1;
+        while (G < s) G <<= 1;
+        const long long per_wave = kWave / G;
+        const long long waves = 2LL * N * ((E + per_wave - 1) / per_wave);
+        hipLaunchKernelGGL(k_edges, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)), dim3(kBlock), 0,
+                           st, sc, N, E, s, G, We, efac, esmp, tx, rx, txe, rxe, o);
+    }
+    if (counts && N > 0) {
+        if (We > 0) {
+            hipLaunchKernelGGL(k_edge_counts, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, N, We, txe, rxe,
+                               counts);
+        } else if ((e = launch_fill_u64((uint64_t *)counts, 0ull, (size_t)N, st)) != hipSuccess) {
+            return e;
+        }
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_items, const TraverseOpts &o,
                              ivm_stats *stats, hipStream_t s) {
     if (total_items <= 0) return hipSuccess;
