@@ -9,7 +9,11 @@
  * ivm_intervisibility_matrix; the inter-visibility table for specific points
  * along a trajectory (Section III-B, Table II; Section III-C) becomes
  * ivm_txrx_visibility_table; the image tree that table prunes (Section II,
- * Section III-B) becomes ivm_image_tree_candidates.
+ * Section III-B), to the orders of Section IV-C, becomes
+ * ivm_image_tree_candidates.  Around them: the interface relations of the
+ * visible pairs (Section II-B, Table I), the visibility ranges and coherence
+ * times along a trajectory (Section III-C/D, eqs. 8-9) and the edges seen from
+ * Tx and Rx for first-order diffraction (Section III-B).
  *
  * Visibility is decided exactly in 3-D over deterministic per-facet sample
  * points:
@@ -24,6 +28,9 @@
  *     blocks).
  *   A point X sees facet f iff orient(f, X) > 0 and some sample p of f has
  *     (X, p) clear of every triangle outside f (Section III-B).
+ *   A point X sees the edge where facets fa and fb meet iff orient(fa, X) > 0
+ *     or orient(fb, X) > 0 and some sample p of the edge has (X, p) clear of
+ *     every triangle outside fa and fb.
  *
  * Conventions
  *   - Every call returns an ivm_status; 0 is success, negative values errors.
