@@ -240,8 +240,8 @@ ivm_status ivm_txrx_visibility_table(ivm_scene *scene, const ivm_matrix_opts *op
  * Table II: transmitter -> reference face -> aim face; orders 3 and 4 are the
  * iteration of Section II-C to the orders timed in Section IV-C).  d_M need not
  * be symmetric.  d_counts is int64[N][max_order + 1] with column 0 = line of
- * sight; counts are exact (orders 3 and 4 need F <= 40960 and an LDS of about
- * 4 F bytes per block, else IVM_ERR_INVALID_ARGUMENT).  If d_paths is NULL
+ * sight; counts are exact (orders 3 and 4 need 1 <= F <= 40960 and an LDS of
+ * about 4 F bytes per block, else IVM_ERR_INVALID_ARGUMENT).  If d_paths is NULL
  * only counts are produced (asynchronous).  Otherwise d_offsets (int64[N *
  * max_order + 1]) receives CSR offsets of the lists (snapshot-major, order-minor)
  * and d_paths the k-tuples as int32 in lexicographic order; this mode
