@@ -72,6 +72,15 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.ivm_image_tree_candidates(None, None, 0, None, None, None, 2, None, None, None, 0, None) \
         == ivm.IVM_ERR_INVALID_ARGUMENT
     assert lib.ivm_destroy_scene(None) == ivm.IVM_ERR_INVALID_ARGUMENT
+    for k in (0, 5):   # orders beyond 1..4
+        assert lib.ivm_image_tree_candidates(None, None, 0, None, None, None, k, None, None, None, 0, None) \
+            == ivm.IVM_ERR_INVALID_ARGUMENT
+    assert lib.ivm_edge_visibility(None, None, 0, 4, None, None, 0, None, None, None, None, None, None) \
+        == ivm.IVM_ERR_INVALID_ARGUMENT
+    assert lib.ivm_interface_relations(None, None, None, None, None, None) == ivm.IVM_ERR_INVALID_ARGUMENT
+    sz = ctypes.c_size_t(0)
+    assert lib.ivm_visibility_ranges_workspace_size(0, ctypes.byref(sz)) == ivm.IVM_ERR_INVALID_ARGUMENT
+    assert lib.ivm_visibility_ranges_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 1000 * 52
     out = ctypes.c_void_p()
     assert lib.ivm_build_scene(None, None, 0, None, ctypes.byref(out)) == ivm.IVM_ERR_INVALID_ARGUMENT
 
