@@ -261,7 +261,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}): the inter-visibility "
-              "path runs on a single MI355X; see DESIGN.md for how it would shard.", file=sys.stderr)
+              "path runs on a single MI355X; a run over several GPUs is not supported.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2501_02747_amd as ivm
