@@ -111,3 +111,34 @@ def test_config_grids_within_budget(cfg):
         v = arr.astype(np.float64) * scale
         assert np.all(v == np.rint(v))
         assert np.all(np.abs(v) < 2 ** 24)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_exact_audit_edge_segments(oracle_mod, cfg):
+    """The edge tables test segments from Tx/Rx positions to edge sample points,
+    which lie on the boundary of the two facets' triangles.  On the generated
+    scenes the FP64 signs of those segment-triangle predicates equal the exact
+    128-bit signs, for random triangles and for the edge's own triangles (the
+    degenerate case: the segment ends on the triangle's boundary), and so do
+    the orientations of the positions against the edge's facets."""
+    import scenegen as sg
+    s = sg.make_config(cfg)
+    rng = np.random.default_rng(5)
+    n = 20000
+    S = s.samples_per_edge
+    E = s.edge_facets.shape[0]
+    X = np.concatenate([s.tx, s.rx])[rng.integers(0, 2 * s.n_snapshots, n)]
+    e = rng.integers(0, E, n)
+    P = s.edge_samples[e * S + rng.integers(0, S, n)]
+    tri = s.vertices[s.tri_vertices]                     # T x 3 x 3
+    t = rng.integers(0, tri.shape[0], n)
+    # half of the sample uses a triangle of one of the edge's two facets
+    own = np.zeros(n, np.int64)
+    first = np.searchsorted(s.tri_facet, np.arange(s.n_facets))
+    f = s.edge_facets[e, rng.integers(0, 2, n)]
+    own[:] = first[f]
+    t[: n // 2] = own[: n // 2]
+    bad, zeros = oracle_mod.exact_audit(X, P, tri[t, 0], tri[t, 1], tri[t, 2], s.g + s.k)
+    assert bad == 0
+    assert oracle_mod.orient_audit(X, tri[own, 0], tri[own, 1], tri[own, 2], s.g + s.k) == 0
+    assert oracle_mod.orient_audit(P, tri[own, 0], tri[own, 1], tri[own, 2], s.g + s.k) == 0
