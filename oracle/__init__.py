@@ -12,8 +12,9 @@ no code.  Each function says which passage of the paper it follows.
   and by integer vector-matrix products.
 * ``morton_treelets``: the Morton (Z-order) partition of triangles into 32
   contiguous equal-count groups, written from its definition.
-* ``image_paths``: exact image-method specular paths on tiny scenes (the
-  image method of Section II and case study 2, Section IV-B), used to pin that
+* ``image_paths`` / ``image_paths_exact``: image-method specular paths on tiny
+  scenes (the image method of Section II and case study 2, Section IV-B), in
+  FP64 with a tolerance and in exact rational arithmetic, used to pin that
   pruning keeps every valid path.
 * ``mlp_*``: FP64 reference of the occluder-ordering network (forward, BCE,
   backward, Adam) and a finite-difference check.
@@ -384,6 +385,114 @@ def image_paths(scene, orc: Oracle, T, R, K: int) -> List[Tuple[int, ...]]:
             if walk and walk[-1] == f:
                 continue
             rec(walk + [f])
+
+    rec([])
+    return sorted(out, key=lambda w: (len(w), w))
+
+
+def _q3(x):
+    from fractions import Fraction
+    return tuple(Fraction(float(c)) for c in x)          # float32/float64 values are dyadic: exact
+
+
+def _sub(a, b):
+    return (a[0] - b[0], a[1] - b[1], a[2] - b[2])
+
+
+def _dot(a, b):
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]
+
+
+def _cross(a, b):
+    return (a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0])
+
+
+def _segtri_exact(p, q, a, b, c) -> bool:
+    """The division-free Moller-Trumbore test of ivm_oracle.c (open segment,
+    closed triangle, a segment parallel to the plane never hits) in rational
+    arithmetic, for end points off the grid."""
+    d, e1, e2, sv = _sub(q, p), _sub(b, a), _sub(c, a), _sub(p, a)
+    h = _cross(d, e2)
+    det = _dot(e1, h)
+    if det == 0:
+        return False
+    u = _dot(sv, h)
+    g = _cross(sv, e1)
+    v, t = _dot(d, g), _dot(e2, g)
+    if det > 0:
+        return u >= 0 and v >= 0 and u + v <= det and 0 < t < det
+    return u <= 0 and v <= 0 and u + v >= det and det < t < 0
+
+
+def image_paths_exact(scene, T, R, K: int) -> List[Tuple[int, ...]]:
+    """The image method of ``image_paths`` in exact rational arithmetic: mirror
+    T in the planes of f1..fk, trace back from R; each reflection point must lie
+    in its closed facet, with the segment's end strictly in front of the plane
+    and the image strictly behind, and every leg's open segment must miss every
+    triangle outside the facets at its ends.  No tolerance: exact on any input."""
+    V = [_q3(v) for v in scene.vertices]
+    tv = scene.tri_vertices
+    tris = [(V[tv[t, 0]], V[tv[t, 1]], V[tv[t, 2]]) for t in range(tv.shape[0])]
+    tfac = [int(f) for f in scene.tri_facet]
+    F = scene.n_facets
+    by_facet = [[] for _ in range(F)]
+    for t, f in enumerate(tfac):
+        by_facet[f].append(tris[t])
+    plane = []
+    for f in range(F):
+        a, b, c = by_facet[f][0]
+        plane.append((a, _cross(_sub(b, a), _sub(c, a))))
+    T, R = _q3(T), _q3(R)
+
+    def reflect(x, f):
+        a, n = plane[f]
+        k = 2 * _dot(_sub(x, a), n) / _dot(n, n)
+        return (x[0] - k * n[0], x[1] - k * n[1], x[2] - k * n[2])
+
+    def in_facet(x, f):
+        for a, b, c in by_facet[f]:
+            n = _cross(_sub(b, a), _sub(c, a))
+            if (_dot(_cross(_sub(b, a), _sub(x, a)), n) >= 0 and _dot(_cross(_sub(c, b), _sub(x, b)), n) >= 0
+                    and _dot(_cross(_sub(a, c), _sub(x, c)), n) >= 0):
+                return True
+        return False
+
+    def clear(p, q, ex1, ex2):
+        return not any(_segtri_exact(p, q, *tris[t]) for t in range(len(tris)) if tfac[t] not in (ex1, ex2))
+
+    def valid(walk):
+        imgs = [T]
+        for f in walk:
+            imgs.append(reflect(imgs[-1], f))
+        pts = [None] * len(walk)
+        target = R
+        for m in range(len(walk) - 1, -1, -1):
+            f = walk[m]
+            a, n = plane[f]
+            I = imgs[m + 1]
+            da, db = _dot(_sub(target, a), n), _dot(_sub(I, a), n)
+            if not (da > 0 and db < 0):
+                return False
+            s_ = da / (da - db)
+            P = tuple(target[i] + s_ * (I[i] - target[i]) for i in range(3))
+            if not in_facet(P, f):
+                return False
+            pts[m] = P
+            target = P
+        chain = [T] + pts + [R]
+        facs = [-1] + list(walk) + [-1]
+        return all(clear(chain[m], chain[m + 1], facs[m], facs[m + 1]) for m in range(len(chain) - 1))
+
+    out = []
+
+    def rec(walk):
+        if walk and valid(walk):
+            out.append(tuple(walk))
+        if len(walk) == K:
+            return
+        for f in range(F):
+            if not (walk and walk[-1] == f):
+                rec(walk + [f])
 
     rec([])
     return sorted(out, key=lambda w: (len(w), w))

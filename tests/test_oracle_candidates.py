@@ -202,3 +202,48 @@ def test_bce_and_adam_closed_forms(oracle_mod):
     st = {}
     oracle_mod.adam_step(p, g, st, lr=0.01, eps=0.0)
     assert np.allclose(p["W0"], [0.99, -1.99, 2.99], atol=1e-12)
+
+
+def test_exact_image_paths_closed_forms(oracle_mod):
+    """The exact validator on the closed forms: two parallel mirrors give two
+    paths of every order; the 90-degree corner gives 2, 1 and 0 paths of orders
+    1-3 (the second-order one is 0 -> 1); the FP64 validator agrees."""
+    s = _parallel_plates()
+    orc = oracle_mod.Oracle(s)
+    ex = oracle_mod.image_paths_exact(s, s.tx[0], s.rx[0], 4)
+    assert [len([p for p in ex if len(p) == k]) for k in (1, 2, 3, 4)] == [2, 2, 2, 2]
+    assert ex == oracle_mod.image_paths(s, orc, s.tx[0], s.rx[0], 4)
+    s = sg.gen_plates([
+        [[0, 0, -20], [0, 40, 0], [0, 0, 40]],
+        [[0, 0, -20], [0, 0, 40], [40, 0, 0]],
+    ], tx=[[5, 12, 1]], rx=[[14, 4, 0.5]])
+    ex = oracle_mod.image_paths_exact(s, s.tx[0], s.rx[0], 3)
+    assert [len([p for p in ex if len(p) == k]) for k in (1, 2, 3)] == [2, 1, 0]
+    assert (0, 1) in ex
+
+
+def test_exact_image_paths_closed_facet_boundary(oracle_mod):
+    """Tx (5, -3, 1) and Rx (5, 3, 1) in front of the mirror x = 0: the specular
+    point is (0, 0, 1).  A plate with its edge on y = 0 contains it (facets are
+    closed), one that starts a grid step further (y = 1/16) does not."""
+    for y0, expect in ((0.0, [(0,)]), (1.0 / 16, [])):
+        s = sg.gen_plates([[[0, y0, -20], [0, 40, 0], [0, 0, 40]]], tx=[[5, -3, 1]], rx=[[5, 3, 1]])  # faces +x
+        assert oracle_mod.image_paths_exact(s, s.tx[0], s.rx[0], 1) == expect, y0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_exact_paths_recall_c1(oracle_mod, seed):
+    """Case study 2's claim in exact arithmetic (Section IV-B): every exact
+    image-method path of order <= 2 whose first and last facets are sample-visible
+    is among the pruned candidates; the FP64 validator finds the same paths."""
+    s = sg.gen_c1(seed, n_snap=3)
+    orc = oracle_mod.Oracle(s)
+    M, _ = orc.matrix()
+    tv, rv, los = orc.txrx(s.tx, s.rx)
+    _, lists = oracle_mod.candidates_enum(M, tv, rv, los, 2)
+    for n in range(3):
+        ex = oracle_mod.image_paths_exact(s, s.tx[n], s.rx[n], 2)
+        assert ex == oracle_mod.image_paths(s, orc, s.tx[n], s.rx[n], 2)
+        for p in ex:
+            if tv[n, p[0]] and rv[n, p[-1]]:
+                assert p in set(lists[n][len(p) - 1]), (n, p)
