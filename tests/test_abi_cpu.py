@@ -98,3 +98,27 @@ def test_pack_unpack_roundtrip(n):
     one[0, n - 1] = True
     w = ivm.pack_bits(one).view(np.uint64)
     assert w[0, (n - 1) >> 6] == np.uint64(1) << np.uint64((n - 1) & 63)
+
+
+def test_he_uniform_init_layout():
+    """Host side of the training script: the flat parameter vector has the
+    library's size and layout (W0, b0, W1, b1, ...), weights within the He-uniform
+    bound sqrt(6 / fan_in), zero biases, and the same vector for the same seed;
+    the shipped weights have the same size and are finite."""
+    import paper_2501_02747_amd as ivm
+    from paper_2501_02747_amd import train
+    sizes = (24, 128, 128, 128, 32)
+    v = train.he_uniform_init(3)
+    assert v.dtype == np.float32 and v.shape == (ivm.IVM_MLP_PARAMS,)
+    assert (v == train.he_uniform_init(3)).all() and not (v == train.he_uniform_init(4)).all()
+    o = 0
+    for l in range(len(sizes) - 1):
+        n_w = sizes[l] * sizes[l + 1]
+        w, b = v[o:o + n_w], v[o + n_w:o + n_w + sizes[l + 1]]
+        bound = np.sqrt(6.0 / sizes[l])
+        assert np.abs(w).max() <= bound and np.abs(w).max() > 0.9 * bound
+        assert (b == 0).all()
+        o += n_w + sizes[l + 1]
+    assert o == ivm.IVM_MLP_PARAMS
+    shipped = np.load(train.DEFAULT_WEIGHTS, allow_pickle=False)
+    assert shipped.size == ivm.IVM_MLP_PARAMS and np.isfinite(shipped).all()
