@@ -117,6 +117,17 @@ def cpu_baseline(scene, seconds, seed=0):
         orc.pairs(I, J)
         t_pairs += time.perf_counter() - t0
         n_pairs += len(I)
+    # the same oracle on one host thread, on a smaller sample (a tenth of the time)
+    n_one, t_one = 0, 0.0
+    while t_one < 0.1 * seconds:
+        I = rng.integers(0, F, 64)
+        J = rng.integers(0, F, 64)
+        keep = I != J
+        I, J = I[keep], J[keep]
+        t0 = time.perf_counter()
+        orc.pairs(I, J, threads=1)
+        t_one += time.perf_counter() - t0
+        n_one += len(I)
     n_snap, t_snap = 0, 0.0
     idx = rng.permutation(scene.n_snapshots)
     while t_snap < 0.25 * seconds and n_snap < len(idx):
@@ -131,7 +142,20 @@ def cpu_baseline(scene, seconds, seed=0):
             "sample": f"{n_pairs} uniformly drawn facet pairs of the same scene ({t_pairs:.1f} s); "
                       f"Tx/Rx table for {n_snap} snapshots: {1e3 * t_snap / max(n_snap, 1):.1f} ms/snapshot "
                       f"(table only)",
-            "ms_per_snapshot": 1e3 * t_snap / max(n_snap, 1)}
+            "ms_per_snapshot": 1e3 * t_snap / max(n_snap, 1),
+            "value_1core": n_one / t_one, "sample_1core": f"{n_one} facet pairs on one thread ({t_one:.1f} s)"}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (as the kernel reports it), else the machine type."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def verify(ivm, scene, M, tv, rv, los, counts):
@@ -252,7 +276,8 @@ def run_batched(args, ivm, torch, sg):
     if not args.no_cpu_baseline:
         progress("timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(scenes[calib], args.cpu_baseline_seconds)
-        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+        out["cpu_baseline"]["host"] = cpu_model()
+        out["cpu_baseline"]["nproc"] = os.cpu_count()
     print(json.dumps(out), flush=True)
 
 
@@ -532,7 +557,8 @@ def main():
     if not args.no_cpu_baseline:
         progress("timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_baseline_seconds)
-        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+        out["cpu_baseline"]["host"] = cpu_model()
+        out["cpu_baseline"]["nproc"] = os.cpu_count()
     print(json.dumps(out), flush=True)
 
 
