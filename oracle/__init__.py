@@ -26,6 +26,12 @@ no code.  Each function says which passage of the paper it follows.
 * ``edge_visibility`` / ``diffraction_counts``: building edges seen from Tx/Rx
   positions and the first-order diffraction candidates Tx -> edge -> Rx
   (Section III-B), with the same exact predicates as the face tables.
+* ``edge_rows``: the edge rows of the matrix (edge to facet and edge to
+  edge visibility; edges are visibility nodes beside faces, Sections I, II-A).
+* ``angular_ranges``: the angular bouncing range of each visible pair (Section
+  II-A: the scene seen in two 2-D views; Section II-B, eq. 1: the angle at an
+  edge of the reference face between the face itself and a vertex of the aim
+  face; eq. 2: angles of 180 degrees or more recorded as 0).
 """
 from __future__ import annotations
 
@@ -83,6 +89,8 @@ def _load():
         lib.ivo_segment_clear.restype = i32
         lib.ivo_segment_clear.argtypes = [P, P, P, i32, i32]
         lib.ivo_pairs_occluder_groups.argtypes = [P, i32, P, P, P, P, i32]
+        lib.ivo_edge_rows.restype = None
+        lib.ivo_edge_rows.argtypes = [P, i32, P, P, i32, i32, P, P, P, i32]
         lib.ivo_exact_audit.restype = i64
         lib.ivo_exact_audit.argtypes = [i32, P, P, P, P, P, i32, P]
         lib.ivo_orient_audit.restype = i64
@@ -424,78 +432,94 @@ def _segtri_exact(p, q, a, b, c) -> bool:
     return u <= 0 and v <= 0 and u + v >= det and det < t < 0
 
 
-def image_paths_exact(scene, T, R, K: int) -> List[Tuple[int, ...]]:
-    """The image method of ``image_paths`` in exact rational arithmetic: mirror
-    T in the planes of f1..fk, trace back from R; each reflection point must lie
-    in its closed facet, with the segment's end strictly in front of the plane
-    and the image strictly behind, and every leg's open segment must miss every
-    triangle outside the facets at its ends.  No tolerance: exact on any input."""
-    V = [_q3(v) for v in scene.vertices]
-    tv = scene.tri_vertices
-    tris = [(V[tv[t, 0]], V[tv[t, 1]], V[tv[t, 2]]) for t in range(tv.shape[0])]
-    tfac = [int(f) for f in scene.tri_facet]
-    F = scene.n_facets
-    by_facet = [[] for _ in range(F)]
-    for t, f in enumerate(tfac):
-        by_facet[f].append(tris[t])
-    plane = []
-    for f in range(F):
-        a, b, c = by_facet[f][0]
-        plane.append((a, _cross(_sub(b, a), _sub(c, a))))
-    T, R = _q3(T), _q3(R)
+class _ExactImage:
+    """The exact image method on one scene (rational arithmetic, no tolerance):
+    mirror T in the planes of f1..fk, trace back from R; each reflection point
+    must lie in its closed facet, with the segment's end strictly in front of
+    the plane and the image strictly behind, and every leg's open segment must
+    miss every triangle outside the facets at its ends."""
 
-    def reflect(x, f):
-        a, n = plane[f]
+    def __init__(self, scene):
+        V = [_q3(v) for v in scene.vertices]
+        tv = scene.tri_vertices
+        self.tris = [(V[tv[t, 0]], V[tv[t, 1]], V[tv[t, 2]]) for t in range(tv.shape[0])]
+        self.tfac = [int(f) for f in scene.tri_facet]
+        self.F = scene.n_facets
+        self.by_facet = [[] for _ in range(self.F)]
+        for t, f in enumerate(self.tfac):
+            self.by_facet[f].append(self.tris[t])
+        self.plane = []
+        for f in range(self.F):
+            a, b, c = self.by_facet[f][0]
+            self.plane.append((a, _cross(_sub(b, a), _sub(c, a))))
+
+    def reflect(self, x, f):
+        a, n = self.plane[f]
         k = 2 * _dot(_sub(x, a), n) / _dot(n, n)
         return (x[0] - k * n[0], x[1] - k * n[1], x[2] - k * n[2])
 
-    def in_facet(x, f):
-        for a, b, c in by_facet[f]:
+    def in_facet(self, x, f):
+        for a, b, c in self.by_facet[f]:
             n = _cross(_sub(b, a), _sub(c, a))
             if (_dot(_cross(_sub(b, a), _sub(x, a)), n) >= 0 and _dot(_cross(_sub(c, b), _sub(x, b)), n) >= 0
                     and _dot(_cross(_sub(a, c), _sub(x, c)), n) >= 0):
                 return True
         return False
 
-    def clear(p, q, ex1, ex2):
-        return not any(_segtri_exact(p, q, *tris[t]) for t in range(len(tris)) if tfac[t] not in (ex1, ex2))
+    def clear(self, p, q, ex1, ex2):
+        return not any(_segtri_exact(p, q, *self.tris[t]) for t in range(len(self.tris))
+                       if self.tfac[t] not in (ex1, ex2))
 
-    def valid(walk):
+    def valid(self, T, R, walk) -> bool:
         imgs = [T]
         for f in walk:
-            imgs.append(reflect(imgs[-1], f))
+            imgs.append(self.reflect(imgs[-1], f))
         pts = [None] * len(walk)
         target = R
         for m in range(len(walk) - 1, -1, -1):
             f = walk[m]
-            a, n = plane[f]
+            a, n = self.plane[f]
             I = imgs[m + 1]
             da, db = _dot(_sub(target, a), n), _dot(_sub(I, a), n)
             if not (da > 0 and db < 0):
                 return False
             s_ = da / (da - db)
             P = tuple(target[i] + s_ * (I[i] - target[i]) for i in range(3))
-            if not in_facet(P, f):
+            if not self.in_facet(P, f):
                 return False
             pts[m] = P
             target = P
         chain = [T] + pts + [R]
         facs = [-1] + list(walk) + [-1]
-        return all(clear(chain[m], chain[m + 1], facs[m], facs[m + 1]) for m in range(len(chain) - 1))
+        return all(self.clear(chain[m], chain[m + 1], facs[m], facs[m + 1]) for m in range(len(chain) - 1))
 
+
+def image_paths_exact(scene, T, R, K: int) -> List[Tuple[int, ...]]:
+    """Every walk f1 -> ... -> fk (k <= K, no facet twice in a row) that is a
+    valid specular path from T to R by the exact image method (_ExactImage)."""
+    ex = _ExactImage(scene)
+    T, R = _q3(T), _q3(R)
     out = []
 
     def rec(walk):
-        if walk and valid(walk):
+        if walk and ex.valid(T, R, walk):
             out.append(tuple(walk))
         if len(walk) == K:
             return
-        for f in range(F):
+        for f in range(ex.F):
             if not (walk and walk[-1] == f):
                 rec(walk + [f])
 
     rec([])
     return sorted(out, key=lambda w: (len(w), w))
+
+
+def validate_paths_exact(scene, T, R, walks, ex: "_ExactImage" = None) -> np.ndarray:
+    """Validity of each given walk as a specular path from T to R by the exact
+    image method (the same steps as image_paths_exact): bool per walk."""
+    ex = ex or _ExactImage(scene)
+    T, R = _q3(T), _q3(R)
+    return np.array([ex.valid(T, R, [int(f) for f in w]) for w in walks], bool)
 
 
 # ---------------------------------------------------------------------------
@@ -816,7 +840,138 @@ def edge_visibility(orc: "Oracle", X: np.ndarray, edge_facets: np.ndarray, edge_
     return out
 
 
+def edge_rows(orc: "Oracle", edge_facets: np.ndarray, edge_samples: np.ndarray, s: int, rows=None,
+              threads: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """The edge rows of the matrix (edges as visibility nodes beside faces,
+    Sections I and II-A; the face seen for diffraction is the face seen for
+    reflection, Section III-B): for each edge e in `rows` (all by default),
+    ef[k][f] for every facet and ee[k][e'] for every edge.  Nodes see each other
+    when some sample p of one and q of the other have q strictly in front of one
+    of the first node's facets, p in front of one of the second's, and the open
+    segment (p, q) meets no triangle outside the facets of both."""
+    E = int(edge_facets.shape[0])
+    rows = np.arange(E, dtype=np.int32) if rows is None else np.ascontiguousarray(rows, np.int32)
+    efac = np.ascontiguousarray(edge_facets, np.int32)
+    esmp = np.ascontiguousarray(edge_samples, np.float32)
+    ef = np.zeros((len(rows), orc.F), np.uint8)
+    ee = np.zeros((len(rows), E), np.uint8)
+    orc.lib.ivo_edge_rows(orc.h, E, _ptr(efac), _ptr(esmp), s, len(rows), _ptr(rows), _ptr(ef), _ptr(ee), threads)
+    return ef.astype(bool), ee.astype(bool)
+
+
 def diffraction_counts(tx_edges: np.ndarray, rx_edges: np.ndarray) -> np.ndarray:
     """First-order diffraction candidates Tx -> edge -> Rx per snapshot: the
     edges visible from both ends."""
     return (np.asarray(tx_edges, bool) & np.asarray(rx_edges, bool)).sum(1).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Angular bouncing ranges (Section II-A: the 3-D scene is read in 2-D views, a
+# horizontal one for vertical faces and a vertical one otherwise; Section II-B,
+# eq. 1: at an edge B of the reference face the angle between BA, along the
+# face, and BF, towards a vertex F of the aim face, is arccos of their
+# normalised dot product; eq. 2: an angle of 180 degrees or more, measured from
+# BA towards the face's visible side, is recorded as 0)
+# ---------------------------------------------------------------------------
+
+def _facet_vertices_int(scene) -> List[List[Tuple[int, int, int]]]:
+    """Every vertex of each facet's triangles, in vertex-grid units (exact)."""
+    su = 1 << scene.g
+    V = [tuple(int(round(float(x) * su)) for x in v) for v in np.asarray(scene.vertices, np.float64)]
+    out: List[List[Tuple[int, int, int]]] = [[] for _ in range(scene.n_facets)]
+    for t, f in enumerate(np.asarray(scene.tri_facet)):
+        for m in range(3):
+            out[int(f)].append(V[int(scene.tri_vertices[t, m])])
+    return out
+
+
+def view_direction(ni, nj) -> Tuple[int, int, int]:
+    """The direction the pair's 2-D view looks along (integers): the line where
+    the two facets' planes meet, n_i x n_j; for parallel planes the vertical for
+    vertical facets (the horizontal view), x for horizontal ones, else the
+    horizontal direction in facet i's plane.  Its first non-zero component in
+    the order z, x, y is made positive."""
+    d = (ni[1] * nj[2] - ni[2] * nj[1], ni[2] * nj[0] - ni[0] * nj[2], ni[0] * nj[1] - ni[1] * nj[0])
+    if d == (0, 0, 0):
+        if ni[2] == 0:
+            d = (0, 0, 1)
+        elif ni[0] == 0 and ni[1] == 0:
+            d = (1, 0, 0)
+        else:
+            d = (-ni[1], ni[0], 0)
+    for k in (2, 0, 1):
+        if d[k] != 0:
+            if d[k] < 0:
+                d = (-d[0], -d[1], -d[2])
+            break
+    return d
+
+
+def angular_ranges(scene, M: np.ndarray, rows=None) -> Dict[str, np.ndarray]:
+    """For every pair with M[i, j] (i the reference face, j the aim face), in
+    row-major order: offsets int64 [F + 1] (CSR over the rows), cols int32 [nnz]
+    and ranges float64 [nnz, 4] = (omega_lo, omega_hi, mu_lo, mu_hi) in degrees.
+
+    The pair is seen along d = view_direction(n_i, n_j), which lies in both
+    facets' planes, so each facet appears as a segment.  The reference facet's
+    ends are its vertices with the smallest (A) and largest (B) value of
+    (d x n_i) . v; the aim facet's ends E, F are its extreme vertices along
+    d x n_j.  omega is the pair of angles at B between BA and BE, BF; mu the
+    pair at A between AB and AE, AF; each pair sorted.  An angle is that of the
+    two vectors projected on the view plane, arccos(u.v / (|u| |v|)) (eq. 1),
+    and it is 0 when the aim vertex is not strictly on the reference facet's
+    visible side, i.e. at or beyond 180 degrees from the face direction (eq. 2)."""
+    import math
+    nrm = facet_normals_int(scene)
+    verts = _facet_vertices_int(scene)
+    F = len(nrm)
+    M = np.asarray(M, bool)
+    offsets = np.zeros(F + 1, np.int64)
+    cols: List[int] = []
+    out: List[Tuple[float, float, float, float]] = []
+
+    def dot(a, b):
+        return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]
+
+    def cross(a, b):
+        return (a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0])
+
+    def sub(a, b):
+        return (a[0] - b[0], a[1] - b[1], a[2] - b[2])
+
+    def ends(f, t):
+        vs = verts[f]
+        k = [dot(t, v) for v in vs]
+        return vs[int(np.argmin(k))], vs[int(np.argmax(k))]
+
+    todo = set(range(F)) if rows is None else {int(r) for r in rows}
+    for i in range(F):
+        if i not in todo:
+            offsets[i + 1] = len(cols)
+            continue
+        a_i = verts[i][0]   # a vertex of the first triangle: the plane's point
+        for j in np.nonzero(M[i])[0]:
+            j = int(j)
+            d = view_direction(nrm[i], nrm[j])
+            dd = dot(d, d)
+            A, B = ends(i, cross(d, nrm[i]))
+            E, Fv = ends(j, cross(d, nrm[j]))
+
+            def angle(at, other, P):
+                if dot(sub(P, a_i), nrm[i]) <= 0:      # eq. 2: not strictly on the visible side
+                    return 0.0
+                u, v = sub(other, at), sub(P, at)
+                # projected dot products times d.d, exact in integers, then rounded once each
+                uv = dd * dot(u, v) - dot(u, d) * dot(v, d)
+                uu = dd * dot(u, u) - dot(u, d) ** 2
+                vv = dd * dot(v, v) - dot(v, d) ** 2
+                c = float(uv) / math.sqrt(float(uu) * float(vv))
+                return math.degrees(math.acos(min(1.0, max(-1.0, c))))
+
+            w = sorted((angle(B, A, E), angle(B, A, Fv)))
+            m = sorted((angle(A, B, E), angle(A, B, Fv)))
+            cols.append(j)
+            out.append((w[0], w[1], m[0], m[1]))
+        offsets[i + 1] = len(cols)
+    return {"offsets": offsets, "cols": np.asarray(cols, np.int32).reshape(-1),
+            "ranges": np.asarray(out, np.float64).reshape(-1, 4)}

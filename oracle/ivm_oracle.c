@@ -278,6 +278,78 @@ void ivo_pairs_occluder_groups(const ivo_scene *s, int n, const int32_t *I, cons
     for (int k = 0; k < n; ++k) out[k] = ivo_pair_occluder_groups(s, I[k], J[k], group_of_tri);
 }
 
+/* ---- edge rows of the matrix ---------------------------------------------
+ * Edges are visibility nodes beside faces (Sections I and II-A); the face seen
+ * for diffraction is the face seen for reflection (Section III-B).  A node is a
+ * facet (its samples, side facets {f}) or a building edge (its samples, side
+ * facets {fa, fb}, fb = -1 for an edge of one facet).  A point x is on a node's
+ * visible side when it is strictly in front of one of its side facets.  Nodes u
+ * and v see each other when some sample p of u and q of v have q on u's visible
+ * side, p on v's visible side, and the open segment (p, q) meets no triangle of
+ * a facet outside the side facets of u and v.  For two facets this is the
+ * matrix definition above. */
+
+static int ivo_front_of(const ivo_scene *s, const int *side, const double *x) {
+    for (int k = 0; k < 2; ++k)
+        if (side[k] >= 0 && ivo_orient(s, side[k], x) > 0.0) return 1;
+    return 0;
+}
+
+static int ivo_clear_ex4(const ivo_scene *s, const double *p, const double *q, const int *ex) {
+    for (int t = 0; t < s->T; ++t) {
+        int f = s->tfacet[t];
+        if (f == ex[0] || f == ex[1] || f == ex[2] || f == ex[3]) continue;
+        if (ivo_segtri(p, q, &s->ta[3 * t], &s->tb[3 * t], &s->tc[3 * t])) return 0;
+    }
+    return 1;
+}
+
+/* Node u (samples P[np], side facets su[2]) against node v (Q[nq], sv[2]). */
+int ivo_node_pair(const ivo_scene *s, const double *P, int np, const int *su, const double *Q, int nq,
+                  const int *sv) {
+    const int ex[4] = {su[0], su[1], sv[0], sv[1]};
+    for (int a = 0; a < np; ++a) {
+        const double *p = &P[3 * a];
+        if (!ivo_front_of(s, sv, p)) continue;
+        for (int b = 0; b < nq; ++b) {
+            const double *q = &Q[3 * b];
+            if (!ivo_front_of(s, su, q)) continue;
+            if (ivo_clear_ex4(s, p, q, ex)) return 1;
+        }
+    }
+    return 0;
+}
+
+/* Rows of the edge part of the matrix for the edges rows[0..n): ef[k][f] for
+ * every facet f and ee[k][e'] for every edge e' (0 on the diagonal).  Edge e
+ * has facets efac[2e], efac[2e+1] and samples esmp[(e*se + j)*3 ..]. */
+void ivo_edge_rows(const ivo_scene *s, int E, const int32_t *efac, const float *esmp, int se, int n,
+                   const int32_t *rows, uint8_t *ef, uint8_t *ee, int nthreads) {
+    double *ES = (double *)malloc(sizeof(double) * 3 * (size_t)(E * se > 0 ? E * se : 1));
+    for (int k = 0; k < 3 * E * se; ++k) ES[k] = (double)esmp[k];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (int k = 0; k < n; ++k) {
+        for (int c = 0; c < s->F + E; ++c) {
+            const int e = rows[k];
+            const int su[2] = {efac[2 * e], efac[2 * e + 1]};
+            if (c < s->F) {
+                const int sv[2] = {c, -1};
+                ef[(size_t)k * s->F + c] = (uint8_t)ivo_node_pair(
+                    s, &ES[3 * (size_t)e * se], se, su, &s->smp[3 * (size_t)s->soff[c]], s->soff[c + 1] - s->soff[c], sv);
+            } else {
+                const int e2 = c - s->F;
+                const int sv[2] = {efac[2 * e2], efac[2 * e2 + 1]};
+                ee[(size_t)k * E + e2] = e2 == e ? 0 : (uint8_t)ivo_node_pair(s, &ES[3 * (size_t)e * se], se, su,
+                                                                              &ES[3 * (size_t)e2 * se], se, sv);
+            }
+        }
+    }
+    free(ES);
+}
+
 /* ---- exactness audit ------------------------------------------------------
  * Re-evaluates the segment/triangle predicate with 128-bit integers on the
  * sample grid (unit 2^-gs m) and compares every comparison with the FP64
