@@ -6,11 +6,14 @@ One step = one pass of the whole path over the workload: build the scene
 visibility table for every snapshot, and image-tree candidate counts up to
 order 2.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  value = facet-pair queries/s = F(F-1)/2 unordered pairs
-decided per second of ivm_intervisibility_matrix GPU time (median over steps);
-txrx_ms_per_snapshot = (table + candidates) GPU time / snapshots.
+Prints one JSON line for the large-city workload (4 x 4 km, 19 872 facets,
+10 000 snapshots: the largest single-GPU configuration), with the urban-grid
+workload (2000 facets, 1000 snapshots) as a nested block.  value = facet-pair
+queries/s = F(F-1)/2 unordered pairs decided per second of
+ivm_intervisibility_matrix GPU time (median over steps); txrx_ms_per_snapshot =
+(table + candidates) GPU time / snapshots.
 
-    python bench.py [--steps K] [--warmup W] [--config c2] [--order plain]
+    python bench.py [--steps K] [--warmup W] [--config c3] [--order plain]
 """
 import argparse
 import json
@@ -26,46 +29,68 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 non-packed FP32 lane-ops/s
-# (one FMA = one lane-op; 78.6 TFLOP/s counting an FMA as two).
+# (one FMA = one lane-op; 78.6 TFLOP/s counting an FMA as two).  FP64 vector
+# operations issue at the same one per lane per clock on MI355X.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic work per counted unit (VALU lane-ops): a segment/box slab test 14
-# (three slabs: six products, six min/max, the entry/exit compare), a segment/triangle test ~43 (Moller-Trumbore 33 + filter 10),
-# an FP64 recheck ~35 more, one face-plane step of an exact solid test ~25 FP64
-# ops (two plane values, the interval update with an exact product compare;
-# MI355X issues FP64 vector ops at one per lane per clock, the rate the peak
-# below counts).
+# (three slabs: six products, six min/max, the entry/exit compare), a
+# segment/triangle test ~43 (Moller-Trumbore 33 + filter 10).  These two are the
+# useful FP32 work the roofline fraction counts.  Reported beside it, not in it:
+# an FP64 recheck ~35 and one face-plane step of an exact solid test ~25 FP64
+# lane-ops (two plane values, the interval update with an exact product compare).
 OPS_BOX, OPS_TRI, OPS_RECHECK, OPS_SOLID_PLANE = 14, 43, 35, 25
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_pairs_urban_grid_c2.txt")
+PROFILES = {"c2": os.path.join(ROOT, "profiles", "k_pairs_urban_grid_c2.txt"),
+            "c3": os.path.join(ROOT, "profiles", "k_pairs_large_city_c3.txt")}
 
 
-def profiled_traffic(config: str):
-    """HBM bytes of one matrix call's pair kernels (two probe rounds and the pair
-    kernel) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the
-    urban-grid workload, or None when it is another workload or the traversal
-    source has changed since the counters were taken."""
+def profiled_counters(config: str) -> dict:
+    """Per-launch counter figures of the pair and point kernels from the committed
+    rocprofv3 summary of this workload, while the traversal source still has the
+    SHA-256 recorded there (else nothing): HBM bytes of one matrix call's pair
+    kernels (two probe rounds and the pair kernel) and of the point kernel
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration the summary
+    states), and L2 bandwidth (TCC requests x 128 B / average kernel time)."""
     import hashlib
     import re
-    if config != "c2" or not os.path.exists(PROFILE):
-        return None
-    text = open(PROFILE).read()
+    path = PROFILES.get(config)
+    if not path or not os.path.exists(path):
+        return {}
+    text = open(path).read()
     m = re.search(r"sha256: ([0-9a-f]{64})", text)
     src = os.path.join(ROOT, "paper_2501_02747_amd", "csrc", "traverse.hip")
     if not m or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
-        return None
-    mib = {}
-    for name in ("k_pairs<false>", "k_probe_pairs<false>"):
+        return {}
+    out = {}
+    hbm = {}
+    for name in ("k_pairs<false>", "k_probe_pairs<false>", "k_points<false>"):
         r = re.search(re.escape(name) + r"\s+fetch\s+([0-9.]+) MiB\s+write\s+([0-9.]+) MiB", text)
-        if not r:
-            return None
-        mib[name] = float(r.group(1)) + float(r.group(2))
-    return int((mib["k_pairs<false>"] + 2 * mib["k_probe_pairs<false>"]) * 2 ** 20)
+        if r:
+            hbm[name] = (float(r.group(1)) + float(r.group(2))) * 2 ** 20
+    if "k_pairs<false>" in hbm and "k_probe_pairs<false>" in hbm:
+        out["pairs_hbm_bytes"] = int(hbm["k_pairs<false>"] + 2 * hbm["k_probe_pairs<false>"])
+    if "k_points<false>" in hbm:
+        out["points_hbm_bytes"] = int(hbm["k_points<false>"])
+    for name, key in (("k_pairs<false>", "pairs"), ("k_points<false>", "points")):
+        r = re.search(re.escape(name) + r"\s+l2\s+([0-9.]+) GB/s", text)
+        if r:
+            out[f"{key}_l2_gbs"] = float(r.group(1))
+    r = re.search(r"counters k_pairs<false>: (.*)", text)
+    if r:
+        out["pairs_counters"] = r.group(1).strip()
+    return out
 
 
 def lane_ops(st: dict) -> int:
-    return (st["box_tests"] * OPS_BOX + st["tri_tests"] * OPS_TRI + st["rechecks"] * OPS_RECHECK
-            + st["solid_planes"] * OPS_SOLID_PLANE)
+    """Useful FP32 VALU lane-ops: box slab tests and triangle tests."""
+    return st["box_tests"] * OPS_BOX + st["tri_tests"] * OPS_TRI
+
+
+def fp64_lane_ops(st: dict) -> int:
+    """FP64 lane-ops of rechecks and exact solid tests (reported separately)."""
+    return st["rechecks"] * OPS_RECHECK + st["solid_planes"] * OPS_SOLID_PLANE
+
 
 WORKLOADS = {
     "c1": "tiny urban 200x200 m, 8 boxes, 42 facets / 84 tris, 4x4 samples, 10 snapshots",
@@ -82,7 +107,8 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-nested", action="store_true", help="skip the nested urban-grid block of the c3 run")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--snapshots", type=int, default=None)
     ap.add_argument("--order", default="plain", choices=["plain", "index", "reversed", "learned"])
@@ -118,15 +144,31 @@ def cpu_baseline(scene, seconds, seed=0):
         orc.pairs(I, J)
         t_pairs += time.perf_counter() - t0
         n_pairs += len(I)
+    # whole snapshots while they are cheap (small scenes); on large scenes one
+    # snapshot's table over a seeded subset of the facets from both ends, scaled
+    # to all F facets
     n_snap, t_snap = 0, 0.0
     idx = rng.permutation(scene.n_snapshots)
-    while t_snap < 0.25 * seconds and n_snap < len(idx):
-        k = idx[n_snap:n_snap + 1]
+    snap_note = ""
+    if F <= 4000:
+        while t_snap < 0.25 * seconds and n_snap < len(idx):
+            k = idx[n_snap:n_snap + 1]
+            t0 = time.perf_counter()
+            tv, rv, los = orc.txrx(scene.tx[k], scene.rx[k])
+            oracle.candidates_matmul(np.zeros((F, F), bool), tv, rv, los, 1)
+            t_snap += time.perf_counter() - t0
+            n_snap += 1
+        snap_note = f"Tx/Rx table for {n_snap} whole snapshots"
+    else:
+        n = idx[0]
+        sub = np.sort(rng.choice(F, F // 16, replace=False))
         t0 = time.perf_counter()
-        tv, rv, los = orc.txrx(scene.tx[k], scene.rx[k])
-        oracle.candidates_matmul(np.zeros((F, F), bool), tv, rv, los, 1)
-        t_snap += time.perf_counter() - t0
-        n_snap += 1
+        orc.point_facets(np.repeat(scene.tx[n:n + 1], len(sub), 0), sub)
+        orc.point_facets(np.repeat(scene.rx[n:n + 1], len(sub), 0), sub)
+        orc.los(scene.tx[n:n + 1], scene.rx[n:n + 1])
+        t_snap = (time.perf_counter() - t0) * F / len(sub)
+        n_snap = 1
+        snap_note = f"Tx/Rx table of one snapshot over {len(sub)} of the {F} facets, scaled to all of them"
     # the same oracle on one host thread, on a smaller sample (a tenth of the time); the
     # oracle's thread setting persists, so it is put back afterwards
     n_one, t_one = 0, 0.0
@@ -144,8 +186,7 @@ def cpu_baseline(scene, seconds, seed=0):
     return {"value": n_pairs / t_pairs, "unit": "facet-pair queries/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{n_pairs} uniformly drawn facet pairs of the same scene ({t_pairs:.1f} s); "
-                      f"Tx/Rx table for {n_snap} snapshots: {1e3 * t_snap / max(n_snap, 1):.1f} ms/snapshot "
-                      f"(table only)",
+                      f"{snap_note}: {1e3 * t_snap / max(n_snap, 1):.1f} ms/snapshot (table only)",
             "ms_per_snapshot": 1e3 * t_snap / max(n_snap, 1),
             "value_1core": n_one / t_one, "sample_1core": f"{n_one} facet pairs on one thread ({t_one:.1f} s)"}
 
@@ -180,6 +221,17 @@ def verify(ivm, scene, M, tv, rv, los, counts):
         ok = bool((gm == Mo).all() and (gtv == tvo).all() and (grv == rvo).all() and (glos == z["los"]).all()
                   and (counts.cpu().numpy() == co).all())
         return {"mode": "full oracle cache", "ok": ok}
+    mode, ok = "", True
+    rows_cache = os.path.join(ROOT, "tests", "golden", "cache", f"{scene.name}_seed{scene.seed}_rows.npz")
+    if os.path.exists(rows_cache):
+        z = np.load(rows_cache, allow_pickle=False)
+        if int(z["F"]) == F and int(z["snaps"].max()) < scene.n_snapshots:
+            rows, snaps = z["rows"], z["snaps"]
+            ok &= bool((gm[rows] == np.unpackbits(z["M"], axis=1)[:, :F].astype(bool)).all())
+            ok &= bool((gtv[snaps] == np.unpackbits(z["tx_vis"], axis=1)[:, :F].astype(bool)).all())
+            ok &= bool((grv[snaps] == np.unpackbits(z["rx_vis"], axis=1)[:, :F].astype(bool)).all())
+            ok &= bool((glos[snaps] == z["los"]).all())
+            mode = f"{len(rows)} whole rows and {len(snaps)} whole snapshots from the stored oracle results; "
     orc = oracle.Oracle(scene)
     rng = np.random.default_rng(1)
     I = rng.integers(0, F, 300)
@@ -190,7 +242,7 @@ def verify(ivm, scene, M, tv, rv, los, counts):
         pick = vis[rng.integers(0, len(vis), 150)]
         I = np.concatenate([I, pick[:, 0]])
         J = np.concatenate([J, pick[:, 1]])
-    ok = bool((orc.pairs(I, J) == gm[I, J]).all())
+    ok &= bool((orc.pairs(I, J) == gm[I, J]).all())
     N = scene.n_snapshots
     n_idx = rng.integers(0, N, 200)
     f_idx = rng.integers(0, F, 200)
@@ -198,7 +250,7 @@ def verify(ivm, scene, M, tv, rv, los, counts):
     ok &= bool((orc.point_facets(scene.rx[n_idx], f_idx) == grv[n_idx, f_idx]).all())
     ok &= bool((orc.los(scene.tx[n_idx], scene.rx[n_idx]) == glos[n_idx]).all())
     ok &= bool((gm == gm.T).all() and not gm.diagonal().any())
-    return {"mode": f"sampled: {len(I)} pairs, 200 Tx + 200 Rx entries, 200 LoS", "ok": ok}
+    return {"mode": mode + f"sampled: {len(I)} pairs, 200 Tx + 200 Rx entries, 200 LoS", "ok": ok}
 
 
 def run_batched(args, ivm, torch, sg):
@@ -301,10 +353,23 @@ def main():
         sys.exit(1)
     if args.config == "c4":
         return run_batched(args, ivm, torch, sg)
+    out = run_single(args, ivm, torch, sg, args.config)
+    if args.config == "c3" and not args.no_nested and args.snapshots is None and args.seed is None:
+        nested = run_single(args, ivm, torch, sg, "c2", headline=False)
+        out["urban_grid_c2"] = {k: nested[k] for k in (
+            "value", "unit", "ms_per_step", "txrx_ms_per_snapshot", "phase_ms_median", "kernel_ms", "config",
+            "roofline", "roofline_points", "compare_order", "verified", "ranges", "relations", "candidates_order4",
+            "edges") if k in nested}
+    print(json.dumps(out), flush=True)
+
+
+def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict:
+    """One single-scene workload: timed steps, the other traversal order, the calls
+    beside the hot path, verification and (for the headline line) the CPU baseline."""
     kw = {}
     if args.snapshots is not None:
         kw["n_snap"] = args.snapshots
-    scene = sg.make_config(args.config, args.seed, **kw)
+    scene = sg.make_config(config, args.seed, **kw)
     F, N = scene.n_facets, scene.n_snapshots
     order = {"plain": ivm.IVM_ORDER_PLAIN, "index": ivm.IVM_ORDER_INDEX, "reversed": ivm.IVM_ORDER_REVERSED,
              "learned": ivm.IVM_ORDER_LEARNED}[args.order]
@@ -359,7 +424,7 @@ def main():
         torch.cuda.synchronize()
         progress(f"copied {args.copy_mib} MiB (profiler calibration)")
         del src, dst
-    progress(f"{args.config}: F={F} T={scene.n_triangles} S={scene.n_samples} N={N}; warmup {args.warmup}")
+    progress(f"{config}: F={F} T={scene.n_triangles} S={scene.n_samples} N={N}; warmup {args.warmup}")
     for k in range(args.warmup):
         step(None)
         torch.cuda.synchronize()
@@ -391,6 +456,8 @@ def main():
     ops_points = lane_ops(sp)
     ach = ops_pairs / (pairs_kernel_ms / 1e3) / 1e12
     ach_p = ops_points / (points_kernel_ms / 1e3) / 1e12
+    f64_pairs, f64_points = fp64_lane_ops(sm), fp64_lane_ops(sp)
+    prof = profiled_counters(config)
     out = {
         "metric": "facet-pair vis queries/s + Tx/Rx table ms/snapshot, learned vs plain, bit-exact",
         "value": value,
@@ -404,7 +471,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.fp64_only else "f32 (f64 recheck)",
         "data": "synthetic (seeded scene generator)",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "facets": F,
+        "config": {"workload": f"{config}: {WORKLOADS[config]}", "facets": F,
                    "triangles": scene.n_triangles, "samples": scene.n_samples, "snapshots": N,
                    "seed": scene.seed, "order": args.order, "exhaustive": bool(args.exhaustive),
                    "parallelism": "single GPU"},
@@ -414,11 +481,20 @@ def main():
         "stats_matrix": sm,
         "stats_table": sp,
         "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
-                     "frac": ach / VALU_PEAK_TOPS, "traffic": profiled_traffic(args.config),
+                     "frac": ach / VALU_PEAK_TOPS, "traffic": prof.get("pairs_hbm_bytes"),
                      "traffic_unit": "HBM bytes per matrix call (FETCH_SIZE + WRITE_SIZE, from profiles/)",
-                     "kernel": "k_probe_pairs + k_pairs (one timed region)", "ops_per_launch": ops_pairs},
+                     "kernel": "k_probe_pairs x2 + k_pairs (one timed region)",
+                     "ops_per_launch": ops_pairs, "ops_units": "box tests x 14 + triangle tests x 43 (FP32)",
+                     "fp64_ops_per_launch": f64_pairs,
+                     "fp64_ops_units": "rechecks x 35 + solid face-plane steps x 25 (FP64, not in frac)",
+                     "frac_incl_fp64": (ops_pairs + f64_pairs) / (pairs_kernel_ms / 1e3) / 1e12 / VALU_PEAK_TOPS,
+                     "l2_gbs": prof.get("pairs_l2_gbs"), "counters": prof.get("pairs_counters")},
         "roofline_points": {"bound": "alu", "achieved": ach_p, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
-                            "frac": ach_p / VALU_PEAK_TOPS, "kernel": "k_points"},
+                            "frac": ach_p / VALU_PEAK_TOPS, "kernel": "k_points",
+                            "fp64_ops_per_launch": f64_points,
+                            "frac_incl_fp64": (ops_points + f64_points) / (points_kernel_ms / 1e3) / 1e12
+                            / VALU_PEAK_TOPS, "traffic": prof.get("points_hbm_bytes"),
+                            "l2_gbs": prof.get("points_l2_gbs")},
     }
     # the other traversal order on the same matrix, timed the same way, bits compared
     if have_model and not args.no_compare:
@@ -558,12 +634,14 @@ def main():
         progress("verifying against the oracle")
         counts_now = counts
         out["verified"] = verify(ivm, scene, M, tv, rv, los, counts_now)
-    if not args.no_cpu_baseline:
+    if headline and not args.no_cpu_baseline:
         progress("timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_baseline_seconds)
         out["cpu_baseline"]["host"] = cpu_model()
         out["cpu_baseline"]["nproc"] = os.cpu_count()
-    print(json.dumps(out), flush=True)
+    return out
+
+
 
 
 if __name__ == "__main__":

@@ -1,6 +1,8 @@
 """Batched scenes in one captured hipGraph: every scene's matrix, tables, LoS and
 candidate counts equal the single-scene calls (and the oracle on the small
-scenes), on every graph replay."""
+scenes), on every graph replay; the batched workload at its full size against
+the single-scene calls and stored oracle rows and snapshots of every scene."""
+import os
 import sys
 
 import numpy as np
@@ -87,3 +89,59 @@ def test_batch_of_many_tiny_scenes(oracle_mod, exhaustive):
         assert torch.equal(batch.M[k], M), k
         Mo, _ = oracle_mod.Oracle(s).matrix()
         assert (ivm.unpack_bits(batch.M[k], s.n_facets) == Mo).all(), k
+
+
+C4_CACHE = os.path.join(os.path.dirname(__file__), "golden", "cache", "c4_rows.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(C4_CACHE), reason="batched-workload oracle rows not generated")
+def test_batched_workload_full_size(oracle_mod):
+    """The batched workload at its real size (64 scenes of 636-4856 facets,
+    seeds 1000-1063, 64 077 snapshots) in one captured graph, in the launch
+    configuration of the batched bench (autotuned waves per CU and stack depth):
+    every scene's matrix, tables, LoS and candidate counts equal the single-scene
+    calls, and two whole seeded rows and two whole seeded snapshots of every
+    scene equal the stored oracle results (tests/golden/make_c4_oracle_cache.py)."""
+    import torch
+    import paper_2501_02747_amd as ivm
+    from paper_2501_02747_amd.autotune import autotune_matrix
+    _log("[batch] generating the 64 batched scenes")
+    scenes = sg.gen_c4(1000, 64)
+    z = np.load(C4_CACHE, allow_pickle=False)
+    F = np.array([s.n_facets for s in scenes])
+    assert F.max() >= 4000 and len(scenes) == 64
+    gs = [ivm.GpuScene.from_scene(s).check() for s in scenes]
+    txs = [torch.as_tensor(s.tx).cuda() for s in scenes]
+    rxs = [torch.as_tensor(s.rx).cuda() for s in scenes]
+    calib = int(np.argsort(F)[len(F) // 2])
+    tune = autotune_matrix(gs[calib], repeats=1, cache_path=None,
+                           grid=[(w, d) for w in (8, 16, 24, 32) for d in (16, 24)])
+    _log(f"[batch] autotuned: waves/CU {tune['waves_per_cu']}, stack {tune['stack_depth']}")
+    opts = ivm.make_opts(waves_per_cu=tune["waves_per_cu"], stack_depth=tune["stack_depth"])
+    batch = ivm.Batch(gs, txs, rxs, opts)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch.run(stream)
+    stream.synchronize()
+    _log("[batch] graph run done; comparing with single-scene calls and the oracle rows")
+    for k, (g, s) in enumerate(zip(gs, scenes)):
+        M = ivm.ivm_intervisibility_matrix(g)
+        tv, rv, los = ivm.ivm_txrx_visibility_table(g, txs[k], rxs[k])
+        c = ivm.ivm_image_tree_candidates(g, M, tv, rv, los, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(batch.M[k], M), (k, "M")
+        assert torch.equal(batch.tv[k], tv) and torch.equal(batch.rv[k], rv), (k, "tables")
+        assert torch.equal(batch.los[k], los) and torch.equal(batch.counts[k], c), (k, "los / counts")
+        tag = f"{k:02d}"
+        n = s.n_facets
+        assert int(z[f"F_{tag}"]) == n
+        m = ivm.unpack_bits(batch.M[k], n)
+        assert (m == m.T).all() and not m.diagonal().any(), k
+        rows, snaps = z[f"rows_{tag}"], z[f"snaps_{tag}"]
+        Mo = np.unpackbits(z[f"M_{tag}"], axis=1)[:, :n].astype(bool)
+        assert (m[rows] == Mo).all(), (k, "rows", int((m[rows] != Mo).sum()))
+        for key, t in (("tx", batch.tv[k]), ("rx", batch.rv[k])):
+            o = np.unpackbits(z[f"{key}_{tag}"], axis=1)[:, :n].astype(bool)
+            assert (ivm.unpack_bits(t, n)[snaps] == o).all(), (k, key)
+        assert (batch.los[k].cpu().numpy().astype(bool)[snaps] == z[f"los_{tag}"]).all(), (k, "los")
+    _log(f"[batch] 64 scenes equal ({int(F.sum())} facets)")
