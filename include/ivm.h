@@ -325,6 +325,25 @@ ivm_status ivm_visibility_ranges(const ivm_scene *scene, int32_t n_snap, const u
                                  int32_t *d_range_start, double *d_range_tc, double *d_range_dist, int32_t *d_n_ranges,
                                  double *d_tc_mean, hipStream_t stream);
 
+/* Allocation-free variant of ivm_visibility_ranges, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, outputs and results are those of
+ * ivm_visibility_ranges without the workspace: the scratch is a fixed array of
+ * the library, about 1.7 MB on each GPU the library runs on, held until the
+ * process ends, sized for at most IVM_RANGES_NOALLOC_MAX_SNAP snapshots.  The
+ * call runs on the current device (the stream must belong to it), looks the
+ * array's address up on the first call on each device and allocates nothing.
+ * Every call on one GPU shares that GPU's array (its contents on entry do not
+ * matter): calls that overlap on one GPU, on any streams, race.
+ * Errors: IVM_ERR_INVALID_ARGUMENT (as ivm_visibility_ranges), IVM_ERR_WORKSPACE
+ * (n_snap > IVM_RANGES_NOALLOC_MAX_SNAP), IVM_ERR_HIP. */
+#define IVM_RANGES_NOALLOC_MAX_SNAP 32768
+ivm_status ivm_visibility_ranges_noalloc(const ivm_scene *scene, int32_t n_snap, const uint64_t *d_tx_vis,
+                                         const uint64_t *d_rx_vis, const uint8_t *d_los, const float *d_tx,
+                                         const float *d_rx, double dt, int32_t *d_events, int32_t *d_range_start,
+                                         double *d_range_tc, double *d_range_dist, int32_t *d_n_ranges,
+                                         double *d_tc_mean, hipStream_t stream);
+
 /* ---- learned occluder ordering ---------------------------------------------
  * A small network scores, for a facet pair, how likely each of the 32 treelets is
  * to hold an occluder; IVM_ORDER_LEARNED visits the treelets in that order.  The

@@ -37,7 +37,8 @@ EXPORTED = [
     "ivm_status_string", "ivm_scene_workspace_size", "ivm_build_scene", "ivm_scene_status",
     "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
     "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups", "ivm_visibility_ranges",
-    "ivm_visibility_ranges_workspace_size", "ivm_interface_relations", "ivm_edge_visibility",
+    "ivm_visibility_ranges_workspace_size", "ivm_visibility_ranges_noalloc", "ivm_interface_relations",
+    "ivm_edge_visibility",
     "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
@@ -127,6 +128,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_image_tree_candidates.argtypes = [P, P, i32, P, P, P, i32, P, P, P, sz, P]
     lib.ivm_visibility_ranges.restype = i32
     lib.ivm_visibility_ranges.argtypes = [P, i32, P, P, P, P, P, ctypes.c_double, P, sz, P, P, P, P, P, P, P]
+    lib.ivm_visibility_ranges_noalloc.restype = i32
+    lib.ivm_visibility_ranges_noalloc.argtypes = [P, i32, P, P, P, P, P, ctypes.c_double, P, P, P, P, P, P, P]
     lib.ivm_interface_relations.restype = i32
     lib.ivm_interface_relations.argtypes = [P, P, P, P, P, P]
     lib.ivm_edge_visibility.restype = i32
@@ -473,6 +476,24 @@ def ivm_visibility_ranges(scene: GpuScene, tx_vis, rx_vis, los, tx, rx, dt: floa
         stream.synchronize()
     L = int(nr.item())
     return events, starts[:L], tc[:L], dist[:L], float(mean.item())
+
+
+IVM_RANGES_NOALLOC_MAX_SNAP = 32768
+
+
+def ivm_visibility_ranges_noalloc(scene: GpuScene, tx_vis, rx_vis, los, tx, rx, dt: float, events, starts, tc,
+                                  dist, n_ranges, mean, stream=None):
+    """The allocation-free ranges call: the outputs are caller tensors (events
+    int32 [N, 5], starts int32 [N], tc float64 [N], dist float64 [N, 2],
+    n_ranges int32 [1], mean float64 [1], all on the current device) and the
+    library's fixed scratch replaces the workspace.  Nothing is allocated or
+    synchronised here."""
+    N = int(tx_vis.shape[0])
+    lib = load_library()
+    _check(lib.ivm_visibility_ranges_noalloc(scene.handle, N, _ptr(tx_vis), _ptr(rx_vis), _ptr(los), _ptr(tx),
+                                             _ptr(rx), float(dt), _ptr(events), _ptr(starts), _ptr(tc), _ptr(dist),
+                                             _ptr(n_ranges), _ptr(mean), _stream(stream)),
+           "ivm_visibility_ranges_noalloc")
 
 
 def ivm_triangle_groups(scene: GpuScene, stream=None):

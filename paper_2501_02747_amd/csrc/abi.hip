@@ -306,6 +306,24 @@ ivm_status ivm_visibility_ranges(const ivm_scene *scene, int32_t n_snap, const u
     return IVM_OK;
 }
 
+ivm_status ivm_visibility_ranges_noalloc(const ivm_scene *scene, int32_t n_snap, const uint64_t *d_tx_vis,
+                                         const uint64_t *d_rx_vis, const uint8_t *d_los, const float *d_tx,
+                                         const float *d_rx, double dt, int32_t *d_events, int32_t *d_range_start,
+                                         double *d_range_tc, double *d_range_dist, int32_t *d_n_ranges,
+                                         double *d_tc_mean, hipStream_t stream) {
+    if (!scene || n_snap < 1 || !(dt > 0.0) || !std::isfinite(dt)) return IVM_ERR_INVALID_ARGUMENT;
+    if (!d_tx_vis || !d_rx_vis || !d_los || !d_tx || !d_rx || !d_events || !d_range_start || !d_range_tc ||
+        !d_range_dist || !d_n_ranges || !d_tc_mean)
+        return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap > kRangesNoAllocMaxSnap) return IVM_ERR_WORKSPACE;
+    void *ws = nullptr;
+    if (ranges_scratch(&ws) != hipSuccess || !ws) return IVM_ERR_HIP;
+    if (launch_ranges(scene->s.dev, n_snap, d_tx_vis, d_rx_vis, d_los, d_tx, d_rx, dt, ws, d_events, d_range_start,
+                      d_range_tc, d_range_dist, d_n_ranges, d_tc_mean, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
 ivm_status ivm_model_workspace_size(int32_t max_batch, size_t *bytes) {
     if (!bytes || max_batch <= 0 || max_batch > (1 << 24)) return IVM_ERR_INVALID_ARGUMENT;
     *bytes = model_workspace_bytes(max_batch);

@@ -226,6 +226,10 @@ hipError_t launch_cull_scan(Scene &sc, uint64_t *M, ivm_stats *stats, hipStream_
 hipError_t launch_relations(const SceneDev &sc, const uint64_t *M, uint64_t *par, uint64_t *per, int8_t *cls,
                             hipStream_t s);
 size_t ranges_workspace_bytes(int N);
+// Largest trajectory of the allocation-free ranges call, and the address of its
+// scratch on the current device (looked up once per device).
+constexpr int kRangesNoAllocMaxSnap = 32768;
+hipError_t ranges_scratch(void **out);
 hipError_t launch_ranges(const SceneDev &sc, int N, const uint64_t *tv, const uint64_t *rv, const uint8_t *los,
                          const float *tx, const float *rx, double dt, void *ws, int *events, int *starts, double *tc,
                          double *dist, int *n_ranges, double *mean, hipStream_t s);

@@ -10,6 +10,8 @@
 // each side's ranges with block scans, and one thread per range sums its route
 // steps in snapshot order (FP64, no contraction), so every result is the
 // sequential one whatever the launch.
+#include <mutex>
+
 #include "ivm_internal.h"
 
 namespace ivm {
@@ -181,6 +183,38 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(int N, double dt, void
 }  // namespace
 
 size_t ranges_workspace_bytes(int N) { return (size_t)N * (4 * sizeof(double) + 5 * sizeof(int)) + 256; }
+
+// Scratch of the allocation-free variant: room for kRangesNoAllocMaxSnap
+// snapshots, one copy per GPU for the life of the process.  Host code never
+// passes `scratch` itself to a kernel (on the host the name is a stand-in, not
+// a device address); it uses the address hipGetSymbolAddress reports for the
+// current device, looked up once per device.
+constexpr size_t kRangesScratchBytes = (size_t)kRangesNoAllocMaxSnap * (4 * sizeof(double) + 5 * sizeof(int)) + 256;
+static_assert(kRangesNoAllocMaxSnap == IVM_RANGES_NOALLOC_MAX_SNAP, "allocation-free limit");
+static __device__ __align__(256) unsigned char scratch[kRangesScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t ranges_scratch(void **out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_ranges(const SceneDev &sc, int N, const uint64_t *tv, const uint64_t *rv, const uint8_t *los,
                          const float *tx, const float *rx, double dt, void *ws, int *events, int *starts, double *tc,

@@ -83,6 +83,15 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.ivm_visibility_ranges_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 1000 * 52
     out = ctypes.c_void_p()
     assert lib.ivm_build_scene(None, None, 0, None, ctypes.byref(out)) == ivm.IVM_ERR_INVALID_ARGUMENT
+    # the allocation-free ranges call: null arguments, and a trajectory beyond its
+    # fixed scratch is refused before the scene or any device memory is touched
+    nul = [None] * 6
+    assert lib.ivm_visibility_ranges_noalloc(None, 10, *[None] * 5, 0.01, *nul, None) \
+        == ivm.IVM_ERR_INVALID_ARGUMENT
+    fake = [1] * 5                                 # never dereferenced
+    assert lib.ivm_visibility_ranges_noalloc(1, ivm.IVM_RANGES_NOALLOC_MAX_SNAP + 1, *fake, 0.01, *[1] * 6, None) \
+        == ivm.IVM_ERR_WORKSPACE
+    assert lib.ivm_visibility_ranges_noalloc(1, 10, *fake, 0.0, *[1] * 6, None) == ivm.IVM_ERR_INVALID_ARGUMENT
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 130])
