@@ -287,6 +287,63 @@ ivm_status ivm_edge_visibility(ivm_scene *scene, const ivm_matrix_opts *opts, in
                                int32_t n_snap, const float *d_tx, const float *d_rx, uint64_t *d_tx_edges,
                                uint64_t *d_rx_edges, int64_t *d_diffraction, hipStream_t stream);
 
+/* Edge rows of the matrix: edges are visibility nodes beside faces (Sections I
+ * and II-A), and the face seen for diffraction is the face seen for reflection
+ * (Section III-B).  A node is a facet (its samples; side facets {f}) or an edge
+ * e (its samples d_edge_samples[e * s + j]; side facets d_edge_facets[e] =
+ * (fa, fb), fb = -1 for an edge of one facet; inputs as ivm_edge_visibility).
+ * Edge e and node v see each other iff some sample p of e and q of v have q
+ * strictly in front of fa or fb, p strictly in front of one of v's side
+ * facets, and the open segment (p, q) meets no triangle of a facet outside the
+ * side facets of both (exact predicates, as the matrix).  For each k < n_rows
+ * and e = d_rows[k] (int32, device): bit f of d_edge_facet[k] (uint64[n_rows][W])
+ * is set iff e and facet f see each other, and bit e2 of d_edge_edge[k]
+ * (uint64[n_rows][We], We = ceil(E / 64)) iff e and edge e2 != e do; padding
+ * bits are zero.  The facet-to-edge columns are the transpose (the relation is
+ * symmetric).  Row ids outside [0, E), off-grid samples and bad facet ids are
+ * reported by ivm_scene_status.  opts may be NULL; results do not depend on it.
+ * Asynchronous on `stream`.  Errors: IVM_ERR_INVALID_ARGUMENT, IVM_ERR_HIP. */
+ivm_status ivm_edge_rows(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_edges, int32_t samples_per_edge,
+                         const int32_t *d_edge_facets, const float *d_edge_samples, int32_t n_rows,
+                         const int32_t *d_rows, uint64_t *d_edge_facet, uint64_t *d_edge_edge, hipStream_t stream);
+
+/* Angular bouncing ranges of the visible facet pairs (Section II-A: the scene
+ * is read in 2-D views, a horizontal one for vertical faces and a vertical one
+ * otherwise, in which each face is a segment; Section II-B, eq. 1: at an end B
+ * of the reference face the angle between BA, along the face, and BF, towards
+ * an end F of the aim face, is the arccos of their normalised dot product;
+ * eq. 2: an angle of 180 degrees or more, measured from the face towards its
+ * visible side, is recorded as 0).  For every set bit (i, j) of d_M (row i the
+ * reference face, column j the aim face; any matrix, symmetric or not):
+ *   - the view looks along d = n_i x n_j (the line where both planes meet),
+ *     or for parallel planes along z (vertical facets), x (horizontal facets)
+ *     or the horizontal direction (-n_i.y, n_i.x, 0) in facet i's plane; the
+ *     first non-zero component of d in the order z, x, y is positive; n_f is
+ *     the normal (b - a) x (c - a) of facet f's first triangle;
+ *   - facet i's ends are its vertices with the smallest (A) and largest (B)
+ *     value of (d x n_i) . v, facet j's ends E and F those of (d x n_j) . v;
+ *   - omega = the two angles at B between BA and BE, BF, sorted; mu = the two
+ *     angles at A between AB and AE, AF, sorted; each angle is that of the two
+ *     vectors projected on the plane normal to d, in degrees in [0, 180], and
+ *     0 when the aim vertex is not strictly in front of facet i (eq. 2).
+ * The three integer terms of each cosine are exact (128-bit) and rounded once
+ * to FP64; the arccos is the device library's (a few ulp).
+ * Outputs (caller-owned device memory, row-major over the set bits):
+ *   d_offsets int64[F + 1]: CSR row offsets (row i's pairs are
+ *     [d_offsets[i], d_offsets[i + 1])); padding bits of d_M are ignored;
+ *   d_cols int32[cap]: the aim facet j of each pair, ascending within a row;
+ *   d_ranges double[cap][4]: (omega_lo, omega_hi, mu_lo, mu_hi).
+ * With d_cols and d_ranges NULL only the offsets are written (asynchronous).
+ * Otherwise the call synchronises the stream twice: to check cap (returns
+ * IVM_ERR_CAPACITY, with valid offsets, when the pairs do not fit) and at the
+ * end to report pairs whose integer terms could leave 128 bits (such a pair
+ * gets NaN angles, the call returns IVM_ERR_GRID and so does ivm_scene_status
+ * from then on; it needs coordinates and normals far beyond the configured
+ * scenes).  Errors: IVM_ERR_INVALID_ARGUMENT, IVM_ERR_CAPACITY, IVM_ERR_GRID,
+ * IVM_ERR_HIP. */
+ivm_status ivm_angular_ranges(ivm_scene *scene, const uint64_t *d_M, int64_t *d_offsets, int32_t *d_cols,
+                              double *d_ranges, size_t cap, hipStream_t stream);
+
 /* Ray creation and suppression points along one trajectory, the visibility
  * ranges between them and their coherence times (Section III-C: the visibility
  * change nodes of the inter-visibility table of a mobile transmitter or

@@ -38,7 +38,7 @@ EXPORTED = [
     "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
     "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups", "ivm_visibility_ranges",
     "ivm_visibility_ranges_workspace_size", "ivm_visibility_ranges_noalloc", "ivm_interface_relations",
-    "ivm_edge_visibility",
+    "ivm_edge_visibility", "ivm_edge_rows", "ivm_angular_ranges",
     "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
@@ -132,6 +132,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_visibility_ranges_noalloc.argtypes = [P, i32, P, P, P, P, P, ctypes.c_double, P, P, P, P, P, P, P]
     lib.ivm_interface_relations.restype = i32
     lib.ivm_interface_relations.argtypes = [P, P, P, P, P, P]
+    lib.ivm_edge_rows.restype = i32
+    lib.ivm_edge_rows.argtypes = [P, ctypes.POINTER(ivm_matrix_opts), i32, i32, P, P, i32, P, P, P, P]
+    lib.ivm_angular_ranges.restype = i32
+    lib.ivm_angular_ranges.argtypes = [P, P, P, P, P, sz, P]
     lib.ivm_edge_visibility.restype = i32
     lib.ivm_edge_visibility.argtypes = [P, ctypes.POINTER(ivm_matrix_opts), i32, i32, P, P, i32, P, P, P, P, P, P]
     lib.ivm_visibility_ranges_workspace_size.restype = i32
@@ -433,6 +437,47 @@ def ivm_edge_visibility(scene: GpuScene, edge_facets, edge_samples, samples_per_
         _ptr(edge_samples), N, _ptr(tx), _ptr(rx), _ptr(te), _ptr(re_), _ptr(cnt), _stream(stream)),
         "ivm_edge_visibility")
     return te[:, :We], re_[:, :We], cnt[:N]
+
+
+def ivm_edge_rows(scene: GpuScene, edge_facets, edge_samples, samples_per_edge: int, rows,
+                  opts: Optional[ivm_matrix_opts] = None, stream=None):
+    """Edge rows of the matrix for the edges listed in `rows` (int32 [n], device):
+    (edge_facet int64 [n, W], edge_edge int64 [n, ceil(E/64)]) bit rows."""
+    import torch
+    n, E = int(rows.shape[0]), int(edge_facets.shape[0])
+    We = (E + 63) // 64
+    ef = torch.empty((max(n, 1), scene.W), dtype=torch.int64, device=scene.device)
+    ee = torch.empty((max(n, 1), max(We, 1)), dtype=torch.int64, device=scene.device)
+    _check(load_library().ivm_edge_rows(
+        scene.handle, ctypes.byref(opts) if opts is not None else None, E, samples_per_edge, _ptr(edge_facets),
+        _ptr(edge_samples), n, _ptr(rows), _ptr(ef), _ptr(ee), _stream(stream)), "ivm_edge_rows")
+    return ef[:n], ee[:n, :We]
+
+
+def ivm_angular_ranges(scene: GpuScene, M, out=None, stream=None):
+    """Angular bouncing ranges of the set bits of M (row = reference facet,
+    column = aim facet): CSR offsets int64 [F + 1], columns int32 [nnz] and
+    ranges float64 [nnz, 4] = (omega_lo, omega_hi, mu_lo, mu_hi) in degrees,
+    as device tensors.  Without `out` the offsets are computed first and read
+    back (one synchronisation) to size the outputs; with out=(offsets, cols,
+    ranges) the call writes into them (cols.numel() is the capacity)."""
+    import torch
+    lib = load_library()
+    h, s = scene.handle, _stream(stream)
+    if out is None:
+        off = torch.empty((scene.F + 1,), dtype=torch.int64, device=scene.device)
+        _check(lib.ivm_angular_ranges(h, _ptr(M), _ptr(off), None, None, 0, s), "ivm_angular_ranges")
+        if stream is not None:
+            stream.synchronize()
+        nnz = int(off[-1].item())
+        cols = torch.empty((max(nnz, 1),), dtype=torch.int32, device=scene.device)
+        rng = torch.empty((max(nnz, 1), 4), dtype=torch.float64, device=scene.device)
+        _check(lib.ivm_angular_ranges(h, _ptr(M), _ptr(off), _ptr(cols), _ptr(rng), nnz, s), "ivm_angular_ranges")
+        return off, cols[:nnz], rng[:nnz]
+    off, cols, rng = out
+    _check(lib.ivm_angular_ranges(h, _ptr(M), _ptr(off), _ptr(cols), _ptr(rng), int(cols.numel()), s),
+           "ivm_angular_ranges")
+    return off, cols, rng
 
 
 def ivm_interface_relations(scene: GpuScene, M, stream=None):

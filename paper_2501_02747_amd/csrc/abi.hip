@@ -19,7 +19,7 @@ namespace {
 
 ivm_status status_from_bits(int bits) {
     if (bits & kStInvalid) return IVM_ERR_INVALID_ARGUMENT;
-    if (bits & kStGrid) return IVM_ERR_GRID;
+    if (bits & (kStGrid | kStAngleRange)) return IVM_ERR_GRID;
     if (bits & kStDegenerate) return IVM_ERR_DEGENERATE;
     return IVM_OK;
 }
@@ -320,6 +320,44 @@ ivm_status ivm_visibility_ranges_noalloc(const ivm_scene *scene, int32_t n_snap,
     if (ranges_scratch(&ws) != hipSuccess || !ws) return IVM_ERR_HIP;
     if (launch_ranges(scene->s.dev, n_snap, d_tx_vis, d_rx_vis, d_los, d_tx, d_rx, dt, ws, d_events, d_range_start,
                       d_range_tc, d_range_dist, d_n_ranges, d_tc_mean, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    return IVM_OK;
+}
+
+ivm_status ivm_angular_ranges(ivm_scene *scene, const uint64_t *d_M, int64_t *d_offsets, int32_t *d_cols,
+                              double *d_ranges, size_t cap, hipStream_t stream) {
+    if (!scene || !d_M || !d_offsets || (!d_cols) != (!d_ranges)) return IVM_ERR_INVALID_ARGUMENT;
+    const SceneDev &d = scene->s.dev;
+    if (d.F == 0) return launch_fill_u64((uint64_t *)d_offsets, 0ull, 1, stream) == hipSuccess ? IVM_OK : IVM_ERR_HIP;
+    if (launch_angle_offsets(d, d_M, d_offsets, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (!d_cols) return IVM_OK;
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, d_offsets + d.F, sizeof(total), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return IVM_ERR_HIP;
+    if ((size_t)total > cap) return IVM_ERR_CAPACITY;
+    if (total > 0 && launch_angles(d, d_M, d_offsets, d_cols, d_ranges, stream) != hipSuccess) return IVM_ERR_HIP;
+    int bits = 0;
+    if (hipMemcpyAsync(&bits, d.status, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return IVM_ERR_HIP;
+    return (bits & kStAngleRange) ? IVM_ERR_GRID : IVM_OK;
+}
+
+ivm_status ivm_edge_rows(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_edges, int32_t samples_per_edge,
+                         const int32_t *d_edge_facets, const float *d_edge_samples, int32_t n_rows,
+                         const int32_t *d_rows, uint64_t *d_edge_facet, uint64_t *d_edge_edge, hipStream_t stream) {
+    if (!scene || n_edges < 0 || n_rows < 0 || samples_per_edge < 1 || samples_per_edge > 64)
+        return IVM_ERR_INVALID_ARGUMENT;
+    if ((long long)n_edges * samples_per_edge > 0x7fffffffLL) return IVM_ERR_INVALID_ARGUMENT;
+    if (opts && (opts->order_mode < IVM_ORDER_PLAIN || opts->order_mode > IVM_ORDER_REVERSED))
+        return IVM_ERR_INVALID_ARGUMENT;
+    if (n_rows > 0 && (!d_rows || !d_edge_facet || (n_edges > 0 && (!d_edge_edge || !d_edge_facets ||
+                                                                     !d_edge_samples))))
+        return IVM_ERR_INVALID_ARGUMENT;
+    if (n_rows == 0) return IVM_OK;
+    const TraverseOpts o = make_opts(opts);
+    if (launch_edge_rows(scene->s, o, n_edges, samples_per_edge, d_edge_facets, d_edge_samples, n_rows, d_rows,
+                         d_edge_facet, d_edge_edge, stream) != hipSuccess)
         return IVM_ERR_HIP;
     return IVM_OK;
 }

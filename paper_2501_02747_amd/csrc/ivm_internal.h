@@ -43,6 +43,7 @@ constexpr int kFacetConvex = 1;       // the facet's triangles tile one convex p
 constexpr int kStGrid = 1;
 constexpr int kStDegenerate = 2;
 constexpr int kStInvalid = 4;
+constexpr int kStAngleRange = 8;  // an angular range's integer terms would leave 128 bits
 
 // Node of a binary BVH whose boxes live in the parent (one 64-byte record):
 //   a = (lo0.x, lo0.y, lo0.z, hi0.x), b = (hi0.y, hi0.z, lo1.x, lo1.y),
@@ -226,6 +227,11 @@ hipError_t launch_cull_scan(Scene &sc, uint64_t *M, ivm_stats *stats, hipStream_
 hipError_t launch_relations(const SceneDev &sc, const uint64_t *M, uint64_t *par, uint64_t *per, int8_t *cls,
                             hipStream_t s);
 size_t ranges_workspace_bytes(int N);
+// Angular bouncing ranges of the visible pairs: CSR row offsets (int64[F + 1]),
+// then the columns and four angles of every set bit of M in row-major order.
+hipError_t launch_angle_offsets(const SceneDev &sc, const uint64_t *M, int64_t *offsets, hipStream_t s);
+hipError_t launch_angles(const SceneDev &sc, const uint64_t *M, const int64_t *offsets, int32_t *cols,
+                         double *ranges, hipStream_t s);
 // Largest trajectory of the allocation-free ranges call, and the address of its
 // scratch on the current device (looked up once per device).
 constexpr int kRangesNoAllocMaxSnap = 32768;
@@ -249,6 +255,9 @@ hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total
 hipError_t launch_edges(Scene &scn, const TraverseOpts &o, int N, int E, int s, const int *efac, const float *esmp,
                         const float *tx, const float *rx, uint64_t *txe, uint64_t *rxe, int64_t *counts,
                         hipStream_t st);
+// Edge rows of the matrix (edge to facet and edge to edge) for the listed edges.
+hipError_t launch_edge_rows(Scene &scn, const TraverseOpts &o, int E, int s, const int *efac, const float *esmp,
+                            int n_rows, const int *rows, uint64_t *ef, uint64_t *ee, hipStream_t st);
 hipError_t launch_los(Scene &sc, const TraverseOpts &o, int N, const float *tx, const float *rx, uint8_t *los,
                       hipStream_t s);
 PairJob make_pair_job(Scene &sc, uint64_t *M, bool learned);

@@ -189,16 +189,33 @@ struct Cnt {
     unsigned boxes = 0, tests = 0, rechecks = 0, fallbacks = 0, traversed = 0, solid_segs = 0, solid_planes = 0;
 };
 
-__device__ inline int test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
-                                 float eps6, bool f64, Cnt &c) {
+// Facets whose triangles a segment test skips: two (a pair's facets, an edge's
+// facets) or four (the facets of two edges, or of an edge and a facet).
+struct Ex2 {
+    int a, b;
+    __device__ bool operator()(int f) const { return f == a || f == b; }
+};
+struct Ex4 {
+    int a, b, c, d;
+    __device__ bool operator()(int f) const { return f == a || f == b || f == c || f == d; }
+};
+
+template <class Ex>
+__device__ inline int test_range_ex(const SceneDev &sc, const Seg &s, int first, int count, Ex ex, float eps6,
+                                    bool f64, Cnt &c) {
     for (int r = first; r < first + count; ++r) {
         const float4 A = sc.tri[3 * r];
         const int f = __float_as_int(A.w);
-        if (f == exA || f == exB) continue;
+        if (ex(f)) continue;
         ++c.tests;
         if (tri_hit(s, A, sc.tri[3 * r + 1], sc.tri[3 * r + 2], eps6, f64, c.rechecks)) return r;
     }
     return -1;
+}
+
+__device__ inline int test_range(const SceneDev &sc, const Seg &s, int first, int count, int exA, int exB,
+                                 float eps6, bool f64, Cnt &c) {
+    return test_range_ex(sc, s, first, count, Ex2{exA, exB}, eps6, f64, c);
 }
 
 constexpr int kNone = 0x7fffffff;
@@ -208,9 +225,9 @@ constexpr int kNone = 0x7fffffff;
 // visit (LDS or constant memory); `stk` is this lane's LDS stack with a stride of
 // one wave.  When the stack is full the far child's whole subtree is scanned
 // linearly (its triangles are a contiguous sorted range), so no node is dropped.
-template <typename OrderPtr>
-__device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr order, int n_order, int *stk,
-                       int depth, float eps6, bool f64, Cnt &c) {
+template <typename OrderPtr, class Ex>
+__device__ int any_hit_ex(const SceneDev &sc, Seg s, Ex ex, OrderPtr order, int n_order, int *stk, int depth,
+                          float eps6, bool f64, Cnt &c) {
     with_inverse(s);
     int r = 0, sp = 0;
     int ref = kNone;
@@ -256,7 +273,7 @@ __device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr ord
                         first = rg.z;
                         count = rg.w - rg.z + 1;
                     }
-                    const int h = test_range(sc, s, first, count, exA, exB, eps6, f64, c);
+                    const int h = test_range_ex(sc, s, first, count, ex, eps6, f64, c);
                     if (h >= 0) return h;
                 }
                 ref = nearc;
@@ -268,11 +285,17 @@ __device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr ord
                 ref = kNone;
             }
         } else {
-            const int h = test_range(sc, s, leaf_first(ref), leaf_count(ref), exA, exB, eps6, f64, c);
+            const int h = test_range_ex(sc, s, leaf_first(ref), leaf_count(ref), ex, eps6, f64, c);
             if (h >= 0) return h;
             ref = kNone;
         }
     }
+}
+
+template <typename OrderPtr>
+__device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr order, int n_order, int *stk,
+                       int depth, float eps6, bool f64, Cnt &c) {
+    return any_hit_ex(sc, s, Ex2{exA, exB}, order, n_order, stk, depth, eps6, f64, c);
 }
 
 // Wave-synchronous any-hit over one batch: every lane traverses its own
@@ -2482,6 +2505,111 @@ __global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int
     }
 }
 
+// Edge rows of the matrix: edges are visibility nodes beside faces (Sections I
+// and II-A), and the face seen for diffraction is the face seen for reflection
+// (Section III-B).  A node is a facet (its samples; side facets {f}) or an edge
+// (its samples; side facets {fa, fb}, fb = -1 for an edge of one facet).  Edge e
+// and node v see each other when some sample p of e and q of v have q strictly
+// in front of fa or fb, p strictly in front of one of v's side facets, and the
+// open segment (p, q) meets no triangle outside the side facets of both.
+//
+// One lane per (row edge, target node, edge sample): G consecutive lanes (G = s
+// rounded up to a power of two) hold one edge-target pair, so a wave covers
+// 64 / G targets of one row.  A lane walks the target's samples in order,
+// tests the triangle that blocked its previous segment before a traversal, and
+// stops at the first clear segment or when another lane of its group has found
+// one (a flag in LDS); a ballot over the group sets the target's bit.
+__global__ __launch_bounds__(kBlock) void k_edge_rows(SceneDev sc, int E, int s, int G, const int *efac,
+                                                      const float *esmp, int n_rows, const int *rows, uint64_t *ef,
+                                                      uint64_t *ee, TraverseOpts o) {
+    __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
+    __shared__ int sDone[kWavesPerBlock][kWave];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int per_wave = kWave / G, n_targets = sc.F + E;
+    const long long nb = (n_targets + per_wave - 1) / per_wave;
+    const long long qw = (long long)blockIdx.x * kWavesPerBlock + wv;
+    if (qw >= (long long)n_rows * nb) return;  // (wave-uniform)
+    const int k = (int)(qw / nb), grp = lane / G, a = lane % G;
+    const int target = (int)(qw % nb) * per_wave + grp;
+    const int e = rows[k];
+    volatile int *done = &sDone[wv][0];
+    done[lane] = 0;
+    bool clear = false;
+    const bool row_ok = e >= 0 && e < E;
+    if (row_ok && target < n_targets && a < s && target != sc.F + e) {
+        const int fa = efac[2 * e], fb = efac[2 * e + 1];
+        const float *p = esmp + 3 * ((size_t)e * s + a);
+        int ta, tb;  // the target's side facets
+        int q0, nq;  // its samples: facet samples [q0, q0 + nq) or edge samples of edge q0
+        const bool is_edge = target >= sc.F;
+        if (is_edge) {
+            ta = efac[2 * (target - sc.F)];
+            tb = efac[2 * (target - sc.F) + 1];
+            q0 = target - sc.F;
+            nq = s;
+        } else {
+            ta = target;
+            tb = -1;
+            q0 = sc.soff[target];
+            nq = sc.soff[target + 1] - q0;
+        }
+        const bool sides_ok = fa >= 0 && fa < sc.F && fb >= -1 && fb < sc.F && ta >= 0 && ta < sc.F && tb >= -1 &&
+                              tb < sc.F;
+        const bool p_front = sides_ok && (orient(sc.fplane + 6 * (size_t)ta, p[0], p[1], p[2]) > 0.0 ||
+                                          (tb >= 0 && orient(sc.fplane + 6 * (size_t)tb, p[0], p[1], p[2]) > 0.0));
+        if (p_front) {
+            const Ex4 ex{fa, fb, ta, tb};
+            int last = -1;
+            Cnt c;
+            for (int b = 0; b < nq && !done[grp]; ++b) {
+                float qx, qy, qz;
+                if (is_edge) {
+                    const float *q = esmp + 3 * ((size_t)q0 * s + b);
+                    qx = q[0];
+                    qy = q[1];
+                    qz = q[2];
+                } else {
+                    const float4 q = sc.smp[q0 + b];
+                    qx = q.x;
+                    qy = q.y;
+                    qz = q.z;
+                }
+                if (!(orient(sc.fplane + 6 * (size_t)fa, qx, qy, qz) > 0.0 ||
+                      (fb >= 0 && orient(sc.fplane + 6 * (size_t)fb, qx, qy, qz) > 0.0)))
+                    continue;
+                const Seg sg = make_seg(p[0], p[1], p[2], qx, qy, qz);
+                if (last >= 0 && tri_hit(sg, sc.tri[3 * last], sc.tri[3 * last + 1], sc.tri[3 * last + 2], o.eps6,
+                                         o.fp64_only != 0, c.rechecks))
+                    continue;
+                const int h = any_hit_ex(sc, sg, ex, kIdentOrder, kTreelets, &sStack[wv][lane], o.stack_depth, o.eps6,
+                                         o.fp64_only != 0, c);
+                if (h < 0) {
+                    clear = true;
+                    done[grp] = 1;
+                    break;
+                }
+                last = h;
+            }
+        }
+    }
+    const unsigned long long bal = __ballot(clear);
+    if (a == 0 && row_ok && target < n_targets) {
+        const unsigned long long gm = (G == kWave ? ~0ull : ((1ull << G) - 1ull)) << lane;
+        if (bal & gm) {
+            if (target < sc.F)
+                atomicOr((unsigned long long *)(ef + (size_t)k * sc.W + (target >> 6)), 1ull << (target & 63));
+            else
+                atomicOr((unsigned long long *)(ee + (size_t)k * ((E + 63) / 64) + ((target - sc.F) >> 6)),
+                         1ull << ((target - sc.F) & 63));
+        }
+    }
+}
+
+__global__ void k_check_rows(int E, int n_rows, const int *rows, int *status) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < n_rows && !(rows[id] >= 0 && rows[id] < E)) atomicOr(status, kStInvalid);
+}
+
 // Edge inputs: facet ids in range and distinct, every sample on the sample grid
 // and inside the scene's box (so the exactness budget of the scene covers it).
 __global__ void k_check_edges(SceneDev sc, int E, int s, const int *efac, const float *esmp) {
@@ -2543,6 +2671,28 @@ hipError_t launch_edges(Scene &scn, const TraverseOpts &o, int N, int E, int s, 
             return e;
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_rows(Scene &scn, const TraverseOpts &o, int E, int s, const int *efac, const float *esmp,
+                            int n_rows, const int *rows, uint64_t *ef, uint64_t *ee, hipStream_t st) {
+    const SceneDev &sc = scn.dev;
+    const int We = (E + 63) / 64;
+    hipError_t e;
+    if (n_rows <= 0) return hipSuccess;
+    if ((e = launch_fill_u64(ef, 0ull, (size_t)n_rows * sc.W, st)) != hipSuccess) return e;
+    if (We > 0 && (e = launch_fill_u64(ee, 0ull, (size_t)n_rows * We, st)) != hipSuccess) return e;
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_rows, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, st, E, n_rows, rows,
+                       sc.status);
+    const long long items = (long long)E * s;
+    hipLaunchKernelGGL(k_check_edges, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, sc, E, s, efac, esmp);
+    int G = 1;
+    while (G < s) G <<= 1;
+    const long long per_wave = kWave / G;
+    const long long waves = (long long)n_rows * ((sc.F + E + per_wave - 1) / per_wave);
+    hipLaunchKernelGGL(k_edge_rows, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)), dim3(kBlock), 0,
+                       st, sc, E, s, G, efac, esmp, n_rows, rows, ef, ee, o);
     return hipGetLastError();
 }
 

@@ -78,6 +78,11 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.ivm_edge_visibility(None, None, 0, 4, None, None, 0, None, None, None, None, None, None) \
         == ivm.IVM_ERR_INVALID_ARGUMENT
     assert lib.ivm_interface_relations(None, None, None, None, None, None) == ivm.IVM_ERR_INVALID_ARGUMENT
+    assert lib.ivm_angular_ranges(None, None, None, None, None, 0, None) == ivm.IVM_ERR_INVALID_ARGUMENT
+    assert lib.ivm_edge_rows(None, None, 0, 4, None, None, 0, None, None, None, None) == ivm.IVM_ERR_INVALID_ARGUMENT
+    for s in (0, 65):   # samples per edge beyond 1..64
+        assert lib.ivm_edge_rows(None, None, 4, s, None, None, 1, None, None, None, None) \
+            == ivm.IVM_ERR_INVALID_ARGUMENT
     sz = ctypes.c_size_t(0)
     assert lib.ivm_visibility_ranges_workspace_size(0, ctypes.byref(sz)) == ivm.IVM_ERR_INVALID_ARGUMENT
     assert lib.ivm_visibility_ranges_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 1000 * 52
