@@ -117,6 +117,8 @@ def _parse():
                     help="ablation: every admissible segment searched on its own (no probes, caches or certificates)")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--stack", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the launch knobs on the workload before timing (always done for the nested urban grid)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
@@ -256,7 +258,7 @@ def verify(ivm, scene, M, tv, rv, los, counts):
 def run_batched(args, ivm, torch, sg):
     """The batched workload: 64 config-1-style scenes of 500-5000 facets in one
     graph-captured run; launch parameters from the autotuner on a calibration scene."""
-    from paper_2501_02747_amd.autotune import autotune_matrix
+    from paper_2501_02747_amd.autotune import KNOBS, autotune_matrix, opts_from
 
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -269,11 +271,10 @@ def run_batched(args, ivm, torch, sg):
     txs = [torch.as_tensor(s.tx).cuda() for s in scenes]
     rxs = [torch.as_tensor(s.rx).cuda() for s in scenes]
     calib = int(np.argsort(F)[len(F) // 2])
-    tune = autotune_matrix(gs[calib], repeats=1, cache_path=None,
-                           grid=[(w, d) for w in (8, 16, 24, 32) for d in (16, 24)])
-    progress(f"autotuned on scene {calib} (F={F[calib]}): waves/CU {tune['waves_per_cu']}, "
-             f"stack {tune['stack_depth']}")
-    opts = ivm.make_opts(waves_per_cu=tune["waves_per_cu"], stack_depth=tune["stack_depth"])
+    tune = autotune_matrix(gs[calib], repeats=1, cache_path=None)
+    progress(f"autotuned on scene {calib} (F={F[calib]}) over {tune['points']} points: "
+             + ", ".join(f"{k} {tune[k]}" for k in KNOBS) + f" ({tune['default_ms']:.2f} -> {tune['ms']:.2f} ms)")
+    opts = opts_from(tune)
     st = ivm.new_stats()
     batch = ivm.Batch(gs, txs, rxs, opts, stats=st)
     stream = torch.cuda.Stream()
@@ -309,8 +310,11 @@ def run_batched(args, ivm, torch, sg):
                    "pairs": n_pairs, "parallelism": "single GPU"},
         "txrx_ms_per_snapshot": ms / float(N.sum()),
         "note": "queries/s and ms/snapshot are both whole-graph time (matrices, tables and candidates together)",
-        "autotune": {k: tune[k] for k in ("waves_per_cu", "stack_depth", "ms")},
+        "autotune": dict({k: tune[k] for k in KNOBS}, ms=tune["ms"], default_ms=tune["default_ms"],
+                         points=tune["points"], calibration_scene=calib),
         "stats_per_run": sd,
+        "autotune": (dict({k: tune[k] for k in KNOBS}, ms=tune["ms"], default_ms=tune["default_ms"],
+                          points=tune["points"]) if tune else "not run (defaults; --autotune tunes this workload)"),
         "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
                      "frac": ach / VALU_PEAK_TOPS, "traffic": None, "kernel": "whole graph (k_probe_pairs + k_pairs + k_points)"},
     }
@@ -359,7 +363,7 @@ def main():
         out["urban_grid_c2"] = {k: nested[k] for k in (
             "value", "unit", "ms_per_step", "txrx_ms_per_snapshot", "phase_ms_median", "kernel_ms", "config",
             "roofline", "roofline_points", "compare_order", "verified", "ranges", "relations", "candidates_order4",
-            "edges") if k in nested}
+            "edges", "autotune", "angles", "edge_rows", "paths") if k in nested}
     print(json.dumps(out), flush=True)
 
 
@@ -393,10 +397,20 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
     counts = torch.empty((N, 3), dtype=torch.int64, device="cuda")
     st_m, st_p = ivm.new_stats(), ivm.new_stats()
     t_pairs, t_points = ivm.KernelTimer(), ivm.KernelTimer()
-    om = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu,
-                       stack_depth=args.stack, timing=t_pairs, exhaustive=args.exhaustive)
-    op = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu,
-                       stack_depth=args.stack, timing=t_points, exhaustive=args.exhaustive)
+    # launch knobs: the autotuner's (nested urban-grid run, or --autotune), else the command line's
+    from paper_2501_02747_amd.autotune import KNOBS, autotune_matrix
+    tune = None
+    knob = {"waves_per_cu": args.waves_per_cu, "stack_depth": args.stack}
+    if (args.autotune or not headline) and not args.exhaustive:
+        tune = autotune_matrix(g, repeats=3 if F <= 4000 else 1, cache_path=None)
+        knob = {k: tune[k] for k in KNOBS}
+        print(f"[bench] {config}: autotuned over {tune['points']} points: "
+              + ", ".join(f"{k} {tune[k]}" for k in KNOBS) + f" ({tune['default_ms']:.2f} -> {tune['ms']:.2f} ms)",
+              file=sys.stderr, flush=True)
+    om = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, timing=t_pairs, exhaustive=args.exhaustive,
+                       **knob)
+    op = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, timing=t_points, exhaustive=args.exhaustive,
+                       **knob)
 
     def step(rec):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -500,8 +514,7 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
     if have_model and not args.no_compare:
         other = "plain" if args.order == "learned" else "learned"
         oo = ivm.make_opts(order_mode=ivm.IVM_ORDER_LEARNED if other == "learned" else ivm.IVM_ORDER_PLAIN,
-                           fp64_only=args.fp64_only, waves_per_cu=args.waves_per_cu, stack_depth=args.stack,
-                           timing=t_pairs)
+                           fp64_only=args.fp64_only, timing=t_pairs, **knob)
         M2 = torch.empty_like(M)
         st_o = ivm.new_stats()
         times = []
@@ -567,6 +580,47 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
     out["relations"] = {"gpu_ms": statistics.median(times),
                         "par_pairs": int(ivm.unpack_bits(par, F).sum()) // 2,
                         "per_pairs": int(ivm.unpack_bits(per, F).sum()) // 2}
+    # angular bouncing ranges of every visible pair (Section II-B, eq. 1-2); the call
+    # sizes its output with one synchronisation, so it is timed end to end
+    times = []
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        aoff, acols, arng = ivm.ivm_angular_ranges(g, M)
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            times.append(1e3 * (time.perf_counter() - t0))
+    out["angles"] = {"ms": statistics.median(times), "pairs": int(acols.numel()),
+                     "note": "wall time of the whole call (row counts, one read-back, angles)"}
+    if not args.no_verify:
+        import oracle
+        rows_o, Mo_rows = None, None
+        cache = os.path.join(ROOT, "tests", "golden", "cache", f"{scene.name}_seed{scene.seed}.npz")
+        rcache = os.path.join(ROOT, "tests", "golden", "cache", f"{scene.name}_seed{scene.seed}_rows.npz")
+        if os.path.exists(cache) and N == 1000:
+            z = np.load(cache, allow_pickle=False)
+            rows_o = np.sort(np.random.default_rng(3).choice(F, 16, replace=False))
+            Mo_rows = np.unpackbits(z["M"], axis=1)[rows_o, :F].astype(bool)
+        elif os.path.exists(rcache):
+            z = np.load(rcache, allow_pickle=False)
+            rows_o = z["rows"][:16]
+            Mo_rows = np.unpackbits(z["M"], axis=1)[:16, :F].astype(bool)
+        if rows_o is not None:
+            gm_rows = ivm.unpack_bits(M, F)[rows_o]
+            Mo = np.zeros((F, F), bool)
+            Mo[rows_o] = Mo_rows
+            t0 = time.perf_counter()
+            ao = oracle.angular_ranges(scene, Mo, rows=rows_o)
+            out["angles"]["oracle_ms"] = 1e3 * (time.perf_counter() - t0)
+            ok = bool((gm_rows == Mo_rows).all())
+            go, gc, gr = aoff.cpu().numpy(), acols.cpu().numpy(), arng.cpu().numpy()
+            for r in rows_o:
+                a, b, oa, ob = go[r], go[r + 1], ao["offsets"][r], ao["offsets"][r + 1]
+                ok &= bool((gc[a:b] == ao["cols"][oa:ob]).all() and
+                           np.allclose(gr[a:b], ao["ranges"][oa:ob], rtol=1e-14, atol=1e-12))
+            out["angles"]["oracle_sample"] = f"{len(rows_o)} whole rows of the oracle's matrix"
+            out["angles"]["matches_oracle"] = ok
+    progress(f"angular ranges: {out['angles']['ms']:.3f} ms, {out['angles']['pairs']} pairs")
     # image-tree candidate counts of orders up to 4 (the orders timed in Section IV-C)
     # over every snapshot of the table, outside the step
     times = []
@@ -595,6 +649,63 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
             out["candidates_order4"]["oracle_sample"] = f"every 10th snapshot ({len(pick)})"
             out["candidates_order4"]["matches_oracle"] = bool((c4np[pick] == co4).all())
     progress(f"candidates up to order 4: {statistics.median(times):.3f} ms")
+    # exact image-method validation of the candidate lists (orders 1-2) of the
+    # first 100 snapshots (Section III-A; the walks the pruned tree keeps)
+    nv = min(N, 100)
+    _, voff, vpaths = ivm.ivm_image_tree_candidates(g, M, tv[:nv], rv[:nv], los[:nv], 2, lists=True)
+    times = []
+    for k in range(min(args.warmup, 1) + min(args.steps, 3)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vst = ivm.new_stats()
+        valid, vcounts = ivm.ivm_validate_paths(g, tx[:nv], rx[:nv], 2, voff, vpaths, stats=vst)
+        torch.cuda.synchronize()
+        if k >= min(args.warmup, 1):
+            times.append(1e3 * (time.perf_counter() - t0))
+    vc = vcounts.cpu().numpy()
+    vs = ivm.stats_dict(vst)
+    out["paths"] = {"ms": statistics.median(times), "snapshots": nv, "walks": int(counts[:nv, 1:3].sum().item()),
+                    "valid_per_order": [int(x) for x in vc.sum(0)], "leg_tests": vs["tri_tests"],
+                    "exact_tests": vs["rechecks"],
+                    "note": "wall time of the whole call (it synchronises once to report undecided walks)"}
+    cache = os.path.join(ROOT, "tests", "golden", "cache", f"{scene.name}_seed{scene.seed}.npz")
+    if not args.no_verify and os.path.exists(cache) and N == 1000:
+        import oracle
+        z = np.load(cache, allow_pickle=False)
+        pick = np.array([0, 50, 99])
+        Mo = np.unpackbits(z["M"], axis=1)[:, :F].astype(bool)
+        tvo = np.unpackbits(z["tx_vis"], axis=1)[pick, :F].astype(bool)
+        rvo = np.unpackbits(z["rx_vis"], axis=1)[pick, :F].astype(bool)
+        _, olists = oracle.candidates_enum(Mo, tvo, rvo, z["los"][pick], 2)
+        rng = np.random.default_rng(6)
+        walks = [(a, w) for a, per in enumerate(olists) for k in (1, 2) for w in per[k - 1]]
+        sel = [walks[q] for q in rng.choice(len(walks), min(12, len(walks)), replace=False)]
+        # one snapshot entry per selected walk: list (q, order 1) then (q, order 2)
+        flat_all, offs, txs, rxs, first = [], [], [], [], []
+        for a, w in sel:
+            txs.append(scene.tx[pick[a]])
+            rxs.append(scene.rx[pick[a]])
+            for k in (1, 2):
+                offs.append(len(flat_all))
+                if len(w) == k:
+                    first.append(len(flat_all))
+                    flat_all.extend(w)
+        offs.append(len(flat_all))
+        offs = np.asarray(offs, np.int64)
+        gv, _ = ivm.ivm_validate_paths(g, torch.as_tensor(np.array(txs, np.float32)).cuda(),
+                                       torch.as_tensor(np.array(rxs, np.float32)).cuda(), 2,
+                                       torch.as_tensor(offs).cuda(), torch.as_tensor(np.array(flat_all, np.int32)).cuda())
+        gv = gv.cpu().numpy()
+        ex = oracle._ExactImage(scene)
+        t0 = time.perf_counter()
+        ok = True
+        for q, (a, w) in enumerate(sel):
+            exp = bool(oracle.validate_paths_exact(scene, scene.tx[pick[a]], scene.rx[pick[a]], [w], ex=ex)[0])
+            ok &= bool(gv[first[q]]) == exp
+        out["paths"]["oracle_ms_per_walk"] = 1e3 * (time.perf_counter() - t0) / len(sel)
+        out["paths"]["oracle_sample"] = f"{len(sel)} walks drawn from the oracle's own candidate lists"
+        out["paths"]["matches_oracle"] = ok
+    progress(f"path validation: {out['paths']['ms']:.2f} ms for the walks of {nv} snapshots")
     # building edges seen from Tx and Rx and the first-order diffraction candidates
     # Tx -> edge -> Rx (Section III-B), over the first 1000 snapshots at most
     E = int(scene.edge_facets.shape[0])
@@ -630,6 +741,32 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
             out["edges"]["matches_oracle"] = bool((gte[pick] == ot).all() and (gre[pick] == orr).all() and (
                 dc.cpu().numpy()[pick] == oracle.diffraction_counts(ot, orr)).all())
         progress(f"edge visibility: {statistics.median(times):.3f} ms for {ne} snapshots")
+    # edge rows of the matrix (edge to facet, edge to edge) for 64 seeded edges
+    if E:
+        rows_e = np.sort(np.random.default_rng(4).choice(E, min(E, 64), replace=False)).astype(np.int32)
+        drows = torch.as_tensor(rows_e).cuda()
+        times = []
+        for k in range(args.warmup + args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            erf, ere = ivm.ivm_edge_rows(g, ef, es, scene.samples_per_edge, drows)
+            e1.record()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(e0.elapsed_time(e1))
+        gef, gee = ivm.unpack_bits(erf, F), ivm.unpack_bits(ere, E)
+        out["edge_rows"] = {"gpu_ms": statistics.median(times), "rows": len(rows_e), "edges": E,
+                            "targets_per_row": F + E, "edge_facet_visible": int(gef.sum()),
+                            "edge_edge_visible": int(gee.sum())}
+        if not args.no_verify:
+            import oracle
+            t0 = time.perf_counter()
+            oef, oee = oracle.edge_rows(oracle.Oracle(scene), scene.edge_facets, scene.edge_samples,
+                                        scene.samples_per_edge, rows=rows_e[:2])
+            out["edge_rows"]["oracle_ms_per_row"] = 1e3 * (time.perf_counter() - t0) / 2
+            out["edge_rows"]["oracle_sample"] = "the first 2 of the 64 rows"
+            out["edge_rows"]["matches_oracle"] = bool((gef[:2] == oef).all() and (gee[:2] == oee).all())
+        progress(f"edge rows: {statistics.median(times):.3f} ms for {len(rows_e)} rows")
     if not args.no_verify:
         progress("verifying against the oracle")
         counts_now = counts

@@ -78,7 +78,10 @@ typedef int32_t ivm_status;
  *   tri_facet       int32[n_triangles], facet id in [0, n_facets), non-decreasing:
  *                   the triangles of one facet are contiguous.  The winding of a
  *                   facet's first triangle defines its visible side.
- *   sample_offsets  int32[n_facets + 1], CSR offsets into samples.
+ *   sample_offsets  int32[n_facets + 1], CSR offsets into samples; at most
+ *                   64 samples per facet (IVM_MAX_SAMPLES_PER_FACET): a facet
+ *                   with more is reported by ivm_scene_status as
+ *                   IVM_ERR_INVALID_ARGUMENT.
  *   samples         float[n_samples][3], every coordinate a multiple of
  *                   2^-grid_sample_log2 (grid_sample_log2 >= grid_vertex_log2).
  * The scene is accepted only if every predicate above is exact in FP64:
@@ -183,9 +186,16 @@ typedef struct ivm_matrix_opts {
                                   call records on its stream immediately before and
                                   after its traversal kernels (the matrix: both probe
                                   rounds and the pair kernel; the table: the point kernel) */
+    int32_t tile_cap;       /* near-field tile capacity in triangles, 1..64; 0 = 64 */
+    int32_t tile_treelets;  /* gather a near-field tile only for segment bundles whose box
+                               meets at most this many treelets, 1..32; 0 = 6 */
+    int32_t pair_chunk;     /* pair-to-wave mapping: consecutive undecided pairs a wave takes
+                               from the queue at a time, 1..256; 0 = 4, or 32 when there are
+                               more than 2048 pairs per wave */
 } ivm_matrix_opts;
 
 #define IVM_MAX_STACK 24
+#define IVM_MAX_SAMPLES_PER_FACET 64
 
 const char *ivm_status_string(ivm_status s);
 
@@ -254,6 +264,35 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
                                      const uint8_t *d_los, int32_t max_order, int64_t *d_counts,
                                      int64_t *d_offsets, int32_t *d_paths, size_t paths_cap,
                                      hipStream_t stream);
+
+/* Exact image-method validation of image-tree candidates (Section III-A: the
+ * image method; Section III-B: the image tree the inter-visibility table
+ * prunes; Section IV-B: the pruned tree yields the same valid rays as brute
+ * force).  The lists are those of ivm_image_tree_candidates (d_offsets
+ * int64[n_snap * max_order + 1] in int32 elements, snapshot-major, order-minor;
+ * d_paths int32[n_elems] of k-tuples), any lists of that layout are accepted.
+ * Walk f1 -> ... -> fk of snapshot n is valid iff, with T = d_tx[n], R =
+ * d_rx[n] and I_1..I_k the images of T mirrored successively in the planes of
+ * f1..fk (plane of a facet: its first triangle): tracing back from R (target
+ * R, then each reflection point), the target is strictly in front of f_m's
+ * plane and I_m strictly behind it, the point where segment (target, I_m)
+ * meets the plane lies in the closed facet f_m, and every leg T -> P_1 -> ...
+ * -> P_k -> R misses (open segment, closed triangles) every triangle outside
+ * the facets at its two ends.  Decisions are exact: rational points are
+ * integer homogeneous vectors of 512 bits, segment tests run in FP64 with an
+ * error bound and fall back to exact integers within it.
+ * d_valid uint8[n_elems]: every element of a walk's k-tuple receives its
+ * verdict, 1 valid, 0 not, 2 undecided (an integer left 512 bits: the call then
+ * returns IVM_ERR_GRID).  d_valid_counts (int64[n_snap][max_order], may be NULL)
+ * receives the valid walks per snapshot and order.  d_stats (may be NULL):
+ * tri_tests += segment/triangle tests of the legs, rechecks += those decided in
+ * exact integers.  Positions must be on the sample grid (else IVM_ERR_GRID).
+ * The call synchronises the stream once at the end to report these errors.
+ * Errors: IVM_ERR_INVALID_ARGUMENT (also facet ids out of range or repeated
+ * consecutively in a walk), IVM_ERR_GRID, IVM_ERR_HIP. */
+ivm_status ivm_validate_paths(ivm_scene *scene, int32_t n_snap, const float *d_tx, const float *d_rx,
+                              int32_t max_order, const int64_t *d_offsets, const int32_t *d_paths, int64_t n_elems,
+                              uint8_t *d_valid, int64_t *d_valid_counts, ivm_stats *d_stats, hipStream_t stream);
 
 /* Interface relations of the visible facet pairs (Section II-B, Table I: the
  * reference face and the aim face are parallel, PAR, or perpendicular, PER).

@@ -38,7 +38,7 @@ EXPORTED = [
     "ivm_scene_info", "ivm_destroy_scene", "ivm_intervisibility_matrix",
     "ivm_txrx_visibility_table", "ivm_image_tree_candidates", "ivm_triangle_groups", "ivm_visibility_ranges",
     "ivm_visibility_ranges_workspace_size", "ivm_visibility_ranges_noalloc", "ivm_interface_relations",
-    "ivm_edge_visibility", "ivm_edge_rows", "ivm_angular_ranges",
+    "ivm_edge_visibility", "ivm_edge_rows", "ivm_angular_ranges", "ivm_validate_paths",
     "ivm_model_workspace_size", "ivm_model_create", "ivm_model_destroy", "ivm_model_set_params",
     "ivm_model_get_params", "ivm_model_forward", "ivm_model_loss_grad", "ivm_model_train_step",
     "ivm_pair_features", "ivm_pair_occluder_labels", "ivm_scene_set_model",
@@ -85,6 +85,7 @@ class ivm_matrix_opts(ctypes.Structure):
         ("eps", ctypes.c_float), ("no_tile", ctypes.c_int32),
         ("exhaustive", ctypes.c_int32),
         ("timing_events", ctypes.c_void_p),
+        ("tile_cap", ctypes.c_int32), ("tile_treelets", ctypes.c_int32), ("pair_chunk", ctypes.c_int32),
     ]
 
 
@@ -134,6 +135,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ivm_interface_relations.argtypes = [P, P, P, P, P, P]
     lib.ivm_edge_rows.restype = i32
     lib.ivm_edge_rows.argtypes = [P, ctypes.POINTER(ivm_matrix_opts), i32, i32, P, P, i32, P, P, P, P]
+    lib.ivm_validate_paths.restype = i32
+    lib.ivm_validate_paths.argtypes = [P, i32, P, P, i32, P, P, ctypes.c_int64, P, P, P, P]
     lib.ivm_angular_ranges.restype = i32
     lib.ivm_angular_ranges.argtypes = [P, P, P, P, P, sz, P]
     lib.ivm_edge_visibility.restype = i32
@@ -200,13 +203,15 @@ def _ptr(t) -> Optional[int]:
 
 def make_opts(order_mode: int = IVM_ORDER_PLAIN, fp64_only: bool = False, stack_depth: int = 0,
               waves_per_cu: int = 0, eps: float = 0.0, timing: Optional["KernelTimer"] = None,
-              no_tile: bool = False, exhaustive: bool = False) -> ivm_matrix_opts:
+              no_tile: bool = False, exhaustive: bool = False, tile_cap: int = 0, tile_treelets: int = 0,
+              pair_chunk: int = 0) -> ivm_matrix_opts:
     o = ivm_matrix_opts()
     o.order_mode, o.fp64_only, o.stack_depth = order_mode, int(fp64_only), stack_depth
     o.no_tile = int(no_tile)
     o.exhaustive = int(exhaustive)
     o.waves_per_cu, o.eps = waves_per_cu, eps
     o.timing_events = timing.array_ptr if timing is not None else None
+    o.tile_cap, o.tile_treelets, o.pair_chunk = tile_cap, tile_treelets, pair_chunk
     return o
 
 
@@ -478,6 +483,22 @@ def ivm_angular_ranges(scene: GpuScene, M, out=None, stream=None):
     _check(lib.ivm_angular_ranges(h, _ptr(M), _ptr(off), _ptr(cols), _ptr(rng), int(cols.numel()), s),
            "ivm_angular_ranges")
     return off, cols, rng
+
+
+def ivm_validate_paths(scene: GpuScene, tx, rx, max_order: int, offsets, paths, stats=None, stream=None):
+    """Exact image-method verdicts for candidate lists (offsets int64 [N*K+1] in
+    int32 elements, paths int32, as ivm_image_tree_candidates writes them):
+    valid uint8 [len(paths)] (each element of a walk's k-tuple carries the walk's
+    verdict: 1 valid, 0 not) and the valid walks per snapshot and order int64 [N, K]."""
+    import torch
+    N = int(tx.shape[0])
+    n_elems = int(paths.numel())
+    valid = torch.empty((max(n_elems, 1),), dtype=torch.uint8, device=scene.device)
+    counts = torch.empty((max(N, 1), max_order), dtype=torch.int64, device=scene.device)
+    _check(load_library().ivm_validate_paths(scene.handle, N, _ptr(tx), _ptr(rx), max_order, _ptr(offsets),
+                                             _ptr(paths), n_elems, _ptr(valid), _ptr(counts), _ptr(stats),
+                                             _stream(stream)), "ivm_validate_paths")
+    return valid[:n_elems], counts[:N]
 
 
 def ivm_interface_relations(scene: GpuScene, M, stream=None):

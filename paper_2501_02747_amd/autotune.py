@@ -1,24 +1,46 @@
 """Launch-parameter search for the traversal kernels.
 
-A grid search over the persistent grid size (waves per CU) and the traversal
-stack depth, timed on a calibration scene with HIP events; every point must
-return the same matrix bits as the first (the parameters never change a
-result).  Results are cached as JSON keyed by GPU architecture and a size
-bucket of the scene, so later runs on similar scenes reuse them.
+Knobs of the matrix call (none of them changes a result bit):
+  waves_per_cu   persistent grid size (waves per compute unit)
+  stack_depth    traversal stack entries per lane (overflow scans a subtree)
+  tile_cap       near-field tile capacity (triangles gathered for a bundle)
+  tile_treelets  largest number of treelets a bundle box may meet for a tile
+  pair_chunk     pair-to-wave mapping: consecutive undecided pairs a wave takes
+                 from the queue at a time (0 = chosen from the load)
+
+The search is coordinate descent: starting from the defaults, each knob in
+turn is swept over its values with the others fixed, and the fastest value is
+kept; the sweep repeats until a pass changes nothing (at most `passes`).  Each
+point is timed with HIP events on the calibration scene, and every point must
+return the bits of the first (a point that changes a bit raises).  Results are
+cached as JSON under a key made of the GPU architecture, a size bucket of the
+scene and the SHA-256 of the loaded library, so a rebuilt kernel is tuned anew.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
 import statistics
-from typing import Dict, List, Optional, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
-from . import GpuScene, ivm_intervisibility_matrix, make_opts
+from . import LIB_PATH, GpuScene, ivm_intervisibility_matrix, make_opts
 
-WAVES_PER_CU = (8, 12, 16, 24, 32)
-STACK_DEPTHS = (12, 16, 20, 24)
+KNOBS: Dict[str, Tuple[int, ...]] = {
+    "waves_per_cu": (8, 12, 16, 24, 32),
+    "stack_depth": (12, 16, 20, 24),
+    "tile_cap": (16, 32, 64),
+    "tile_treelets": (2, 4, 6, 10),
+    "pair_chunk": (0, 2, 4, 8, 16, 32, 64),
+}
+DEFAULTS = {"waves_per_cu": 16, "stack_depth": 24, "tile_cap": 64, "tile_treelets": 6, "pair_chunk": 0}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ivm_autotune.json")
+
+
+def library_hash(path: str = LIB_PATH) -> str:
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def size_bucket(scene: GpuScene) -> str:
@@ -38,20 +60,27 @@ def _load(path: str) -> Dict[str, dict]:
 
 
 def autotune_matrix(scene: GpuScene, repeats: int = 3, cache_path: Optional[str] = DEFAULT_CACHE,
-                    grid: Optional[List[Tuple[int, int]]] = None, force: bool = False) -> dict:
-    """Best (waves_per_cu, stack_depth) for ivm_intervisibility_matrix on this scene."""
+                    knobs: Optional[Dict[str, Sequence[int]]] = None, passes: int = 2,
+                    force: bool = False) -> dict:
+    """Best knob values for ivm_intervisibility_matrix on this scene (see the module doc)."""
     import torch
-    key = size_bucket(scene)
+    key = f"{size_bucket(scene)}/lib{library_hash()}"
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         return dict(cache[key], cached=True)
-    grid = grid or [(w, s) for w in WAVES_PER_CU for s in STACK_DEPTHS]
+    knobs = dict(knobs or KNOBS)
+    out = torch.empty((scene.F, scene.W), dtype=torch.int64, device=scene.device)
     ref = None
-    table = []
-    for wpc, depth in grid:
-        opts = make_opts(waves_per_cu=wpc, stack_depth=depth)
-        out = torch.empty((scene.F, scene.W), dtype=torch.int64, device=scene.device)
-        ivm_intervisibility_matrix(scene, opts, out=out)           # warm-up
+    timed: Dict[Tuple[Tuple[str, int], ...], float] = {}
+    table: List[dict] = []
+
+    def measure(point: Dict[str, int]) -> float:
+        nonlocal ref
+        tkey = tuple(sorted(point.items()))
+        if tkey in timed:
+            return timed[tkey]
+        opts = make_opts(**point)
+        ivm_intervisibility_matrix(scene, opts, out=out)            # warm-up
         times = []
         for _ in range(repeats):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -63,11 +92,26 @@ def autotune_matrix(scene: GpuScene, repeats: int = 3, cache_path: Optional[str]
         if ref is None:
             ref = out.clone()
         elif not torch.equal(ref, out):
-            raise RuntimeError(f"launch parameters {wpc}, {depth} changed the result")
-        table.append({"waves_per_cu": wpc, "stack_depth": depth, "ms": statistics.median(times)})
-    best = min(table, key=lambda r: r["ms"])
-    res = {"waves_per_cu": best["waves_per_cu"], "stack_depth": best["stack_depth"], "ms": best["ms"],
-           "table": table, "bucket": key}
+            raise RuntimeError(f"launch parameters {point} changed the result")
+        ms = statistics.median(times)
+        timed[tkey] = ms
+        table.append(dict(point, ms=ms))
+        return ms
+
+    best = {k: DEFAULTS[k] for k in knobs}
+    best_ms = measure(best)
+    for _ in range(passes):
+        changed = False
+        for name, values in knobs.items():
+            for v in values:
+                if v == best[name]:
+                    continue
+                ms = measure(dict(best, **{name: v}))
+                if ms < best_ms:
+                    best, best_ms, changed = dict(best, **{name: v}), ms, True
+        if not changed:
+            break
+    res = dict(best, ms=best_ms, default_ms=table[0]["ms"], points=len(table), table=table, bucket=key)
     if cache_path:
         cache[key] = res
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
@@ -76,3 +120,8 @@ def autotune_matrix(scene: GpuScene, repeats: int = 3, cache_path: Optional[str]
             json.dump(cache, fh, indent=1)
         os.replace(tmp, cache_path)
     return dict(res, cached=False)
+
+
+def opts_from(tune: dict, **extra):
+    """ivm_matrix_opts with the tuned knob values (plus any other make_opts arguments)."""
+    return make_opts(**{k: tune[k] for k in KNOBS if k in tune}, **extra)

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libivm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["abi.hip", "scene.hip", "solids.hip", "traverse.hip", "candidates.hip", "ranges.hip", "relations.hip", "angles.hip", "mlp.hip",
+SOURCES = ["abi.hip", "scene.hip", "solids.hip", "traverse.hip", "candidates.hip", "ranges.hip", "relations.hip", "angles.hip", "paths.hip", "mlp.hip",
            "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

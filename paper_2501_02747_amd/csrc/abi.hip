@@ -19,7 +19,7 @@ namespace {
 
 ivm_status status_from_bits(int bits) {
     if (bits & kStInvalid) return IVM_ERR_INVALID_ARGUMENT;
-    if (bits & (kStGrid | kStAngleRange)) return IVM_ERR_GRID;
+    if (bits & (kStGrid | kStAngleRange | kStPathRange)) return IVM_ERR_GRID;
     if (bits & kStDegenerate) return IVM_ERR_DEGENERATE;
     return IVM_OK;
 }
@@ -36,6 +36,11 @@ bool desc_sizes_ok(const ivm_scene_desc *d) {
     if (d->n_solids < 0 || d->n_solids > 65535) return false;
     return true;
 }
+
+
+}  // namespace
+
+namespace ivm {
 
 TraverseOpts make_opts(const ivm_matrix_opts *o) {
     TraverseOpts t{};
@@ -56,10 +61,16 @@ TraverseOpts make_opts(const ivm_matrix_opts *o) {
     t.events = o ? o->timing_events : nullptr;
     t.exhaustive = o ? o->exhaustive : 0;
     t.no_tile = (o ? o->no_tile : 0) || t.exhaustive;
+    const int cap = (o && o->tile_cap > 0) ? o->tile_cap : 64;
+    t.tile_cap = cap > 64 ? 64 : cap;
+    const int tt = (o && o->tile_treelets > 0) ? o->tile_treelets : 6;
+    t.tile_treelets = tt > kTreelets ? kTreelets : tt;
+    const int pc = o ? o->pair_chunk : 0;
+    t.pair_chunk = pc <= 0 ? 0 : (pc > 256 ? 256 : pc);
     return t;
 }
 
-}  // namespace
+}  // namespace ivm
 
 extern "C" {
 
@@ -360,6 +371,25 @@ ivm_status ivm_edge_rows(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t 
                          d_edge_facet, d_edge_edge, stream) != hipSuccess)
         return IVM_ERR_HIP;
     return IVM_OK;
+}
+
+ivm_status ivm_validate_paths(ivm_scene *scene, int32_t n_snap, const float *d_tx, const float *d_rx,
+                              int32_t max_order, const int64_t *d_offsets, const int32_t *d_paths, int64_t n_elems,
+                              uint8_t *d_valid, int64_t *d_valid_counts, ivm_stats *d_stats, hipStream_t stream) {
+    if (!scene || n_snap < 0 || max_order < 1 || max_order > 4 || n_elems < 0) return IVM_ERR_INVALID_ARGUMENT;
+    if ((long long)n_snap * max_order > 0x7fffffffLL) return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap > 0 && (!d_tx || !d_rx || !d_offsets)) return IVM_ERR_INVALID_ARGUMENT;
+    if (n_elems > 0 && (!d_paths || !d_valid || n_snap == 0)) return IVM_ERR_INVALID_ARGUMENT;
+    if (n_snap == 0) return IVM_OK;
+    const SceneDev &d = scene->s.dev;
+    if (launch_validate_paths(d, n_snap, max_order, d_tx, d_rx, d_offsets, d_paths, n_elems, d_valid, d_valid_counts,
+                              d_stats ? (unsigned long long *)&d_stats->tri_tests : nullptr, stream) != hipSuccess)
+        return IVM_ERR_HIP;
+    int bits = 0;
+    if (hipMemcpyAsync(&bits, d.status, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return IVM_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return IVM_ERR_HIP;
+    if (bits & kStInvalid) return IVM_ERR_INVALID_ARGUMENT;
+    return (bits & (kStPathRange | kStGrid)) ? IVM_ERR_GRID : IVM_OK;
 }
 
 ivm_status ivm_model_workspace_size(int32_t max_batch, size_t *bytes) {

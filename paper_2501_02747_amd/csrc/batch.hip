@@ -96,21 +96,8 @@ hipError_t record(ivm_batch *b, hipStream_t s) {
 }
 
 TraverseOpts batch_opts(const ivm_matrix_opts *o) {
-    TraverseOpts t{};
-    t.order_mode = o ? o->order_mode : IVM_ORDER_PLAIN;
-    t.fp64_only = o ? o->fp64_only : 0;
-    int depth = (o && o->stack_depth > 0) ? o->stack_depth : kDefaultStack;
-    t.stack_depth = depth < 2 ? 2 : (depth > IVM_MAX_STACK ? IVM_MAX_STACK : depth);
-    float eps = (o && o->eps > 0.f) ? o->eps : kDefaultEps;
-    if (!(eps >= kDefaultEps)) eps = kDefaultEps;
-    t.eps6 = __builtin_isinf(eps) ? __builtin_inff() : 6.0f * eps;
-    int wpc = (o && o->waves_per_cu > 0) ? o->waves_per_cu : 16;
-    if (wpc > 64) wpc = 64;
-    long long blocks = (long long)device_cu_count() * wpc / 4;
-    t.grid_blocks = (int)(blocks < 1 ? 1 : blocks);
+    TraverseOpts t = make_opts(o);
     t.events = nullptr;  // a captured graph records no caller events
-    t.exhaustive = o ? o->exhaustive : 0;
-    t.no_tile = (o ? o->no_tile : 0) || t.exhaustive;
     return t;
 }
 

@@ -14,7 +14,7 @@ constexpr int kWave = 64;
 constexpr int kTreelets = 32;      // top-level subtrees: contiguous equal-count Morton ranges
 constexpr int kLeafMax = 4;        // subtrees of <= kLeafMax triangles become leaves
 constexpr int kDefaultStack = 24;
-constexpr int kMaxSamplesPerFacet = 64;
+constexpr int kMaxSamplesPerFacet = IVM_MAX_SAMPLES_PER_FACET;
 constexpr float kDefaultEps = 1e-5f;
 constexpr int kHullMax = 8;       // sample convex hull points kept per facet (0 = none kept)
 constexpr int kSolidMaxFacets = 64;   // facets per solid group considered by the prism check
@@ -44,6 +44,7 @@ constexpr int kStGrid = 1;
 constexpr int kStDegenerate = 2;
 constexpr int kStInvalid = 4;
 constexpr int kStAngleRange = 8;  // an angular range's integer terms would leave 128 bits
+constexpr int kStPathRange = 16;  // a path validation's integers would leave 512 bits
 
 // Node of a binary BVH whose boxes live in the parent (one 64-byte record):
 //   a = (lo0.x, lo0.y, lo0.z, hi0.x), b = (hi0.y, hi0.z, lo1.x, lo1.y),
@@ -168,7 +169,13 @@ struct TraverseOpts {
     int no_tile;               // 1: skip the near-field tile
     int exhaustive;            // 1: every admissible segment gets its own search
     hipEvent_t *events;        // optional: recorded around the traversal kernel
+    int tile_cap;              // near-field tile capacity (1..kTile triangles)
+    int tile_treelets;         // gather a tile only for bundles meeting at most this many treelets
+    int pair_chunk;            // consecutive undecided pairs a wave takes at a time (0 = by load)
 };
+
+// Traversal options from the public ones (defaults and clamping).
+TraverseOpts make_opts(const ivm_matrix_opts *o);
 
 // One scene's share of a (possibly multi-scene) persistent pair launch.
 struct PairJob {
@@ -255,6 +262,11 @@ hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total
 hipError_t launch_edges(Scene &scn, const TraverseOpts &o, int N, int E, int s, const int *efac, const float *esmp,
                         const float *tx, const float *rx, uint64_t *txe, uint64_t *rxe, int64_t *counts,
                         hipStream_t st);
+// Exact image-method validation of candidate lists (CSR of int32 k-tuples, as
+// ivm_image_tree_candidates writes them): a verdict byte per element.
+hipError_t launch_validate_paths(const SceneDev &sc, int N, int K, const float *tx, const float *rx,
+                                 const int64_t *offsets, const int32_t *paths, long long n_elems, uint8_t *valid,
+                                 int64_t *valid_counts, unsigned long long *stats, hipStream_t s);
 // Edge rows of the matrix (edge to facet and edge to edge) for the listed edges.
 hipError_t launch_edge_rows(Scene &scn, const TraverseOpts &o, int E, int s, const int *efac, const float *esmp,
                             int n_rows, const int *rows, uint64_t *ef, uint64_t *ee, hipStream_t st);

@@ -1076,7 +1076,7 @@ __device__ unsigned certify_subpairs(const SceneDev &sc, int i, int j, int C, un
 
 constexpr int kTile = 64;       // near-field tile capacity (triangle ranks)
 constexpr int kFrontier = 128;  // cooperative traversal frontier capacity
-constexpr int kTileMaxTreelets = 6;  // gather a tile only when the bundle box meets at most this many treelets
+// (a tile is gathered only when the bundle box meets at most TraverseOpts::tile_treelets treelets, 6 by default)
 
 __device__ inline bool box_overlap(float lx, float ly, float lz, float hx, float hy, float hz, const float lo[3],
                                    const float hi[3]) {
@@ -1092,7 +1092,7 @@ __device__ inline bool box_overlap(float lx, float ly, float lz, float hx, float
 // segment is decided by scanning the tile alone.  Returns the tile size, or -1
 // when the tile would overflow.
 __device__ int gather_tile(const SceneDev &sc, int i, int j, const float lo[3], const float hi[3],
-                           const uint8_t *order, int n_order, int *frontier, int *tile, int *counters) {
+                           const uint8_t *order, int n_order, int *frontier, int *tile, int *counters, int cap) {
     const int lane = lane_id();
     if (lane == 0) {
         counters[0] = 0;  // frontier size
@@ -1116,7 +1116,7 @@ __device__ int gather_tile(const SceneDev &sc, int i, int j, const float lo[3], 
                 const int f = __float_as_int(sc.tri[3 * r].w);
                 if (f == i || f == j) continue;
                 const int at = atomicAdd(&counters[1], 1);
-                if (at < kTile) tile[at] = r;
+                if (at < cap) tile[at] = r;
                 else counters[2] = 1;
             }
         };
@@ -1364,7 +1364,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     unsigned long long d_m = 0ull;
     uint32_t d_gl = 0xffffffffu;
     const uint32_t nwaves_all = gridDim.x * (uint32_t)kWavesPerBlock;
-    const uint32_t chunk = total / nwaves_all > kLargePerWave ? (uint32_t)kPairChunkLarge : (uint32_t)kPairChunk;
+    const uint32_t chunk = o.pair_chunk > 0 ? (uint32_t)o.pair_chunk
+                           : (total / nwaves_all > kLargePerWave ? (uint32_t)kPairChunkLarge : (uint32_t)kPairChunk);
     while (true) {
         if (g_next >= g_end) {
             uint32_t g0 = 0;
@@ -1538,9 +1539,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int n_order = wave_rank_order(treelet_key(sc, lane, lo, hi, o.order_mode, lcode), sKey[wv], sOrder[wv]);
         // near-field tile (the miss queue's storage doubles as the walk frontier)
         // (only for bundles meeting few treelets: a long bundle would overflow the tile anyway)
-        const int ntile = (o.no_tile || n_order > kTileMaxTreelets)
+        const int ntile = (o.no_tile || n_order > o.tile_treelets)
                               ? -1
-                              : gather_tile(sc, i, j, lo, hi, sOrder[wv], n_order, sMiss[wv], sTile[wv], sTileCnt[wv]);
+                              : gather_tile(sc, i, j, lo, hi, sOrder[wv], n_order, sMiss[wv], sTile[wv], sTileCnt[wv],
+                                            o.tile_cap);
         ntiled += ntile >= 0;
         // the segment space: the whole product (one rectangle, spread order over
         // all of it) unless some sub-pairs are already certified

@@ -98,13 +98,13 @@ C4_CACHE = os.path.join(os.path.dirname(__file__), "golden", "cache", "c4_rows.n
 def test_batched_workload_full_size(oracle_mod):
     """The batched workload at its real size (64 scenes of 636-4856 facets,
     seeds 1000-1063, 64 077 snapshots) in one captured graph, in the launch
-    configuration of the batched bench (autotuned waves per CU and stack depth):
+    configuration of the batched bench (the autotuned knobs of the calibration scene):
     every scene's matrix, tables, LoS and candidate counts equal the single-scene
     calls, and two whole seeded rows and two whole seeded snapshots of every
     scene equal the stored oracle results (tests/golden/make_c4_oracle_cache.py)."""
     import torch
     import paper_2501_02747_amd as ivm
-    from paper_2501_02747_amd.autotune import autotune_matrix
+    from paper_2501_02747_amd.autotune import KNOBS, autotune_matrix, opts_from
     _log("[batch] generating the 64 batched scenes")
     scenes = sg.gen_c4(1000, 64)
     z = np.load(C4_CACHE, allow_pickle=False)
@@ -114,10 +114,9 @@ def test_batched_workload_full_size(oracle_mod):
     txs = [torch.as_tensor(s.tx).cuda() for s in scenes]
     rxs = [torch.as_tensor(s.rx).cuda() for s in scenes]
     calib = int(np.argsort(F)[len(F) // 2])
-    tune = autotune_matrix(gs[calib], repeats=1, cache_path=None,
-                           grid=[(w, d) for w in (8, 16, 24, 32) for d in (16, 24)])
-    _log(f"[batch] autotuned: waves/CU {tune['waves_per_cu']}, stack {tune['stack_depth']}")
-    opts = ivm.make_opts(waves_per_cu=tune["waves_per_cu"], stack_depth=tune["stack_depth"])
+    tune = autotune_matrix(gs[calib], repeats=1, cache_path=None)
+    _log("[batch] autotuned: " + ", ".join(f"{k} {tune[k]}" for k in KNOBS))
+    opts = opts_from(tune)
     batch = ivm.Batch(gs, txs, rxs, opts)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
