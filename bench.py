@@ -271,7 +271,7 @@ def run_batched(args, ivm, torch, sg):
     txs = [torch.as_tensor(s.tx).cuda() for s in scenes]
     rxs = [torch.as_tensor(s.rx).cuda() for s in scenes]
     calib = int(np.argsort(F)[len(F) // 2])
-    tune = autotune_matrix(gs[calib], repeats=1, cache_path=None)
+    tune = autotune_matrix(gs[calib], repeats=1, cache_path=None, rebuild=True)
     progress(f"autotuned on scene {calib} (F={F[calib]}) over {tune['points']} points: "
              + ", ".join(f"{k} {tune[k]}" for k in KNOBS) + f" ({tune['default_ms']:.2f} -> {tune['ms']:.2f} ms)")
     opts = opts_from(tune)
@@ -313,8 +313,6 @@ def run_batched(args, ivm, torch, sg):
         "autotune": dict({k: tune[k] for k in KNOBS}, ms=tune["ms"], default_ms=tune["default_ms"],
                          points=tune["points"], calibration_scene=calib),
         "stats_per_run": sd,
-        "autotune": (dict({k: tune[k] for k in KNOBS}, ms=tune["ms"], default_ms=tune["default_ms"],
-                          points=tune["points"]) if tune else "not run (defaults; --autotune tunes this workload)"),
         "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
                      "frac": ach / VALU_PEAK_TOPS, "traffic": None, "kernel": "whole graph (k_probe_pairs + k_pairs + k_points)"},
     }
@@ -402,7 +400,7 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
     tune = None
     knob = {"waves_per_cu": args.waves_per_cu, "stack_depth": args.stack}
     if (args.autotune or not headline) and not args.exhaustive:
-        tune = autotune_matrix(g, repeats=3 if F <= 4000 else 1, cache_path=None)
+        tune = autotune_matrix(g, repeats=3 if F <= 4000 else 1, cache_path=None, rebuild=True)
         knob = {k: tune[k] for k in KNOBS}
         print(f"[bench] {config}: autotuned over {tune['points']} points: "
               + ", ".join(f"{k} {tune[k]}" for k in KNOBS) + f" ({tune['default_ms']:.2f} -> {tune['ms']:.2f} ms)",
@@ -494,6 +492,8 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
         "kernel_ms": {"k_probe_pairs+k_pairs": pairs_kernel_ms, "k_points": points_kernel_ms},
         "stats_matrix": sm,
         "stats_table": sp,
+        "autotune": (dict({k: tune[k] for k in KNOBS}, ms=tune["ms"], default_ms=tune["default_ms"],
+                          points=tune["points"]) if tune else "not run (defaults; --autotune tunes this workload)"),
         "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
                      "frac": ach / VALU_PEAK_TOPS, "traffic": prof.get("pairs_hbm_bytes"),
                      "traffic_unit": "HBM bytes per matrix call (FETCH_SIZE + WRITE_SIZE, from profiles/)",
@@ -533,7 +533,8 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
             "queries_per_s": n_pairs / (statistics.median(times) / 1e3),
             "k_pairs_ms": t_pairs.elapsed_ms(), "identical_bits": bool(torch.equal(M, M2)),
             "box_tests": so["box_tests"], "tri_tests": so["tri_tests"], "segments": so["segments"],
-            "certified": so["certified"],
+            "certified": so["certified"], "traversed": so["traversed"], "solid_certified": so["solid_certified"],
+            "solid_segments": so["solid_segments"], "solid_planes": so["solid_planes"],
             "note": "learned = network inference (in the matrix call) + learned treelet order",
         }
         progress(f"{other} order: {statistics.median(times):.2f} ms, identical bits "

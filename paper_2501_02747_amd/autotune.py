@@ -61,8 +61,10 @@ def _load(path: str) -> Dict[str, dict]:
 
 def autotune_matrix(scene: GpuScene, repeats: int = 3, cache_path: Optional[str] = DEFAULT_CACHE,
                     knobs: Optional[Dict[str, Sequence[int]]] = None, passes: int = 2,
-                    force: bool = False) -> dict:
-    """Best knob values for ivm_intervisibility_matrix on this scene (see the module doc)."""
+                    force: bool = False, rebuild: bool = False) -> dict:
+    """Best knob values for ivm_intervisibility_matrix on this scene (see the module doc).
+    With rebuild=True the scene is rebuilt before every timed call (as in a
+    pipeline step that builds and then queries), so caches start as they would."""
     import torch
     key = f"{size_bucket(scene)}/lib{library_hash()}"
     cache = _load(cache_path) if cache_path else {}
@@ -83,6 +85,8 @@ def autotune_matrix(scene: GpuScene, repeats: int = 3, cache_path: Optional[str]
         ivm_intervisibility_matrix(scene, opts, out=out)            # warm-up
         times = []
         for _ in range(repeats):
+            if rebuild:
+                scene.rebuild()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             ivm_intervisibility_matrix(scene, opts, out=out)

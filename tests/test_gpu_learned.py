@@ -182,3 +182,81 @@ def test_learned_without_model_falls_back(ivm):
     torch.cuda.synchronize()
     assert torch.equal(M, Mp)
     assert ivm.stats_dict(st)["flags"] & 1
+
+
+def test_trained_network_gain_on_held_out_urban_grid(oracle_mod, ivm):
+    """What the shipped network (trained on urban-grid seeds 200-209) gains on the
+    held-out urban grid (seed 2, the benchmark scene): identical bits in every
+    order, fewer box tests than the plain order (nearest treelet first), than a
+    random-weight network and than Morton index order, and a ranking of the
+    treelets that finds a blocking treelet first far more often than chance.
+    Times of plain and learned calls are reported (the learned call includes
+    the network's inference), not asserted."""
+    import os
+    import statistics
+    import torch
+    from paper_2501_02747_amd import train as tr
+    cache = os.path.join(os.path.dirname(__file__), "golden", "cache", "c2_seed2.npz")
+    if not os.path.exists(cache):
+        pytest.skip("full oracle cache not generated")
+    s = sg.gen_c2(2, n_snap=1)
+    F = s.n_facets
+    z = np.load(cache, allow_pickle=False)
+    Mo = np.unpackbits(z["M"], axis=1)[:, :F].astype(bool)
+    g = ivm.GpuScene.from_scene(s, learned=True).check()
+    trained = ivm.Model(max_batch=1024, precision=ivm.IVM_MODEL_BF16)
+    trained.set_params(np.load(tr.DEFAULT_WEIGHTS, allow_pickle=False))
+    rand = ivm.Model(max_batch=1024, precision=ivm.IVM_MODEL_BF16)
+    rand.set_params(tr.he_uniform_init(11))
+
+    def run(order, model=None):
+        ivm.ivm_scene_set_model(g, model)
+        st = ivm.new_stats()
+        times = []
+        for k in range(4):
+            st.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            M = ivm.ivm_intervisibility_matrix(g, ivm.make_opts(order_mode=order), stats=st)
+            e1.record()
+            torch.cuda.synchronize()
+            if k:
+                times.append(e0.elapsed_time(e1))
+        assert (ivm.unpack_bits(M, F) == Mo).all(), order
+        d = ivm.stats_dict(st)
+        return d["box_tests"], d["tri_tests"], statistics.median(times)
+
+    res = {"plain": run(ivm.IVM_ORDER_PLAIN), "index": run(ivm.IVM_ORDER_INDEX),
+           "learned": run(ivm.IVM_ORDER_LEARNED, trained), "random-weights": run(ivm.IVM_ORDER_LEARNED, rand)}
+    ivm.ivm_scene_set_model(g, None)
+    for k, (b, t, ms) in res.items():
+        _log(f"[gain] {k:15s} box tests {b:12d}  triangle tests {t:11d}  matrix {ms:7.3f} ms")
+    lb = res["learned"][0]
+    assert lb < 0.98 * res["plain"][0]
+    assert lb < res["random-weights"][0] and lb < res["index"][0]
+    # ranking quality on held-out hit records: the top-scored treelet holds a
+    # blocker (all-hit labels, pinned against the oracle) for how many pairs
+    rng = np.random.default_rng(21)
+    I, J = rng.integers(0, F, 60000), rng.integers(0, F, 60000)
+    keep = I != J
+    I, J = np.minimum(I, J)[keep].astype(np.int32), np.maximum(I, J)[keep].astype(np.int32)
+    dI, dJ = torch.as_tensor(I).cuda(), torch.as_tensor(J).cuda()
+    lab = ivm.ivm_pair_occluder_labels(g, dI, dJ).cpu().numpy().view(np.uint32)
+    hit = lab != 0
+    X = ivm.ivm_pair_features(g, dI[torch.as_tensor(hit).cuda()], dJ[torch.as_tensor(hit).cuda()])
+    lab = lab[hit]
+    bits = (lab[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1
+
+    def p_at_1(model):
+        out = []
+        for c0 in range(0, X.shape[0], 1024):
+            out.append(model.forward(X[c0:c0 + 1024]).cpu().numpy())
+        sc = np.nan_to_num(np.concatenate(out), nan=-np.inf)
+        top = np.argmax(sc, 1)
+        return float(bits[np.arange(len(top)), top].mean())
+
+    p_tr, p_rand = p_at_1(trained), p_at_1(rand)
+    chance = float(bits.mean())
+    _log(f"[gain] {len(lab)} held-out hit records: top treelet holds a blocker for {p_tr:.3f} (trained), "
+         f"{p_rand:.3f} (random weights), {chance:.3f} (a random treelet)")
+    assert p_tr > p_rand + 0.2 and p_tr > 2 * chance
