@@ -192,6 +192,11 @@ typedef struct ivm_matrix_opts {
     int32_t pair_chunk;     /* pair-to-wave mapping: consecutive undecided pairs a wave takes
                                from the queue at a time, 1..256; 0 = 4, or 32 when there are
                                more than 2048 pairs per wave */
+    int32_t xcd_parts;      /* the pair queues (and the table's item ranges) are split into this
+                               many contiguous ranges, 1..8; workgroups start on range (block
+                               index mod ranges), one per XCD with 8, so neighbouring rows (or
+                               snapshots) share an L2; 0 = 1 (measured: no faster on the
+                               configured scenes) */
 } ivm_matrix_opts;
 
 #define IVM_MAX_STACK 24

@@ -86,6 +86,7 @@ class ivm_matrix_opts(ctypes.Structure):
         ("exhaustive", ctypes.c_int32),
         ("timing_events", ctypes.c_void_p),
         ("tile_cap", ctypes.c_int32), ("tile_treelets", ctypes.c_int32), ("pair_chunk", ctypes.c_int32),
+        ("xcd_parts", ctypes.c_int32),
     ]
 
 
@@ -204,14 +205,14 @@ def _ptr(t) -> Optional[int]:
 def make_opts(order_mode: int = IVM_ORDER_PLAIN, fp64_only: bool = False, stack_depth: int = 0,
               waves_per_cu: int = 0, eps: float = 0.0, timing: Optional["KernelTimer"] = None,
               no_tile: bool = False, exhaustive: bool = False, tile_cap: int = 0, tile_treelets: int = 0,
-              pair_chunk: int = 0) -> ivm_matrix_opts:
+              pair_chunk: int = 0, xcd_parts: int = 0) -> ivm_matrix_opts:
     o = ivm_matrix_opts()
     o.order_mode, o.fp64_only, o.stack_depth = order_mode, int(fp64_only), stack_depth
     o.no_tile = int(no_tile)
     o.exhaustive = int(exhaustive)
     o.waves_per_cu, o.eps = waves_per_cu, eps
     o.timing_events = timing.array_ptr if timing is not None else None
-    o.tile_cap, o.tile_treelets, o.pair_chunk = tile_cap, tile_treelets, pair_chunk
+    o.tile_cap, o.tile_treelets, o.pair_chunk, o.xcd_parts = tile_cap, tile_treelets, pair_chunk, xcd_parts
     return o
 
 

@@ -7,6 +7,8 @@ Knobs of the matrix call (none of them changes a result bit):
   tile_treelets  largest number of treelets a bundle box may meet for a tile
   pair_chunk     pair-to-wave mapping: consecutive undecided pairs a wave takes
                  from the queue at a time (0 = chosen from the load)
+  xcd_parts      the pair queues and table items split into one range per XCD
+                 (8) or a single range (1, the default)
 
 The search is coordinate descent: starting from the defaults, each knob in
 turn is swept over its values with the others fixed, and the fastest value is
@@ -33,8 +35,9 @@ KNOBS: Dict[str, Tuple[int, ...]] = {
     "tile_cap": (16, 32, 64),
     "tile_treelets": (2, 4, 6, 10),
     "pair_chunk": (0, 2, 4, 8, 16, 32, 64),
+    "xcd_parts": (1, 8),
 }
-DEFAULTS = {"waves_per_cu": 16, "stack_depth": 24, "tile_cap": 64, "tile_treelets": 6, "pair_chunk": 0}
+DEFAULTS = {"waves_per_cu": 16, "stack_depth": 24, "tile_cap": 64, "tile_treelets": 6, "pair_chunk": 0, "xcd_parts": 1}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ivm_autotune.json")
 
 
@@ -102,7 +105,7 @@ def autotune_matrix(scene: GpuScene, repeats: int = 3, cache_path: Optional[str]
         table.append(dict(point, ms=ms))
         return ms
 
-    best = {k: DEFAULTS[k] for k in knobs}
+    best = dict(DEFAULTS)  # knobs not swept keep their defaults
     best_ms = measure(best)
     for _ in range(passes):
         changed = False

@@ -67,6 +67,8 @@ TraverseOpts make_opts(const ivm_matrix_opts *o) {
     t.tile_treelets = tt > kTreelets ? kTreelets : tt;
     const int pc = o ? o->pair_chunk : 0;
     t.pair_chunk = pc <= 0 ? 0 : (pc > 256 ? 256 : pc);
+    const int xp = (o && o->xcd_parts > 0) ? o->xcd_parts : 1;
+    t.xcd_parts = xp > kXcdParts ? kXcdParts : xp;
     return t;
 }
 

@@ -172,7 +172,13 @@ struct TraverseOpts {
     int tile_cap;              // near-field tile capacity (1..kTile triangles)
     int tile_treelets;         // gather a tile only for bundles meeting at most this many treelets
     int pair_chunk;            // consecutive undecided pairs a wave takes at a time (0 = by load)
+    int xcd_parts;             // ranges the pair queues and table items are split into (1..kXcdParts)
 };
+
+// Queue counters of a matrix call (64 zeroed slots): the pair kernel's ranges at
+// kQueuePairs, probe round r's at kQueueProbe + kXcdParts r.
+constexpr int kXcdParts = 8;
+constexpr int kQueuePairs = 8, kQueueProbe = 16;
 
 // Traversal options from the public ones (defaults and clamping).
 TraverseOpts make_opts(const ivm_matrix_opts *o);

@@ -1254,6 +1254,33 @@ __device__ bool certify_pair_lane(const SceneDev &sc, int K, int i, int j, Cnt &
 // round 0 left undecided (und / uprefix), with other samples.  Each wave takes 64 consecutive candidates of one scene; in
 // the MULTI form pbase[] is the exclusive prefix of the scenes' candidate
 // totals rounded up to multiples of 64.
+// Work queue over [0, total) split into `parts` contiguous ranges with a counter
+// each (counters[0..parts)).  Workgroups are dispatched to the XCDs round-robin,
+// so block b starts on range b % parts, and with one range per XCD the scene
+// data its waves touch (neighbouring rows of the matrix) stays in that XCD's L2;
+// a wave whose range is used up moves on to the next ranges, so every wave ends
+// only when all ranges are empty.  Range bounds are multiples of `align`.
+// Takes the next chunk [g0, g1) for the wave; returns false when none is left.
+__device__ inline bool take_chunk(uint32_t *counters, int parts, uint32_t total, uint32_t align, uint32_t chunk,
+                                  int &tries, uint32_t &g0, uint32_t &g1) {
+    const uint32_t units = (total + align - 1) / align;
+    while (tries < parts) {
+        const int r = (int)((blockIdx.x + (unsigned)tries) % (unsigned)parts);
+        const uint32_t lo = (uint32_t)((uint64_t)units * r / parts) * align;
+        const uint32_t hi = min(total, (uint32_t)((uint64_t)units * (r + 1) / parts) * align);
+        uint32_t off = 0;
+        if (lane_id() == 0) off = atomicAdd(&counters[r], chunk);
+        off = __shfl(off, 0);
+        if (off < hi - lo) {
+            g0 = lo + off;
+            g1 = min(hi, g0 + chunk);
+            return true;
+        }
+        ++tries;
+    }
+    return false;
+}
+
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJob *many, const uint32_t *pbase,
                                                         int n_jobs, uint32_t *queue, int round, TraverseOpts o,
@@ -1266,11 +1293,10 @@ __global__ __launch_bounds__(kBlock) void k_probe_pairs(PairJob one, const PairJ
     unsigned long long segs = 0, nvis = 0, ncert = 0;
     const uint32_t total =
         MULTI ? pbase[n_jobs] : ((round ? one.uprefix : one.prefix)[one.n_items] + kWave - 1) / kWave * kWave;
+    int tries = 0;
     while (true) {
-        uint32_t g0 = 0;
-        if (lane == 0) g0 = atomicAdd(queue, (uint32_t)kWave);
-        g0 = __shfl(g0, 0);
-        if (g0 >= total) break;
+        uint32_t g0 = 0, g1 = 0;
+        if (!take_chunk(queue, o.xcd_parts, total, kWave, kWave, tries, g0, g1)) break;
         int js = 0;
         if (MULTI) {
             int lo = 0, hi = n_jobs - 1;
@@ -1366,14 +1392,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const uint32_t nwaves_all = gridDim.x * (uint32_t)kWavesPerBlock;
     const uint32_t chunk = o.pair_chunk > 0 ? (uint32_t)o.pair_chunk
                            : (total / nwaves_all > kLargePerWave ? (uint32_t)kPairChunkLarge : (uint32_t)kPairChunk);
+    int tries = 0;
     while (true) {
         if (g_next >= g_end) {
-            uint32_t g0 = 0;
-            if (lane == 0) g0 = atomicAdd(queue, chunk);
-            g0 = __shfl(g0, 0);
-            if (g0 >= total) break;
+            uint32_t g0 = 0, g1 = 0;
+            if (!take_chunk(queue, o.xcd_parts, total, 1u, chunk, tries, g0, g1)) break;
             g_next = g0;
-            g_end = min(total, g0 + chunk);
+            g_end = g1;
         }
         const uint32_t g = g_next++;
         int js = 0;
@@ -1932,15 +1957,15 @@ hipError_t launch_probe_jobs(const PairJob *d_jobs, const uint32_t *d_base, int 
                              const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
     PairJob none{};
     hipLaunchKernelGGL(k_probe_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base + n_jobs + 1,
-                       n_jobs, d_queue + 1 + round, round, o, stats);
+                       n_jobs, d_queue + kQueueProbe + kXcdParts * round, round, o, stats);
     return hipGetLastError();
 }
 
 hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue,
                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
     PairJob none{};
-    hipLaunchKernelGGL(k_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base, n_jobs, d_queue, o,
-                       stats);
+    hipLaunchKernelGGL(k_pairs<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, d_base, n_jobs,
+                       d_queue + kQueuePairs, o, stats);
     return hipGetLastError();
 }
 
@@ -1959,15 +1984,15 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
     // (the exhaustive baseline runs no probe and takes every candidate)
     for (int round = 0; round < kProbeRounds && !o.exhaustive; ++round) {
         hipLaunchKernelGGL(k_probe_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job,
-                           (const PairJob *)nullptr, (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue) + 1 + round,
-                           round, o, stats);
+                           (const PairJob *)nullptr, (const uint32_t *)nullptr, 1,
+                           (uint32_t *)(ws + L.queue) + kQueueProbe + kXcdParts * round, round, o, stats);
         if ((e = launch_undecided(scn, M, s)) != hipSuccess) return e;
     }
     if (o.exhaustive && (e = launch_undecided(scn, M, s)) != hipSuccess) return e;
     // the learned treelet order of the undecided pairs (network inference)
     if (learned && (e = launch_learned_order(scn, *scn.model, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pairs<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PairJob *)nullptr,
-                       (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue), o, stats);
+                       (const uint32_t *)nullptr, 1, (uint32_t *)(ws + L.queue) + kQueuePairs, o, stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (o.events && (e = hipEventRecord(o.events[1], s)) != hipSuccess) return e;
     return hipSuccess;
@@ -2156,8 +2181,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
     const bool f64 = o.fp64_only != 0;
-    const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+    // Each wave takes a contiguous range of items.  Workgroups are dispatched to
+    // the XCDs round-robin; with xcd_parts ranges the waves of one XCD take
+    // consecutive ranges (consecutive snapshots: nearby points, whose scene data
+    // then stays in that XCD's L2).
     const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+    const int xp = o.xcd_parts;
+    if (xp > 1 && gridDim.x % (unsigned)xp == 0) {
+        const long long per_part = (long long)(gridDim.x / (unsigned)xp) * kWavesPerBlock;
+        wave = (long long)(blockIdx.x % (unsigned)xp) * per_part + (long long)(blockIdx.x / (unsigned)xp) * kWavesPerBlock +
+               wv;
+    }
     const long long per = (n_items + nwaves - 1) / nwaves;
     const long long it0 = wave * per, it1 = min(n_items, it0 + per);
     const unsigned long long lt = (1ull << lane) - 1ull;
