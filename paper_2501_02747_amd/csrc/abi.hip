@@ -127,39 +127,39 @@ ivm_status ivm_build_scene(const ivm_scene_desc *desc, void *d_workspace, size_t
     d.max_spf = kMaxSamplesPerFacet;
     d.g = desc->grid_vertex_log2;
     d.gs = desc->grid_sample_log2;
-    d.tri = (const float4 *)(ws + L.tri);
-    d.tri_orig = (const int *)(ws + L.tri_orig);
-    d.tri_group = (const int *)(ws + L.tri_group);
-    d.nodes = (const Node *)(ws + L.nodes);
-    d.nodes4 = (const Node4 *)(ws + L.nodes4);
-    d.tl_box = (const float *)(ws + L.tl_box);
-    d.tl_root = (const int *)(ws + L.tl_root);
-    d.fplane = (const double *)(ws + L.fplane);
-    d.fbox = (const float *)(ws + L.fbox);
-    d.soff = (const int *)(ws + L.soff);
-    d.smp = (const float4 *)(ws + L.smp);
-    d.sfacet = (const int *)(ws + L.sfacet);
-    d.tri_caller = (const float4 *)(ws + L.tri_caller);
-    d.ftri = (const int *)(ws + L.ffirst);
-    d.fhull = (const int *)(ws + L.fhull);
-    d.fhull_n = (const int *)(ws + L.fhull_n);
-    d.scluster = (const int *)(ws + L.scluster);
-    d.fchull = (const int *)(ws + L.fchull);
-    d.fchull_n = (const int *)(ws + L.fchull_n);
-    d.ffeat = (const float *)(ws + L.ffeat);
-    d.fnorm = (const float *)(ws + L.fnorm);
-    d.status = (int *)(ws + L.status);
-    d.extent = (const double *)(ws + L.extent);
-    d.fflags = (const int *)(ws + L.fflags);
-    d.fsolid = (const int *)(ws + L.fsolid);
-    d.solid = (const int4 *)(ws + L.sol_rec);
-    d.splane = (const int4 *)(ws + L.sol_plane);
-    d.sbox = (const float4 *)(ws + L.sol_box);
-    d.gridp = (const float4 *)(ws + L.grid_p);
-    d.gridi = (const int *)(ws + L.grid_p + sizeof(float4));
-    d.gcell_off = (const int *)(ws + L.grid_off);
-    d.gcell_list = (const int *)(ws + L.grid_list);
-    d.gcell_ent = (const float4 *)(ws + L.grid_ent);
+    d.tri = (const IVM_GLOBAL float4 *)(ws + L.tri);
+    d.tri_orig = (const IVM_GLOBAL int *)(ws + L.tri_orig);
+    d.tri_group = (const IVM_GLOBAL int *)(ws + L.tri_group);
+    d.nodes = (const IVM_GLOBAL Node *)(ws + L.nodes);
+    d.nodes4 = (const IVM_GLOBAL Node4 *)(ws + L.nodes4);
+    d.tl_box = (const IVM_GLOBAL float *)(ws + L.tl_box);
+    d.tl_root = (const IVM_GLOBAL int *)(ws + L.tl_root);
+    d.fplane = (const IVM_GLOBAL double *)(ws + L.fplane);
+    d.fbox = (const IVM_GLOBAL float *)(ws + L.fbox);
+    d.soff = (const IVM_GLOBAL int *)(ws + L.soff);
+    d.smp = (const IVM_GLOBAL float4 *)(ws + L.smp);
+    d.sfacet = (const IVM_GLOBAL int *)(ws + L.sfacet);
+    d.tri_caller = (const IVM_GLOBAL float4 *)(ws + L.tri_caller);
+    d.ftri = (const IVM_GLOBAL int *)(ws + L.ffirst);
+    d.fhull = (const IVM_GLOBAL int *)(ws + L.fhull);
+    d.fhull_n = (const IVM_GLOBAL int *)(ws + L.fhull_n);
+    d.scluster = (const IVM_GLOBAL int *)(ws + L.scluster);
+    d.fchull = (const IVM_GLOBAL int *)(ws + L.fchull);
+    d.fchull_n = (const IVM_GLOBAL int *)(ws + L.fchull_n);
+    d.ffeat = (const IVM_GLOBAL float *)(ws + L.ffeat);
+    d.fnorm = (const IVM_GLOBAL float *)(ws + L.fnorm);
+    d.status = (IVM_GLOBAL int *)(ws + L.status);
+    d.extent = (const IVM_GLOBAL double *)(ws + L.extent);
+    d.fflags = (const IVM_GLOBAL int *)(ws + L.fflags);
+    d.fsolid = (const IVM_GLOBAL int *)(ws + L.fsolid);
+    d.solid = (const IVM_GLOBAL int4 *)(ws + L.sol_rec);
+    d.splane = (const IVM_GLOBAL int4 *)(ws + L.sol_plane);
+    d.sbox = (const IVM_GLOBAL float4 *)(ws + L.sol_box);
+    d.gridp = (const IVM_GLOBAL float4 *)(ws + L.grid_p);
+    d.gridi = (const IVM_GLOBAL int *)(ws + L.grid_p + sizeof(float4));
+    d.gcell_off = (const IVM_GLOBAL int *)(ws + L.grid_off);
+    d.gcell_list = (const IVM_GLOBAL int *)(ws + L.grid_list);
+    d.gcell_ent = (const IVM_GLOBAL float4 *)(ws + L.grid_ent);
     d.n_solids = desc->facet_solid ? desc->n_solids : 0;
     sc.n_items = F * d.W;
     if (launch_build(sc, stream) != hipSuccess) {

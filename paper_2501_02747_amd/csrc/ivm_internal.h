@@ -79,45 +79,55 @@ __host__ __device__ inline int leaf_count(int ref) { return ((~ref) & 7) + 1; }
 //   [2] = (e2 = c - a, max |e2_k|)
 // All components are exact: vertices sit on a dyadic grid.
 
+// Scene arrays live in global memory.  Device code sees the pointers in the
+// global address space, so every access is a global load even when the view is
+// read from memory (a batch's job table) or from a private copy; host code sees
+// plain pointers (the layout is the same).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define IVM_GLOBAL __attribute__((address_space(1)))
+#else
+#define IVM_GLOBAL
+#endif
+
 // Device view of a built scene (passed by value to kernels).
 struct SceneDev {
     int F, T, S, W, n_treelets, max_spf;
     int g, gs;                 // grid exponents (vertex, sample)
-    const float4 *tri;         // 3 * T
-    const int *tri_orig;       // sorted rank -> caller's triangle index
-    const int *tri_group;      // caller's triangle index -> treelet
-    const Node *nodes;         // T (internal nodes at global slots)
-    const Node4 *nodes4;       // T: 4-wide records, same slots
-    const float *tl_box;       // kTreelets * 6 (lo.xyz, hi.xyz)
-    const int *tl_root;        // kTreelets root refs (0x7fffffff = empty)
-    const double *fplane;      // F * 6: a.xyz, n.xyz
-    const float *fbox;         // F * 6
-    const int *soff;           // F + 1
-    const float4 *smp;         // S
-    const int *sfacet;         // S
-    const float4 *tri_caller;  // 3 * T, same records in the caller's triangle order
-    const int *ftri;           // F * 2: first caller triangle of the facet, triangle count
-    const int *fhull;          // F * kHullMax: sample indices of the convex hull of the facet's samples
-    const int *fhull_n;        // F: hull size (0 = unavailable)
-    const int *scluster;       // S: quadrant cluster (0..3) of each sample within its facet
-    const int *fchull;         // F * 4 * kHullMax: hull sample indices per cluster
-    const int *fchull_n;       // F * 4: cluster hull sizes (0 = unavailable or empty)
-    const float *ffeat;        // F * 8: normalised centroid (3), unit normal (3), area (1), pad
-    const float *fnorm;        // 4: scene-box centre (3) and half-size used to normalise features
-    int *status;               // device status bits
-    const double *extent;      // [0..5] = sample-unit integer box of vertices+samples as doubles; [6] = E
-    const int *fflags;         // F: kFacet* bits
-    const int *fsolid;         // F: verified solid of the facet, or -1
-    const int4 *solid;         // n_solids: (wall planes, top z, base z, 0), sample units; 0 planes = rejected
-    const int4 *splane;        // n_solids * kSolidMaxPlanes: (u.x, u.y, d.x, d.y) sample units; the
+    const IVM_GLOBAL float4 *tri;         // 3 * T
+    const IVM_GLOBAL int *tri_orig;       // sorted rank -> caller's triangle index
+    const IVM_GLOBAL int *tri_group;      // caller's triangle index -> treelet
+    const IVM_GLOBAL Node *nodes;         // T (internal nodes at global slots)
+    const IVM_GLOBAL Node4 *nodes4;       // T: 4-wide records, same slots
+    const IVM_GLOBAL float *tl_box;       // kTreelets * 6 (lo.xyz, hi.xyz)
+    const IVM_GLOBAL int *tl_root;        // kTreelets root refs (0x7fffffff = empty)
+    const IVM_GLOBAL double *fplane;      // F * 6: a.xyz, n.xyz
+    const IVM_GLOBAL float *fbox;         // F * 6
+    const IVM_GLOBAL int *soff;           // F + 1
+    const IVM_GLOBAL float4 *smp;         // S
+    const IVM_GLOBAL int *sfacet;         // S
+    const IVM_GLOBAL float4 *tri_caller;  // 3 * T, same records in the caller's triangle order
+    const IVM_GLOBAL int *ftri;           // F * 2: first caller triangle of the facet, triangle count
+    const IVM_GLOBAL int *fhull;          // F * kHullMax: sample indices of the convex hull of the facet's samples
+    const IVM_GLOBAL int *fhull_n;        // F: hull size (0 = unavailable)
+    const IVM_GLOBAL int *scluster;       // S: quadrant cluster (0..3) of each sample within its facet
+    const IVM_GLOBAL int *fchull;         // F * 4 * kHullMax: hull sample indices per cluster
+    const IVM_GLOBAL int *fchull_n;       // F * 4: cluster hull sizes (0 = unavailable or empty)
+    const IVM_GLOBAL float *ffeat;        // F * 8: normalised centroid (3), unit normal (3), area (1), pad
+    const IVM_GLOBAL float *fnorm;        // 4: scene-box centre (3) and half-size used to normalise features
+    IVM_GLOBAL int *status;    // device status bits
+    const IVM_GLOBAL double *extent;      // [0..5] = sample-unit integer box of vertices+samples as doubles; [6] = E
+    const IVM_GLOBAL int *fflags;         // F: kFacet* bits
+    const IVM_GLOBAL int *fsolid;         // F: verified solid of the facet, or -1
+    const IVM_GLOBAL int4 *solid;         // n_solids: (wall planes, top z, base z, 0), sample units; 0 planes = rejected
+    const IVM_GLOBAL int4 *splane;        // n_solids * kSolidMaxPlanes: (u.x, u.y, d.x, d.y) sample units; the
                                // outside of wall k is d.y (x - u.x) - d.x (y - u.y) > 0
     int n_solids;
-    const float4 *sbox;        // n_solids * 2: footprint box and (base, top) in .z, metres; empty if rejected
-    const float4 *gridp;       // (x0, y0, cell width, cell height) of the solid grid
-    const int *gridi;          // (G, usable, entries, 0)
-    const int *gcell_off;      // G * G + 1: CSR offsets of the cells' solid lists
-    const int *gcell_list;     // solid ids, sorted within each cell
-    const float4 *gcell_ent;   // the same entries with the solid's footprint box inline: 2 float4 each,
+    const IVM_GLOBAL float4 *sbox;        // n_solids * 2: footprint box and (base, top) in .z, metres; empty if rejected
+    const IVM_GLOBAL float4 *gridp;       // (x0, y0, cell width, cell height) of the solid grid
+    const IVM_GLOBAL int *gridi;          // (G, usable, entries, 0)
+    const IVM_GLOBAL int *gcell_off;      // G * G + 1: CSR offsets of the cells' solid lists
+    const IVM_GLOBAL int *gcell_list;     // solid ids, sorted within each cell
+    const IVM_GLOBAL float4 *gcell_ent;   // the same entries with the solid's footprint box inline: 2 float4 each,
                                // (lo.x, lo.y, lo.z, id as int bits), (hi.x, hi.y, hi.z, 0)
 };
 

@@ -1030,8 +1030,11 @@ __device__ inline void remember_solid_ids(const SceneDev &sc, int *solids, int &
 // meets C (same convexity argument as above).  Lanes run over the flattened
 // (sub-pair, corner, corner, triangle) items; returns the certified sub-pairs
 // among `todo` (bit 4 ci + cj).
-__device__ unsigned certify_subpairs(const SceneDev &sc, int i, int j, int C, unsigned todo,
-                                     unsigned long long *bits, float eps6, bool f64, Cnt &c) {
+// (Always inlined: an out-of-line call taking the scene view by reference makes
+// the pair kernel keep its kernel-argument copy in private memory and read every
+// scene array through generic flat loads.)
+__device__ __forceinline__ unsigned certify_subpairs(const SceneDev &sc, int i, int j, int C, unsigned todo,
+                                                     unsigned long long *bits, float eps6, bool f64, Cnt &c) {
     const int lane = lane_id();
     const int t0 = sc.ftri[2 * C], nt = sc.ftri[2 * C + 1];
     if (nt <= 0 || !todo || !(sc.fflags[C] & kFacetConvex)) return 0u;
@@ -1437,8 +1440,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
         const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
         const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
-        const float4 p = lane < ni ? sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
-        const float4 q = lane < nj ? sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
+        const float4 p = lane < ni ? (float4)sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
+        const float4 q = lane < nj ? (float4)sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
         const bool okp = lane < ni && orient(plj, p.x, p.y, p.z) > 0.0;
         const bool okq = lane < nj && orient(pli, q.x, q.y, q.z) > 0.0;
         const int clp = lane < ni ? sc.scluster[si0 + lane] : 0;
@@ -1773,8 +1776,8 @@ __global__ __launch_bounds__(kBlock) void k_labels(SceneDev sc, int n, const int
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
         const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
         const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
-        const float4 p = lane < ni ? sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
-        const float4 q = lane < nj ? sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
+        const float4 p = lane < ni ? (float4)sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
+        const float4 q = lane < nj ? (float4)sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
         const bool okp = lane < ni && orient(plj, p.x, p.y, p.z) > 0.0;
         const bool okq = lane < nj && orient(pli, q.x, q.y, q.z) > 0.0;
         const unsigned long long mp = __ballot(okp), mq = __ballot(okq);
@@ -2560,7 +2563,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_rows(SceneDev sc, int E, int s,
                                                       const float *esmp, int n_rows, const int *rows, uint64_t *ef,
                                                       uint64_t *ee, TraverseOpts o) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
-    __shared__ int sDone[kWavesPerBlock][kWave];
+    __shared__ volatile int sDone[kWavesPerBlock][kWave];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const int per_wave = kWave / G, n_targets = sc.F + E;
     const long long nb = (n_targets + per_wave - 1) / per_wave;
@@ -2569,7 +2572,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_rows(SceneDev sc, int E, int s,
     const int k = (int)(qw / nb), grp = lane / G, a = lane % G;
     const int target = (int)(qw % nb) * per_wave + grp;
     const int e = rows[k];
-    volatile int *done = &sDone[wv][0];
+    volatile int *done = sDone[wv];
     done[lane] = 0;
     bool clear = false;
     const bool row_ok = e >= 0 && e < E;

@@ -95,14 +95,28 @@ def test_forward_and_gradients_match_oracle(oracle_mod, ivm, precision):
     g_ref = oracle_mod.mlp_flatten(go)
     rel = np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)
     assert rel <= (1e-2 if bf16 else 1e-4), rel
-    # per layer as well
+    # per layer as well, and element by element: |g - g_ref| <= rtol |g_ref| + atol rms(layer).
+    # FP32 mode differs from the FP64 reference only in summation order (n terms of FP32
+    # products: about n 2^-24 of the summed magnitudes), so rtol 1e-4 with a floor of 1e-4 of
+    # the layer's rms.  BF16 mode rounds the same operands to BF16 on both sides, but an
+    # activation that differs in its last FP32 bit can round to the neighbouring BF16 value
+    # (a 2^-8 relative step) and move its terms by that much: rtol 5e-2 with a floor of 5e-2
+    # of the layer's rms (elements far below the rms come from cancellation).
+    rtol, afl = (5e-2, 5e-2) if bf16 else (1e-4, 1e-4)
     off = 0
+    worst = 0.0
     for l in range(4):
         for key in (f"W{l}", f"b{l}"):
             n = go[key].size
             seg_g, seg_r = g_gpu[off:off + n], g_ref[off:off + n]
             assert np.linalg.norm(seg_g - seg_r) <= (2e-2 if bf16 else 2e-4) * np.linalg.norm(seg_r) + 1e-9, key
+            rms = float(np.sqrt(np.mean(seg_r ** 2))) + 1e-30
+            bound = rtol * np.abs(seg_r) + afl * rms
+            ratio = np.abs(seg_g - seg_r) / bound
+            worst = max(worst, float(ratio.max()))
+            assert (ratio <= 1.0).all(), (key, int((ratio > 1).sum()), float(ratio.max()))
             off += n
+    _log(f"[mlp] {precision}: largest element error / bound = {worst:.3f}")
 
 
 def test_adam_step_matches_oracle(oracle_mod, ivm):
