@@ -154,7 +154,7 @@ typedef struct ivm_stats {
     uint64_t point_items;
     uint64_t flags; /* bit 0: learned order fell back to the plain order */
     uint64_t certified; /* pairs proven blocked by one convex occluder from hull corners */
-    uint64_t subpair_runs; /* pairs whose explicit segments were limited to uncertified sub-pairs */
+    uint64_t subpair_runs; /* pairs whose explicit segments were limited to uncertified sub-pairs or fans */
     uint64_t tiled_pairs;  /* pairs decided from a complete near-field tile, without the BVH */
     uint64_t solid_certified; /* matrix: pairs proven blocked by verified solids on whole or sub-pair
                                  bundles; table: (point, facet) pairs proven blocked by one solid */
@@ -201,6 +201,7 @@ typedef struct ivm_matrix_opts {
 
 #define IVM_MAX_STACK 24
 #define IVM_MAX_SAMPLES_PER_FACET 64
+#define IVM_MAX_SNAPSHOTS (1 << 24) /* snapshots per Tx/Rx table call or batch item */
 
 const char *ivm_status_string(ivm_status s);
 
@@ -244,7 +245,8 @@ ivm_status ivm_intervisibility_matrix(ivm_scene *scene, const ivm_matrix_opts *o
  * d_tx[n] and from d_rx[n] (uint64[N][W] each) and line of sight between them
  * (uint8[N]).  Positions are float[N][3] on the sample grid; off-grid positions
  * or positions that break the exactness budget are reported by ivm_scene_status.
- * opts may be NULL.  Errors: IVM_ERR_INVALID_ARGUMENT, IVM_ERR_HIP. */
+ * opts may be NULL.  Errors: IVM_ERR_INVALID_ARGUMENT (also for N above
+ * IVM_MAX_SNAPSHOTS), IVM_ERR_HIP. */
 ivm_status ivm_txrx_visibility_table(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_snap,
                                      const float *d_tx, const float *d_rx, uint64_t *d_tx_vis,
                                      uint64_t *d_rx_vis, uint8_t *d_los, ivm_stats *d_stats,
@@ -516,7 +518,7 @@ typedef struct ivm_batch ivm_batch; /* opaque host handle */
 typedef struct ivm_batch_item {
     ivm_scene *scene;          /* built scene, kept alive by the caller */
     uint64_t *d_M;             /* uint64[F][W] */
-    int32_t n_snap;
+    int32_t n_snap;            /* 0..IVM_MAX_SNAPSHOTS */
     const float *d_tx;         /* float[n_snap][3] */
     const float *d_rx;         /* float[n_snap][3] */
     uint64_t *d_tx_vis;        /* uint64[n_snap][W] */

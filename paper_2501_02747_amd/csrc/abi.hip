@@ -229,7 +229,7 @@ ivm_status ivm_intervisibility_matrix(ivm_scene *scene, const ivm_matrix_opts *o
 ivm_status ivm_txrx_visibility_table(ivm_scene *scene, const ivm_matrix_opts *opts, int32_t n_snap,
                                      const float *d_tx, const float *d_rx, uint64_t *d_tx_vis, uint64_t *d_rx_vis,
                                      uint8_t *d_los, ivm_stats *d_stats, hipStream_t stream) {
-    if (!scene || n_snap < 0) return IVM_ERR_INVALID_ARGUMENT;
+    if (!scene || n_snap < 0 || n_snap > IVM_MAX_SNAPSHOTS) return IVM_ERR_INVALID_ARGUMENT;
     if (n_snap > 0 && (!d_tx || !d_rx || !d_tx_vis || !d_rx_vis || !d_los)) return IVM_ERR_INVALID_ARGUMENT;
     if (opts && (opts->order_mode < IVM_ORDER_PLAIN || opts->order_mode > IVM_ORDER_REVERSED))
         return IVM_ERR_INVALID_ARGUMENT;

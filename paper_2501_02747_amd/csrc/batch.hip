@@ -22,7 +22,7 @@ struct ivm_batch {
     PointJob *d_qjobs;
     uint32_t *d_base;
     uint32_t *d_queue;
-    long long total_items;
+    long long total_units;
     TraverseOpts o;
     ivm_stats *stats;
     hipGraph_t graph;
@@ -83,7 +83,7 @@ hipError_t record(ivm_batch *b, hipStream_t s) {
             hipSuccess)
             return e;
     }
-    if ((e = launch_point_jobs(b->d_qjobs, b->n, b->total_items, b->o, b->stats, s)) != hipSuccess) return e;
+    if ((e = launch_point_jobs(b->d_qjobs, b->n, b->total_units, b->o, b->stats, s)) != hipSuccess) return e;
     for (int k = 0; k < b->n; ++k) {
         const ivm_batch_item &it = b->items[k];
         if ((e = launch_los(it.scene->s, b->o, it.n_snap, it.d_tx, it.d_rx, it.d_los, s)) != hipSuccess) return e;
@@ -121,7 +121,7 @@ ivm_status ivm_batch_create(int32_t n_items, const ivm_batch_item *items, const 
     if (workspace_bytes < batch_bytes(n_items)) return IVM_ERR_WORKSPACE;
     for (int k = 0; k < n_items; ++k) {
         const ivm_batch_item &it = items[k];
-        if (!it.scene || !it.d_M || it.n_snap < 0) return IVM_ERR_INVALID_ARGUMENT;
+        if (!it.scene || !it.d_M || it.n_snap < 0 || it.n_snap > IVM_MAX_SNAPSHOTS) return IVM_ERR_INVALID_ARGUMENT;
         if (it.n_snap > 0 && (!it.d_tx || !it.d_rx || !it.d_tx_vis || !it.d_rx_vis || !it.d_los))
             return IVM_ERR_INVALID_ARGUMENT;
     }
@@ -150,9 +150,9 @@ ivm_status ivm_batch_create(int32_t n_items, const ivm_batch_item *items, const 
         Scene &sc = it.scene->s;
         pj[k] = make_pair_job(sc, it.d_M, learned && sc.model != nullptr);
         qj[k] = make_point_job(sc, it.n_snap, it.d_tx, it.d_rx, it.d_tx_vis, it.d_rx_vis, base);
-        base += point_items(sc, it.n_snap);
+        base += point_units(sc, it.n_snap);
     }
-    b->total_items = base;
+    b->total_units = base;
     if (hipMemcpy(b->d_pjobs, pj.data(), sizeof(PairJob) * n_items, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_qjobs, qj.data(), sizeof(PointJob) * n_items, hipMemcpyHostToDevice) != hipSuccess) {
         delete b;

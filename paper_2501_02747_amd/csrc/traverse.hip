@@ -304,7 +304,8 @@ __device__ int any_hit(const SceneDev &sc, Seg s, int exA, int exB, OrderPtr ord
 //   kAbortAll      - once any lane is clear, all stop (a pair is visible as soon
 //                    as one admissible segment is clear);
 //   kAbortSameKey  - once a lane is clear, the lanes with the same key stop (a
-//                    facet is visible from a point as soon as one sample is).
+//                    facet is visible from a point as soon as one sample is; the
+//                    key names the point and the facet).
 // Returns the hit rank (>= 0), -1 clear, or -2 for a lane that did not run or
 // was stopped.
 constexpr int kAbortAll = 1, kAbortSameKey = 2;
@@ -667,10 +668,6 @@ __device__ inline bool prod_less(double a, double b, double c, double d) {
     return fma(a, b, -p) < fma(c, d, -q);
 }
 
-// Up to kSolidTries distinct verified solids among the blockers `hit` of the
-// lanes with `blocked`, appended to the wave-uniform list (oldest replaced).
-
-
 // Solid certificate.  A verified solid s is an open convex prism K (wall
 // planes and roof plane; unbounded below) whose walls and roof above its base
 // height zb are covered by triangles of its facets.  Every segment between the
@@ -1001,6 +998,40 @@ __device__ unsigned certify_solid_subpairs(const SolidLds &S, const HullLds &H, 
     const unsigned res = (unsigned)(__ballot(ok) & 0xffffull);
     wave_sync();
     return res;
+}
+
+// Fan certificate: the solid certificate with one side's hull shrunk to a
+// single sample.  Every segment from sample p of facet i to H_j passes through
+// K when (i) holds for H_i (so for p) and H_j, p and the corners of H_j have
+// z >= zb, and the segments from p to the corners of H_j pass through K (the
+// convexity argument above with H_i = {p}); the same from a sample of j to the
+// corners of H_i.  Lanes run over the (side, sample, corner) items of the
+// compacted admissible samples sp[0, np) and sq[0, nq); fi / fj get the
+// samples whose fans are certified (bit a = sp[a] / sq[a]).
+__device__ void certify_fans(const SolidLds &S, const HullLds &H, const float4 *sp, int np, const float4 *sq, int nq,
+                             double u, unsigned long long *fail, unsigned long long &fi, unsigned long long &fj,
+                             Cnt &c) {
+    fi = fj = 0ull;
+    if (S.pl[kSolidMaxPlanes].x <= 0 || H.ni == 0 || H.nj == 0 || !solid_sides(S, H, u, c)) return;
+    const int lane = lane_id();
+    if (lane < 2) fail[lane] = 0ull;
+    wave_sync();
+    const int ti = np * H.nj, total = ti + nq * H.ni;
+    for (int it = lane; it < total; it += kWave) {
+        const bool si = it < ti;
+        const int r = si ? it : it - ti;
+        const int hc = si ? H.nj : H.ni;
+        const int a = r / hc, k = r - a * hc;
+        const float4 A = si ? sp[a] : sq[a];
+        const float4 B = H.hc[(si ? kHullMax : 0) + k];
+        if (!solid_segment(S, A, B, u, c)) atomicOr(&fail[si ? 0 : 1], 1ull << a);
+    }
+    wave_sync();
+    const unsigned long long mi = np >= 64 ? ~0ull : ((1ull << np) - 1ull);
+    const unsigned long long mj = nq >= 64 ? ~0ull : ((1ull << nq) - 1ull);
+    fi = ~fail[0] & mi;
+    fj = ~fail[1] & mj;
+    wave_sync();
 }
 
 // Up to kSolidTries distinct verified solids among the blockers `hit` of the
@@ -1375,7 +1406,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     Rects &R = sR[wv];
     const bool f64 = o.fp64_only != 0;
     Cnt c;
-    unsigned segs = 0, nvis = 0, ncert = 0, nsub = 0, ntiled = 0, nsolid = 0;  // per-wave counts fit 32 bits
+    unsigned segs = 0, nvis = 0, ncert = 0, nsub = 0, ntiled = 0, nsolid = 0, nfan = 0;  // per-wave counts fit 32 bits
     const unsigned long long lt = (1ull << lane) - 1ull;
     // A wave takes a chunk of consecutive candidates at a time (same facet i,
     // neighbouring j), and keeps its recent blocker triangles and solids from
@@ -1456,7 +1487,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             pco[cl + 1] = pco[cl] + __popcll(mpc);
             qco[cl + 1] = qco[cl] + __popcll(mqc);
         }
-        const int np = pco[4], nq = qco[4];
+        int np = pco[4], nq = qco[4];
         // bounding box of every admissible segment
         float lo[3], hi[3];
         {
@@ -1556,6 +1587,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 if (!((reach_sub >> m) & 1u)) continue;
                 todo &= ~certify_solid_subpairs(sSL[wv][m], sH[wv], gsu, todo, sBits[wv], c);
                 early = todo == 0u;
+            }
+            // a pair that several solids block (no single one certifies it): fans of
+            // one sample against the other facet's hull, by each solid that reaches
+            // the bundle; a segment is blocked when either end's fan is certified, so
+            // the segment space shrinks to the samples of uncertified fans on both
+            // sides (small sample sets only: the cluster sub-pairs serve large ones)
+            if (!early && !split && reach_sub) {
+                unsigned long long ci = 0ull, cj = 0ull;
+                for (int m = 0; m < nsol; ++m) {
+                    if (!((reach_sub >> m) & 1u)) continue;
+                    unsigned long long fi, fj;
+                    certify_fans(sSL[wv][m], sH[wv], sP[wv], np, sQ[wv], nq, gsu, sBits[wv], fi, fj, c);
+                    ci |= fi;
+                    cj |= fj;
+                }
+                if (ci | cj) {
+                    const bool kp = lane < np && !((ci >> lane) & 1ull);
+                    const bool kq = lane < nq && !((cj >> lane) & 1ull);
+                    const float4 vp = sP[wv][lane < np ? lane : 0], vq = sQ[wv][lane < nq ? lane : 0];
+                    const unsigned long long bp = __ballot(kp), bq = __ballot(kq);
+                    wave_sync();
+                    if (kp) sP[wv][__popcll(bp & lt)] = vp;
+                    if (kq) sQ[wv][__popcll(bq & lt)] = vq;
+                    wave_sync();
+                    np = __popcll(bp);
+                    nq = __popcll(bq);
+                    early = np == 0 || nq == 0;
+                    ++nfan;
+                }
             }
         }
         if (early) {
@@ -1743,7 +1803,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     flush_counters(st, c, segs, nvis, 0);
     if (st && lane == 0 && ncert) atomicAdd((unsigned long long *)&st->certified, (unsigned long long)ncert);
-    if (st && lane == 0 && nsub) atomicAdd((unsigned long long *)&st->subpair_runs, (unsigned long long)nsub);
+    if (st && lane == 0 && (nsub + nfan))
+        atomicAdd((unsigned long long *)&st->subpair_runs, (unsigned long long)(nsub + nfan));
     if (st && lane == 0 && ntiled) atomicAdd((unsigned long long *)&st->tiled_pairs, (unsigned long long)ntiled);
     if (st && lane == 0 && nsolid) atomicAdd((unsigned long long *)&st->solid_certified, (unsigned long long)nsolid);
 }
@@ -2006,13 +2067,21 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
 // ---------------------------------------------------------------------------
 
 
-// Items are (job, snapshot, side, chunk of 64 consecutive samples); each wave
-// walks a contiguous range of global items so consecutive items share the Tx
-// or Rx point.  A lane first tests its sample's segment against the wave's
-// recent blockers; the misses are queued in LDS and traversed in full 64-lane
-// batches.  The queue is drained whenever the point (or the scene) changes.
-// Samples of facets already known visible are skipped (a set bit is never
-// cleared, so a stale read only costs work).
+// Work units are (job, side, chunk of 64 consecutive samples, block of
+// kSnapBlock consecutive snapshots); wave w takes units w, w + waves, ... (an
+// interleave that spreads the costly chunks, those near the trajectory, over
+// all waves).  Within a unit the wave follows its chunk of samples along the
+// trajectory from one point to the next.  A lane keeps a hint for its sample:
+// what decided it at an earlier point of the unit (a verified solid or a
+// triangle that blocked it, or clear), and a blocker hint is tested first; the
+// next point is a few centimetres away and the same blocker nearly always
+// blocks again.  A hint only orders the exact tests: every bit of every point
+// is decided by tests at that point.  The samples left then go through the
+// wave's recent blockers and solids and the point certificates, and the rest
+// into the probe and miss queues, which are traversed in full 64-lane batches
+// that mix points of the unit (an entry carries its snapshot) and are drained
+// at the unit's end.  Samples of facets already known visible from the point
+// are skipped (a set bit is never cleared, so a stale read only costs work).
 __device__ inline void remember_blockers(int *cache, int &ncache, int &cpos, unsigned long long fm, int hit) {
     for (int added = 0; fm && added < kCache; ++added) {
         const int src = __ffsll((long long)fm) - 1;
@@ -2034,15 +2103,68 @@ __device__ inline void remember_blockers(int *cache, int &ncache, int &cpos, uns
 // and the segment stays outside the prism.
 constexpr int kSolidCache = 2;
 
-// Set the visible bit of facet f for the lanes with `clear`.  Queue entries of
-// one facet are adjacent, so only a lane whose nearest clear lane below holds
-// another facet issues the atomic (repeats would only cost memory traffic).
-__device__ inline void mark_visible(uint64_t *out, bool clear, int f) {
+// A lane's hint: a verified solid (>= 0), none, clear (its sample was seen
+// from an earlier point), or triangle h (-(h + 3)).
+constexpr int kHintNone = -1, kHintClear = -2;
+constexpr int kSweptMinLeft = 8;  // points a unit must still hold for a swept certificate to be tried
+static_assert(kSnapBlock <= kWave, "a unit's points are reduced one per lane");
+constexpr int kNoUpdate = (int)0x80000000;  // (a slot of the hint-update buffer with nothing new)
+
+// The hint left by a traversal that found triangle `hit`: its facet's verified
+// solid if there is one (a solid also blocks segments that pass beside this
+// particular triangle), else the triangle.
+__device__ inline int hint_of_hit(const SceneDev &sc, int hit) {
+    const int K = sc.fsolid[__float_as_int(sc.tri[3 * hit].w)];
+    return K >= 0 ? K : -(hit + 3);
+}
+
+// Swept solid test: the segments from every point X of the box [bl, bh] to
+// sample Q pass through verified solid sid.  The box lies strictly outside one
+// face plane of the prism (tested at the corner where that plane's value is
+// least, the value being linear), so every X does; the segment from each box
+// corner to Q passes through the prism, both ends at or above the base.  For
+// fixed Q the points X whose open segment to Q meets the open prism form a
+// convex set (for X a combination of two such points, the same combination of
+// their segments' points in the prism lies on the open segment from X), so the
+// whole box is covered, and from each X the segment enters the prism at
+// 0 < t < 1, above the base, through a covered face.  The corners' coordinates
+// are those of on-grid points, so every plane value stays exact.
+__device__ bool swept_solid(const SceneDev &sc, int sid, float4 bl, float4 bh, float4 Q, Cnt &c) {
+    const double u = ldexp(1.0, sc.gs);
+    const int4 R = sc.solid[sid];
+    if (R.x <= 0) return false;
+    bool sep = false;
+    for (int k = 0; k <= R.x && !sep; ++k) {
+        ++c.solid_planes;
+        if (k < R.x) {
+            const int4 pl = sc.splane[sid * kSolidMaxPlanes + k];
+            const double x = (double)(pl.w > 0 ? bl.x : bh.x) * u, y = (double)(pl.z < 0 ? bl.y : bh.y) * u;
+            sep = (double)pl.w * (x - (double)pl.x) - (double)pl.z * (y - (double)pl.y) > 0.0;
+        } else {
+            sep = (double)bl.z * u - (double)R.y > 0.0;
+        }
+    }
+    if (!sep) return false;
+    const int nx = bl.x == bh.x ? 1 : 2, ny = bl.y == bh.y ? 1 : 2, nz = bl.z == bh.z ? 1 : 2;
+    for (int k = 0; k < nx * ny * nz; ++k) {
+        const float4 X = make_float4((k % nx) ? bh.x : bl.x, ((k / nx) % ny) ? bh.y : bl.y, (k / (nx * ny)) ? bh.z : bl.z,
+                                     0.f);
+        if (!solid_segment_global(sc, sid, X, Q, c)) return false;
+    }
+    return true;
+}
+
+// Set the visible bit of facet f in row n of the table at `base` for the lanes
+// with `clear`.  Entries of one point and facet are usually adjacent, so only a
+// lane whose nearest clear lane below holds another point or facet issues the
+// atomic (repeats would only cost memory traffic).
+__device__ inline void mark_visible(uint64_t *base, int W, bool clear, int n, int f) {
     const int lane = lane_id();
     const unsigned long long below = __ballot(clear) & ((1ull << lane) - 1ull);
     const int prev = below ? 63 - __clzll((long long)below) : lane;
-    const int fprev = __shfl(f, prev);
-    if (clear && (prev == lane || fprev != f)) atomicOr((unsigned long long *)&out[f >> 6], 1ull << (f & 63));
+    const int fprev = __shfl(f, prev), nprev = __shfl(n, prev);
+    if (clear && (prev == lane || fprev != f || nprev != n))
+        atomicOr((unsigned long long *)&base[(size_t)n * W + (f >> 6)], 1ull << (f & 63));
 }
 
 // Point certificate: every segment from X to the sample hull of facet f passes
@@ -2053,7 +2175,7 @@ __device__ inline void mark_visible(uint64_t *out, bool clear, int f) {
 // either end first; they are staged in the wave's solid cache slots.  One lane
 // per hull corner.
 __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLds *lds, int *scache, int &nsc,
-                                    int &spos, Cnt &c) {
+                                    int &spos, int &sid_out, Cnt &c) {
     const int lane = lane_id();
     const int nh = sc.fhull_n[f];
     if (nh == 0) return false;
@@ -2095,7 +2217,10 @@ __device__ bool certify_point_facet(const SceneDev &sc, int f, float4 X, SolidLd
         Cnt tmp;
         const bool good = lane < nh && solid_segment(lds[slot], X, corner, gu, tmp);
         c.solid_planes += tmp.solid_planes;
-        if (__ballot(lane < nh && !good) == 0ull) return true;
+        if (__ballot(lane < nh && !good) == 0ull) {
+            sid_out = sid;
+            return true;
+        }
     }
     return false;
 }
@@ -2167,27 +2292,30 @@ __device__ unsigned certify_point_facets(const SceneDev &sc, int nf, int f0, int
 
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_points(PointJob one, const PointJob *many, int n_jobs,
-                                                   long long n_items, TraverseOpts o, ivm_stats *st) {
+                                                   long long n_units, TraverseOpts o, ivm_stats *st) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
     __shared__ int sMiss[kWavesPerBlock][2 * kWave];
     __shared__ SolidLds sSL[kWavesPerBlock][kSolidCache];
     __shared__ int sList[kWavesPerBlock][kCache + kSolidCache];
-    // probe queue [0, np): probe sample, the facet's other missing samples of the
-    // chunk (bits from the chunk's first sample); then [np, np + nexp): facets whose
-    // probe was blocked, with the blocking triangle in place of the sample
+    // probe queue [0, np): the probe sample (snapshot * 64 + lane) and the facet's
+    // other missing samples at that snapshot (lane bits); then [np, np + nexp):
+    // facets whose probe was blocked, with the blocking triangle in place of the
+    // sample.  Miss queue entries are snapshot * 64 + lane.
     __shared__ int sProbe[kWavesPerBlock][2 * kWave];
     __shared__ unsigned long long sPMask[kWavesPerBlock][2 * kWave];
-    __shared__ int sPBase[kWavesPerBlock][2 * kWave];
-    const int wv = threadIdx.x >> 6, lane = lane_id();
+    __shared__ int sPSnap[kWavesPerBlock][2 * kWave];
+    __shared__ int sUpd[kWavesPerBlock][kWave];  // hints found by a traversal batch, by sample lane
+    // (the wave index made explicitly wave-uniform: everything derived from it
+    // then lives in scalar registers)
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = lane_id();
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
     const bool f64 = o.fp64_only != 0;
-    // Each wave takes a contiguous range of items.  Workgroups are dispatched to
-    // the XCDs round-robin; with xcd_parts ranges the waves of one XCD take
-    // consecutive ranges (consecutive snapshots: nearby points, whose scene data
-    // then stays in that XCD's L2).
+    // Workgroups are dispatched to the XCDs round-robin; with xcd_parts the waves
+    // of one XCD take neighbouring units (nearby chunks and snapshots, whose
+    // scene data then stays in that XCD's L2).
     const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
     long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
     const int xp = o.xcd_parts;
@@ -2196,8 +2324,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         wave = (long long)(blockIdx.x % (unsigned)xp) * per_part + (long long)(blockIdx.x / (unsigned)xp) * kWavesPerBlock +
                wv;
     }
-    const long long per = (n_items + nwaves - 1) / nwaves;
-    const long long it0 = wave * per, it1 = min(n_items, it0 + per);
     const unsigned long long lt = (1ull << lane) - 1ull;
     Cnt c;
     unsigned long long segs = 0, items = 0;
@@ -2205,228 +2331,306 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     int ncache = 0, cpos = 0, nmiss = 0, n_order = 0;
     unsigned long long nsolidf = 0;  // (point, facet) pairs certified by a solid
     int nsc = 0, spos = 0;
-    long long cur = -1;  // current (job, snapshot, side)
-    int cur_job = 0;
-    float xx = 0.f, xy = 0.f, xz = 0.f;
-    uint64_t *out = nullptr;
     int np = 0, nexp = 0;
     const bool probing = !o.exhaustive;
-    // Runs the traversals the queues call for, from X: full batches of misses;
-    // the other missing samples of a facet whose probe was blocked (less those
-    // the probe's blocking triangle also blocks) into the miss queue; batches of
-    // up to 64 probes, one sample per facet, where a clear probe shows its facet
-    // visible at once.  `fin` empties the queues.
-    auto pump = [&](const SceneDev &S, bool fin) __attribute__((always_inline)) {
+    sUpd[wv][lane] = kNoUpdate;
+    // the current unit's chunk and side, and its job's points and table (row 0)
+    int cur_chunk = 0, cur_side = 0;
+    const float *pts = nullptr;
+    uint64_t *out = nullptr;
+    int hint = kHintNone;
+    float xx = 0.f, xy = 0.f, xz = 0.f;  // the current point
+    long long pt = 0, ord_pt = -1;       // the current point (a wave-local count), the point sOrder was ranked for
+    // Runs the traversals the queues call for: full batches of misses; the other
+    // missing samples of a facet whose probe was blocked (less those the probe's
+    // blocking triangle also blocks) into the miss queue; batches of up to 64
+    // probes, one sample per (point, facet), where a clear probe shows its facet
+    // visible from its point at once.  `fin` empties the queues.
+    auto pump = [&](const PointJob &JK, bool fin) __attribute__((always_inline)) {
+        const SceneDev &S = JK.sc;
+        const int base = cur_chunk * kWave;
         while (true) {
             const bool do_miss = nmiss >= kWave || (fin && nmiss > 0 && nexp == 0);
             if (!do_miss && nexp > 0) {
                 const int e = np + nexp - 1;
                 const unsigned long long m = sPMask[wv][e];
-                const int base = sPBase[wv][e], h = sProbe[wv][e];
+                const int h = sProbe[wv][e], ne = sPSnap[wv][e];
                 --nexp;
                 bool keep = (m >> lane) & 1ull;
                 if (keep) {
-                    const float4 P3 = S.smp[base + lane];
-                    const Seg sg3 = make_seg(xx, xy, xz, P3.x, P3.y, P3.z);
+                    const float *X = pts + 3 * ne;
+                    const float4 P = S.smp[base + lane];
+                    const Seg sg3 = make_seg(X[0], X[1], X[2], P.x, P.y, P.z);
                     ++c.tests;
                     keep = !tri_hit(sg3, S.tri[3 * h], S.tri[3 * h + 1], S.tri[3 * h + 2], o.eps6, f64, c.rechecks);
+                    if (!keep) hint = hint_of_hit(S, h);
                 }
                 const unsigned long long km = __ballot(keep);
-                if (keep) miss[nmiss + __popcll(km & lt)] = base + lane;
+                if (keep) miss[nmiss + __popcll(km & lt)] = ne * kWave + lane;
                 nmiss += __popcll(km);
                 wave_sync();
                 continue;
             }
             if (!do_miss && !(np >= kWave || (fin && np > 0))) break;
+            if (ord_pt != pt) {
+                // treelet order for the current point, nearest treelet box first (a
+                // heuristic only; the batch's other points are close by)
+                ord_pt = pt;
+                const float xq[3] = {xx, xy, xz};
+                const int mode = o.order_mode == IVM_ORDER_LEARNED ? IVM_ORDER_PLAIN : o.order_mode;
+                unsigned long long tk = ~0ull;
+                if (lane < kTreelets && S.tl_root[lane] != kNone) {
+                    const float *b = S.tl_box + 6 * lane;
+                    float d2 = 0.f;
+                    for (int q = 0; q < 3; ++q) {
+                        const float cq = fmaxf(fmaxf(b[q] - xq[q], xq[q] - b[3 + q]), 0.f);
+                        d2 += cq * cq;
+                    }
+                    const unsigned dk = __float_as_uint(d2);
+                    tk = mode == IVM_ORDER_INDEX ? (unsigned long long)lane
+                         : (mode == IVM_ORDER_REVERSED ? (unsigned long long)(0xffffffffu - dk) : dk);
+                }
+                n_order = wave_rank_order(tk, sKey[wv], sOrder[wv]);
+            }
             const int k = min(kWave, do_miss ? nmiss : np);
             const bool act = lane < k;
             const int q = (do_miss ? nmiss : np) - (act ? k - lane : 1);
-            const int s2 = do_miss ? miss[q] : sProbe[wv][q];
+            const int code = do_miss ? miss[q] : sProbe[wv][q];
             const unsigned long long pm = do_miss || !act ? 0ull : sPMask[wv][q];
-            const int pb = do_miss ? 0 : sPBase[wv][q];
-            const int f = S.sfacet[s2];
-            const float4 P = S.smp[s2];
-            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+            const int ne = code >> 6, sl = code & (kWave - 1);
+            const int f = S.sfacet[base + sl];
+            const float4 Pq = S.smp[base + sl];
+            const float *X = pts + 3 * ne;
+            const Seg sg = make_seg(X[0], X[1], X[2], Pq.x, Pq.y, Pq.z);
             if (act) ++c.traversed;
+            // (the key names the point and the facet: the facet by its first sample's lane in the chunk)
+            const int key_pf = (ne << 6) | max(S.soff[f] - base, 0);
             const int hit = any_hit_wave(S, sg, act, f, f, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c,
-                                         kAbortSameKey, f);
+                                         kAbortSameKey, key_pf);
             const bool clear = hit == -1;
             if (do_miss) nmiss -= k;
             else np -= k;
             wave_sync();
-            mark_visible(out, clear, f);
+            mark_visible(out, S.W, clear, ne, f);
+            if (act && (clear || hit >= 0)) sUpd[wv][sl] = clear ? kHintClear : hint_of_hit(S, hit);
             remember_blockers(cache, ncache, cpos, __ballot(hit >= 0), hit);
             if (S.n_solids > 0) remember_solid_ids(S, scache, nsc, spos, sSL[wv], kSolidCache, hit >= 0, hit);
             if (!do_miss) {
-                // (a facet cut by a chunk boundary has two probes: a clear one settles both)
+                // (another probe of the same point and facet that is clear settles it)
                 bool vis = clear;
-                for (unsigned long long cm = __ballot(clear); cm; cm &= cm - 1)
-                    vis |= __shfl(f, __ffsll((long long)cm) - 1) == f;
+                for (unsigned long long cm = __ballot(clear); cm; cm &= cm - 1) {
+                    const int src = __ffsll((long long)cm) - 1;
+                    vis |= __shfl(f, src) == f && __shfl(ne, src) == ne;
+                }
                 const bool blk = act && hit >= 0 && !vis && pm != 0ull;
                 const unsigned long long bm = __ballot(blk);
                 if (blk) {
                     const int pos = np + __popcll(bm & lt);
                     sProbe[wv][pos] = hit;
                     sPMask[wv][pos] = pm;
-                    sPBase[wv][pos] = pb;
+                    sPSnap[wv][pos] = ne;
                 }
                 nexp = __popcll(bm);
-                wave_sync();
             }
+            wave_sync();
+            // the batch's hints go to the lanes that own the samples
+            const int u = sUpd[wv][lane];
+            if (u != kNoUpdate) {
+                hint = u;
+                sUpd[wv][lane] = kNoUpdate;
+            }
+            wave_sync();
         }
     };
-    for (long long it = it0; it <= it1; ++it) {
-        const bool more = it < it1;
-        long long key = -1;
-        int js = 0, chunk = 0;
-        if (more) {
-            if (MULTI) {
-                int lo = 0, hi = n_jobs - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (many[mid].item_base <= it) lo = mid;
-                    else hi = mid - 1;
-                }
-                js = lo;
+    for (long long u = wave; u < n_units; u += nwaves) {
+        int js = 0;
+        if (MULTI) {
+            int lo = 0, hi = n_jobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (many[mid].unit_base <= u) lo = mid;
+                else hi = mid - 1;
             }
-            const PointJob &J = MULTI ? many[js] : one;
-            const int nch = (J.sc.S + kWave - 1) / kWave;
-            const long long local = it - J.item_base;
-            const int n = (int)(local / (2 * nch));
-            const int rem = (int)(local - (long long)n * 2 * nch);
-            const int side = rem / nch;
-            chunk = rem - side * nch;
-            key = ((long long)js << 32) | (long long)(2 * n + side);
+            js = lo;
         }
-        // drain the queues when the point changes (or at the end)
-        if (key != cur && (np > 0 || nmiss > 0)) pump(MULTI ? many[cur_job].sc : one.sc, true);
-        if (!more) break;
         const PointJob &J = MULTI ? many[js] : one;
         const SceneDev &sc = J.sc;
-        if (key != cur) {
-            cur = key;
-            cur_job = js;
-            const int n = (int)(key & 0xffffffff) >> 1, side = (int)(key & 1);
-            const float *X = (side ? J.rx : J.tx) + 3 * n;
-            xx = X[0]; xy = X[1]; xz = X[2];
-            out = (side ? J.rxv : J.txv) + (size_t)n * sc.W;
-            ncache = 0;
-            cpos = 0;
-            nsc = 0;
-            spos = 0;
-            // treelet order for this point: nearest treelet box first (a heuristic only)
-            const float xp[3] = {xx, xy, xz};
-            const int mode = o.order_mode == IVM_ORDER_LEARNED ? IVM_ORDER_PLAIN : o.order_mode;
-            unsigned long long tk = ~0ull;
-            if (lane < kTreelets && sc.tl_root[lane] != kNone) {
-                const float *b = sc.tl_box + 6 * lane;
-                float d2 = 0.f;
-                for (int q = 0; q < 3; ++q) {
-                    const float cq = fmaxf(fmaxf(b[q] - xp[q], xp[q] - b[3 + q]), 0.f);
-                    d2 += cq * cq;
-                }
-                const unsigned dk = __float_as_uint(d2);
-                tk = mode == IVM_ORDER_INDEX ? (unsigned long long)lane
-                     : (mode == IVM_ORDER_REVERSED ? (unsigned long long)(0xffffffffu - dk) : dk);
-            }
-            n_order = wave_rank_order(tk, sKey[wv], sOrder[wv]);
+        const int N = J.N, nb = (N + kSnapBlock - 1) / kSnapBlock, nch = (sc.S + kWave - 1) / kWave;
+        const long long local = u - J.unit_base;
+        const int kx = (int)(local / nb), blk = (int)(local - (long long)kx * nb);
+        cur_side = kx / nch;
+        cur_chunk = kx - cur_side * nch;
+        pts = cur_side ? J.rx : J.tx;
+        out = cur_side ? J.rxv : J.txv;
+        ncache = cpos = nsc = spos = 0;
+        hint = kHintNone;
+        const int sidx = cur_chunk * kWave + lane;
+        const int fl = sidx < sc.S ? sc.sfacet[sidx] : -1;  // the facet of this lane's sample (-1 = none)
+        const int own = fl >= 0 ? sc.fsolid[fl] : -1;       // the solid the sample's facet belongs to
+        const int n0 = blk * kSnapBlock, n1 = min(N, n0 + kSnapBlock);
+        // the box of the unit's points, for swept certificates: a lane whose hint
+        // solid blocks its sample from the whole box skips the unit's other points
+        float4 bl, bh;
+        {
+            const bool in = lane < n1 - n0;
+            const float *Xb = pts + 3 * (in ? n0 + lane : n0);
+            // (wave-uniform: kept in scalar registers)
+            auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+            bl = make_float4(uni(wave_min(Xb[0])), uni(wave_min(Xb[1])), uni(wave_min(Xb[2])), 0.f);
+            bh = make_float4(uni(wave_max(Xb[0])), uni(wave_max(Xb[1])), uni(wave_max(Xb[2])), 0.f);
         }
-        const int sidx = chunk * kWave + lane;
-        bool need = false;
-        if (sidx < sc.S) {
-            const int f = sc.sfacet[sidx];
-            need = orient(sc.fplane + 6 * f, xx, xy, xz) > 0.0 && !((out[f >> 6] >> (f & 63)) & 1ull);
-            if (need) {
-                ++segs;
-                for (int m = 0; m < nsc && need && !o.exhaustive; ++m) {
-                    if (solid_segment(sSL[wv][m], make_float4(xx, xy, xz, 0.f), sc.smp[sidx], ldexp(1.0, sc.gs), c)) {
-                        need = false;
-                        ++c.solid_segs;
-                    }
-                }
-                if (need && ncache > 0 && !o.exhaustive) {
-                    const float4 P = sc.smp[sidx];
-                    const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
-                    for (int k = 0; k < ncache && need; ++k) {
-                        const int r = cache[k];
-                        if (__float_as_int(sc.tri[3 * r].w) == f) continue;
+        bool swept = false, tried = false;
+        for (int n = n0; n < n1; ++n) {
+            xx = pts[3 * n];
+            xy = pts[3 * n + 1];
+            xz = pts[3 * n + 2];
+            ++pt;
+            const float4 X4 = make_float4(xx, xy, xz, 0.f);
+            const uint64_t *row = out + (size_t)n * sc.W;
+            bool need = false;
+            const float4 P = fl >= 0 ? (float4)sc.smp[sidx] : make_float4(0.f, 0.f, 0.f, 0.f);
+            bool by_solid = false;  // decided by a solid at this point
+            if (fl >= 0 && !swept) {
+                need = orient(sc.fplane + 6 * fl, xx, xy, xz) > 0.0 && !((row[fl >> 6] >> (fl & 63)) & 1ull);
+                if (need && !o.exhaustive) {
+                    ++segs;
+                    // the hint first
+                    if (hint >= 0) {
+                        if (solid_segment_global(sc, hint, X4, P, c)) {
+                            need = false;
+                            by_solid = true;
+                            ++c.solid_segs;
+                        } else {
+                            hint = kHintNone;
+                        }
+                    } else if (hint <= -3) {
+                        const int r = -(hint + 3);
+                        const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
                         ++c.tests;
                         if (tri_hit(sg, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], o.eps6, f64, c.rechecks))
                             need = false;
+                        else
+                            hint = kHintNone;
                     }
+                    // then the wave's recent solids and blockers
+                    for (int m = 0; m < nsc && need; ++m) {
+                        if (solid_segment(sSL[wv][m], X4, P, ldexp(1.0, sc.gs), c)) {
+                            need = false;
+                            by_solid = true;
+                            hint = scache[m];
+                            ++c.solid_segs;
+                        }
+                    }
+                    if (need && ncache > 0) {
+                        const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+                        for (int k = 0; k < ncache && need; ++k) {
+                            const int r = cache[k];
+                            if (__float_as_int(sc.tri[3 * r].w) == fl) continue;
+                            ++c.tests;
+                            if (tri_hit(sg, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], o.eps6, f64, c.rechecks)) {
+                                need = false;
+                                hint = -(r + 3);
+                            }
+                        }
+                    }
+                } else if (need) {
+                    ++segs;
                 }
             }
-        }
-        unsigned long long nm = __ballot(need);
-        // a facet left with misses: try to prove it blocked from X by a solid of the scene
-        if (nm && !o.exhaustive && sc.n_solids > 0 && sc.n_solids <= kScanMaxSolidsPoint) {
-            const int fl = sidx < sc.S ? sc.sfacet[sidx] : -1;
-            unsigned long long left = nm;
-            while (left) {
-                // up to four facets at once, one lane group each
-                int fq0 = -1, fq1 = -1, fq2 = -1, fq3 = -1;
-                int nf = 0;
-                for (; nf < 4 && left; ++nf) {
-                    const int fc = __shfl(fl, __ffsll((long long)left) - 1);
-                    left &= ~__ballot(need && fl == fc);
-                    if (nf == 0) fq0 = fc;
-                    else if (nf == 1) fq1 = fc;
-                    else if (nf == 2) fq2 = fc;
-                    else fq3 = fc;
+            // one swept certificate per lane and unit, while enough points remain
+            if (by_solid && !tried && hint != own && n + kSweptMinLeft < n1) {
+                tried = true;
+                swept = swept_solid(sc, hint, bl, bh, P, c);
+            }
+            unsigned long long nm = __ballot(need);
+            // a facet left with misses: try to prove it blocked from X by a solid of the
+            // scene (not a facet seen from an earlier point: it goes to its probe)
+            if (nm && !o.exhaustive && sc.n_solids > 0 && sc.n_solids <= kScanMaxSolidsPoint) {
+                bool seen = false;
+                for (unsigned long long hc = __ballot(need && hint == kHintClear); hc;) {
+                    const int fc = __shfl(fl, __ffsll((long long)hc) - 1);
+                    seen |= fl == fc;
+                    hc &= ~__ballot(fl == fc);
                 }
-                const float4 Xp = make_float4(xx, xy, xz, 0.f);
-                if (nf == 1) {
-                    if (certify_point_facet(sc, fq0, Xp, sSL[wv], scache, nsc, spos, c)) {
-                        if (fl == fq0) need = false;
-                        ++nsolidf;
+                unsigned long long left = nm & ~__ballot(seen);
+                while (left) {
+                    // up to four facets at once, one lane group each
+                    int fq0 = -1, fq1 = -1, fq2 = -1, fq3 = -1;
+                    int nf = 0;
+                    for (; nf < 4 && left; ++nf) {
+                        const int fc = __shfl(fl, __ffsll((long long)left) - 1);
+                        left &= ~__ballot(need && fl == fc);
+                        if (nf == 0) fq0 = fc;
+                        else if (nf == 1) fq1 = fc;
+                        else if (nf == 2) fq2 = fc;
+                        else fq3 = fc;
                     }
-                } else {
-                    int sid_g;
-                    const unsigned ok = certify_point_facets(sc, nf, fq0, fq1, fq2, fq3, Xp, scache, nsc, sid_g, c);
-                    const int gs = nf <= 2 ? 32 : 16;
-                    for (int q = 0; q < nf; ++q) {
-                        if (!((ok >> q) & 1u)) continue;
-                        const int fcq = q == 0 ? fq0 : (q == 1 ? fq1 : (q == 2 ? fq2 : fq3));
-                        if (fl == fcq) need = false;
-                        ++nsolidf;
-                        // the certifying solid joins the wave's solid cache
-                        const int sid = __shfl(sid_g, q * gs);
-                        bool cached = false;
-                        for (int m = 0; m < nsc; ++m) cached |= scache[m] == sid;
-                        if (!cached) {
-                            int slot;
-                            if (nsc < kSolidCache) slot = nsc++;
-                            else { slot = spos; spos = (spos + 1) % kSolidCache; }
-                            scache[slot] = sid;
-                            stage_solid(sc, sid, sSL[wv][slot]);
+                    if (nf == 1) {
+                        int sid = -1;
+                        if (certify_point_facet(sc, fq0, X4, sSL[wv], scache, nsc, spos, sid, c)) {
+                            if (fl == fq0 && need) {
+                                need = false;
+                                hint = sid;
+                            }
+                            ++nsolidf;
+                        }
+                    } else {
+                        int sid_g;
+                        const unsigned ok = certify_point_facets(sc, nf, fq0, fq1, fq2, fq3, X4, scache, nsc, sid_g, c);
+                        const int gs = nf <= 2 ? 32 : 16;
+                        for (int q = 0; q < nf; ++q) {
+                            if (!((ok >> q) & 1u)) continue;
+                            const int fcq = q == 0 ? fq0 : (q == 1 ? fq1 : (q == 2 ? fq2 : fq3));
+                            // the certifying solid joins the wave's solid cache
+                            const int sid = __shfl(sid_g, q * gs);
+                            if (fl == fcq && need) {
+                                need = false;
+                                hint = sid;
+                            }
+                            ++nsolidf;
+                            bool cached = false;
+                            for (int m = 0; m < nsc; ++m) cached |= scache[m] == sid;
+                            if (!cached) {
+                                int slot;
+                                if (nsc < kSolidCache) slot = nsc++;
+                                else { slot = spos; spos = (spos + 1) % kSolidCache; }
+                                scache[slot] = sid;
+                                stage_solid(sc, sid, sSL[wv][slot]);
+                            }
                         }
                     }
                 }
+                nm = __ballot(need);
             }
-            nm = __ballot(need);
-        }
-        if (nm) ++items;
-        if (probing) {
-            // one probe per facet left with misses: its middle missing sample
-            // (np < 64 here, and a chunk adds at most 64)
-            const int fl = sidx < sc.S ? sc.sfacet[sidx] : -1;
-            for (unsigned long long left = nm; left;) {
-                const int fc = __shfl(fl, __ffsll((long long)left) - 1);
-                const unsigned long long mf = __ballot(need && fl == fc);
-                left &= ~mf;
-                if (need && fl == fc && __popcll(mf & lt) == (__popcll(mf) >> 1)) {
-                    sProbe[wv][np] = sidx;
-                    sPMask[wv][np] = mf & ~(1ull << lane);
-                    sPBase[wv][np] = chunk * kWave;
+            if (nm) ++items;
+            if (probing) {
+                // one probe per facet left with misses: the sample seen from an earlier
+                // point if there is one, else the middle missing sample (np < 64 here,
+                // and a chunk adds at most 64)
+                for (unsigned long long left = nm; left;) {
+                    const int fc = __shfl(fl, __ffsll((long long)left) - 1);
+                    const bool mine = need && fl == fc;
+                    const unsigned long long mf = __ballot(mine);
+                    left &= ~mf;
+                    const unsigned long long mc = __ballot(mine && hint == kHintClear);
+                    const unsigned long long mm = __ballot(mine && __popcll(mf & lt) == (__popcll(mf) >> 1));
+                    const int pick = __ffsll((long long)(mc ? mc : mm)) - 1;
+                    if (lane == pick) {
+                        sProbe[wv][np] = n * kWave + lane;
+                        sPMask[wv][np] = mf & ~(1ull << lane);
+                        sPSnap[wv][np] = n;
+                    }
+                    ++np;
                 }
-                ++np;
+            } else {
+                if (need) miss[nmiss + __popcll(nm & lt)] = n * kWave + lane;
+                nmiss += __popcll(nm);
             }
-        } else {
-            if (need) miss[nmiss + __popcll(nm & lt)] = sidx;
-            nmiss += __popcll(nm);
+            wave_sync();
+            pump(J, false);
         }
-        wave_sync();
-        pump(sc, false);
+        // drain the queues at the unit's end
+        if (np > 0 || nmiss > 0) pump(J, true);
     }
     flush_counters(st, c, segs, 0, items);
     if (st && lane == 0 && nsolidf) atomicAdd((unsigned long long *)&st->solid_certified, nsolidf);
@@ -2467,13 +2671,14 @@ __global__ void k_check_points(SceneDev sc, int N, const float *tx, const float 
     if (bad) atomicOr(sc.status, bad);
 }
 
-long long point_items(const Scene &scn, int N) {
+// Work units of the Tx/Rx kernel: (side, chunk of 64 samples, block of kSnapBlock snapshots).
+long long point_units(const Scene &scn, int N) {
     const int nch = (scn.dev.S + kWave - 1) / kWave;
-    return (scn.dev.S > 0 && scn.dev.F > 0) ? (long long)N * 2 * nch : 0;
+    return (scn.dev.S > 0 && scn.dev.F > 0 && N > 0) ? (long long)2 * nch * ((N + kSnapBlock - 1) / kSnapBlock) : 0;
 }
 
 PointJob make_point_job(Scene &scn, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
-                        long long item_base) {
+                        long long unit_base) {
     PointJob j;
     j.sc = scn.dev;
     j.N = N;
@@ -2481,7 +2686,7 @@ PointJob make_point_job(Scene &scn, int N, const float *tx, const float *rx, uin
     j.rx = rx;
     j.txv = txv;
     j.rxv = rxv;
-    j.item_base = item_base;
+    j.unit_base = unit_base;
     return j;
 }
 
@@ -2736,11 +2941,11 @@ hipError_t launch_edge_rows(Scene &scn, const TraverseOpts &o, int E, int s, con
     return hipGetLastError();
 }
 
-hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_items, const TraverseOpts &o,
+hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_units, const TraverseOpts &o,
                              ivm_stats *stats, hipStream_t s) {
-    if (total_items <= 0) return hipSuccess;
+    if (total_units <= 0) return hipSuccess;
     PointJob none{};
-    hipLaunchKernelGGL(k_points<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, n_jobs, total_items, o,
+    hipLaunchKernelGGL(k_points<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, n_jobs, total_units, o,
                        stats);
     return hipGetLastError();
 }
@@ -2751,11 +2956,11 @@ hipError_t launch_points(Scene &scn, const TraverseOpts &o, int N, const float *
     if ((e = launch_points_prep(scn, N, tx, rx, txv, rxv, s)) != hipSuccess) return e;
     if (N == 0) return hipSuccess;
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
-    const long long items = point_items(scn, N);
-    if (items > 0) {
+    const long long units = point_units(scn, N);
+    if (units > 0) {
         const PointJob job = make_point_job(scn, N, tx, rx, txv, rxv, 0);
         hipLaunchKernelGGL(k_points<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PointJob *)nullptr, 1,
-                           items, o, stats);
+                           units, o, stats);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (o.events && (e = hipEventRecord(o.events[1], s)) != hipSuccess) return e;
