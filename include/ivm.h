@@ -40,9 +40,11 @@
  *     stream has been synchronised.
  *   - Hot calls (matrix, table, candidates in count mode) allocate no device
  *     memory; all device state lives in the caller-provided scene workspace.
- *   - Read-only calls on one scene (table, candidates) may run concurrently on
- *     different streams; ivm_intervisibility_matrix uses the scene's scratch
- *     area and must not overlap another matrix call on the same scene.
+ *   - Calls on one scene that only read it (candidates, relations, angles,
+ *     ranges, edges, path validation) may run concurrently on different
+ *     streams; ivm_intervisibility_matrix and ivm_txrx_visibility_table use the
+ *     scene's scratch area (work queues) and must not overlap a matrix or table
+ *     call on the same scene.
  *   - Bit layout of every facet bit set: bit j of row r is word j >> 6, bit
  *     j & 63, of row r; rows have W = ceil(F / 64) uint64 words; padding bits
  *     are zero.

@@ -83,7 +83,7 @@ hipError_t record(ivm_batch *b, hipStream_t s) {
             hipSuccess)
             return e;
     }
-    if ((e = launch_point_jobs(b->d_qjobs, b->n, b->total_units, b->o, b->stats, s)) != hipSuccess) return e;
+    if ((e = launch_point_jobs(b->d_qjobs, b->n, b->total_units, b->d_queue, b->o, b->stats, s)) != hipSuccess) return e;
     for (int k = 0; k < b->n; ++k) {
         const ivm_batch_item &it = b->items[k];
         if ((e = launch_los(it.scene->s, b->o, it.n_snap, it.d_tx, it.d_rx, it.d_los, s)) != hipSuccess) return e;
@@ -143,14 +143,20 @@ ivm_status ivm_batch_create(int32_t n_items, const ivm_batch_item *items, const 
     b->exec = nullptr;
     std::vector<PairJob> pj(n_items);
     std::vector<PointJob> qj(n_items);
+    std::vector<int> jS(n_items), jN(n_items);
+    for (int k = 0; k < n_items; ++k) {
+        jS[k] = items[k].scene->s.dev.S;
+        jN[k] = items[k].n_snap;
+    }
+    const int U = point_unit_len(jS.data(), jN.data(), n_items, b->o.grid_blocks);
     long long base = 0;
     const bool learned = b->o.order_mode == IVM_ORDER_LEARNED;
     for (int k = 0; k < n_items; ++k) {
         const ivm_batch_item &it = items[k];
         Scene &sc = it.scene->s;
         pj[k] = make_pair_job(sc, it.d_M, learned && sc.model != nullptr);
-        qj[k] = make_point_job(sc, it.n_snap, it.d_tx, it.d_rx, it.d_tx_vis, it.d_rx_vis, base);
-        base += point_units(sc, it.n_snap);
+        qj[k] = make_point_job(sc, it.n_snap, it.d_tx, it.d_rx, it.d_tx_vis, it.d_rx_vis, base, U);
+        base += point_units(sc, it.n_snap, U);
     }
     b->total_units = base;
     if (hipMemcpy(b->d_pjobs, pj.data(), sizeof(PairJob) * n_items, hipMemcpyHostToDevice) != hipSuccess ||

@@ -189,6 +189,7 @@ struct TraverseOpts {
 // kQueuePairs, probe round r's at kQueueProbe + kXcdParts r.
 constexpr int kXcdParts = 8;
 constexpr int kQueuePairs = 8, kQueueProbe = 16;
+constexpr int kQueuePoints = 32;  // the Tx/Rx kernel's 64-bit work-unit counter (slots 32 and 33)
 
 // Traversal options from the public ones (defaults and clamping).
 TraverseOpts make_opts(const ivm_matrix_opts *o);
@@ -213,6 +214,7 @@ struct PointJob {
     const float *tx, *rx;
     uint64_t *txv, *rxv;
     long long unit_base;      // first global work unit of this job
+    int U;                    // snapshots per work unit (a multiple of kSweptBlock)
 };
 
 // Launchers (each returns hipSuccess or the launch error).
@@ -262,7 +264,8 @@ hipError_t ranges_scratch(void **out);
 hipError_t launch_ranges(const SceneDev &sc, int N, const uint64_t *tv, const uint64_t *rv, const uint8_t *los,
                          const float *tx, const float *rx, double dt, void *ws, int *events, int *starts, double *tc,
                          double *dist, int *n_ranges, double *mean, hipStream_t s);
-constexpr int kSnapBlock = 32;   // consecutive snapshots of one sample chunk in a Tx/Rx work unit
+constexpr int kSweptBlock = 32;  // points per box of a swept certificate in the Tx/Rx kernel
+constexpr int kUnitMax = 512;    // most consecutive snapshots of one sample chunk in a Tx/Rx work unit
 constexpr int kProbeRounds = 2;  // probe passes over the candidate pairs before the pair kernel
 hipError_t launch_undecided(Scene &scn, uint64_t *M, hipStream_t s);
 hipError_t launch_probe_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n_jobs, uint32_t *d_queue, int round,
@@ -272,7 +275,8 @@ hipError_t launch_pair_jobs(const PairJob *d_jobs, const uint32_t *d_base, int n
 hipError_t launch_job_base(const PairJob *d_jobs, int n_jobs, uint32_t *d_base, bool undecided, hipStream_t s);
 hipError_t launch_points_prep(Scene &sc, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
                               hipStream_t s);
-hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_units, const TraverseOpts &o,
+hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_units, uint32_t *d_queue,
+                             const TraverseOpts &o,
                              ivm_stats *stats, hipStream_t s);
 // Edge visibility from Tx/Rx positions (first-order diffraction) and the
 // per-snapshot counts of edges seen from both ends (counts may be null).
@@ -291,8 +295,9 @@ hipError_t launch_los(Scene &sc, const TraverseOpts &o, int N, const float *tx, 
                       hipStream_t s);
 PairJob make_pair_job(Scene &sc, uint64_t *M, bool learned);
 PointJob make_point_job(Scene &sc, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
-                        long long unit_base);
-long long point_units(const Scene &sc, int N);
+                        long long unit_base, int U);
+long long point_units(const Scene &sc, int N, int U);
+int point_unit_len(const int *S, const int *N, int n_jobs, int grid_blocks);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 

@@ -2067,10 +2067,10 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
 // ---------------------------------------------------------------------------
 
 
-// Work units are (job, side, chunk of 64 consecutive samples, block of
-// kSnapBlock consecutive snapshots); wave w takes units w, w + waves, ... (an
-// interleave that spreads the costly chunks, those near the trajectory, over
-// all waves).  Within a unit the wave follows its chunk of samples along the
+// Work units are (job, side, chunk of 64 consecutive samples, block of U
+// consecutive snapshots); a wave takes the next unit from a counter
+// until none is left (units differ in cost by orders of magnitude: chunks of
+// facets seen from the trajectory need traversals).  Within a unit the wave follows its chunk of samples along the
 // trajectory from one point to the next.  A lane keeps a hint for its sample:
 // what decided it at an earlier point of the unit (a verified solid or a
 // triangle that blocked it, or clear), and a blocker hint is tested first; the
@@ -2080,7 +2080,7 @@ hipError_t launch_matrix(Scene &scn, const TraverseOpts &o, uint64_t *M, ivm_sta
 // wave's recent blockers and solids and the point certificates, and the rest
 // into the probe and miss queues, which are traversed in full 64-lane batches
 // that mix points of the unit (an entry carries its snapshot) and are drained
-// at the unit's end.  Samples of facets already known visible from the point
+// at the unit's end.  Swept certificates cover kSweptBlock points at a time.  Samples of facets already known visible from the point
 // are skipped (a set bit is never cleared, so a stale read only costs work).
 __device__ inline void remember_blockers(int *cache, int &ncache, int &cpos, unsigned long long fm, int hit) {
     for (int added = 0; fm && added < kCache; ++added) {
@@ -2107,7 +2107,7 @@ constexpr int kSolidCache = 2;
 // from an earlier point), or triangle h (-(h + 3)).
 constexpr int kHintNone = -1, kHintClear = -2;
 constexpr int kSweptMinLeft = 8;  // points a unit must still hold for a swept certificate to be tried
-static_assert(kSnapBlock <= kWave, "a unit's points are reduced one per lane");
+static_assert(kSweptBlock <= kWave, "a swept box's points are reduced one per lane");
 constexpr int kNoUpdate = (int)0x80000000;  // (a slot of the hint-update buffer with nothing new)
 
 // The hint left by a traversal that found triangle `hit`: its facet's verified
@@ -2292,7 +2292,8 @@ __device__ unsigned certify_point_facets(const SceneDev &sc, int nf, int f0, int
 
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_points(PointJob one, const PointJob *many, int n_jobs,
-                                                   long long n_units, TraverseOpts o, ivm_stats *st) {
+                                                   long long n_units, unsigned long long *counter, TraverseOpts o,
+                                                   ivm_stats *st) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
@@ -2313,17 +2314,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     int *stk = &sStack[wv][lane];
     int *miss = sMiss[wv];
     const bool f64 = o.fp64_only != 0;
-    // Workgroups are dispatched to the XCDs round-robin; with xcd_parts the waves
-    // of one XCD take neighbouring units (nearby chunks and snapshots, whose
-    // scene data then stays in that XCD's L2).
-    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-    long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
-    const int xp = o.xcd_parts;
-    if (xp > 1 && gridDim.x % (unsigned)xp == 0) {
-        const long long per_part = (long long)(gridDim.x / (unsigned)xp) * kWavesPerBlock;
-        wave = (long long)(blockIdx.x % (unsigned)xp) * per_part + (long long)(blockIdx.x / (unsigned)xp) * kWavesPerBlock +
-               wv;
-    }
     const unsigned long long lt = (1ull << lane) - 1ull;
     Cnt c;
     unsigned long long segs = 0, items = 0;
@@ -2442,7 +2432,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             wave_sync();
         }
     };
-    for (long long u = wave; u < n_units; u += nwaves) {
+    while (true) {
+        unsigned long long ut = 0ull;
+        if (lane == 0) ut = atomicAdd(counter, 1ull);
+        const long long u = (long long)__shfl(ut, 0);
+        if (u >= n_units) break;
         int js = 0;
         if (MULTI) {
             int lo = 0, hi = n_jobs - 1;
@@ -2455,7 +2449,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         const PointJob &J = MULTI ? many[js] : one;
         const SceneDev &sc = J.sc;
-        const int N = J.N, nb = (N + kSnapBlock - 1) / kSnapBlock, nch = (sc.S + kWave - 1) / kWave;
+        const int N = J.N, U = J.U, nb = (N + U - 1) / U, nch = (sc.S + kWave - 1) / kWave;
         const long long local = u - J.unit_base;
         const int kx = (int)(local / nb), blk = (int)(local - (long long)kx * nb);
         cur_side = kx / nch;
@@ -2467,20 +2461,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int sidx = cur_chunk * kWave + lane;
         const int fl = sidx < sc.S ? sc.sfacet[sidx] : -1;  // the facet of this lane's sample (-1 = none)
         const int own = fl >= 0 ? sc.fsolid[fl] : -1;       // the solid the sample's facet belongs to
-        const int n0 = blk * kSnapBlock, n1 = min(N, n0 + kSnapBlock);
-        // the box of the unit's points, for swept certificates: a lane whose hint
-        // solid blocks its sample from the whole box skips the unit's other points
-        float4 bl, bh;
-        {
-            const bool in = lane < n1 - n0;
-            const float *Xb = pts + 3 * (in ? n0 + lane : n0);
-            // (wave-uniform: kept in scalar registers)
-            auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
-            bl = make_float4(uni(wave_min(Xb[0])), uni(wave_min(Xb[1])), uni(wave_min(Xb[2])), 0.f);
-            bh = make_float4(uni(wave_max(Xb[0])), uni(wave_max(Xb[1])), uni(wave_max(Xb[2])), 0.f);
-        }
+        const int n0 = blk * U, n1 = min(N, n0 + U);
+        float4 bl = make_float4(0.f, 0.f, 0.f, 0.f), bh = bl;
         bool swept = false, tried = false;
+        int nb1 = n0;  // end of the current swept box's points
         for (int n = n0; n < n1; ++n) {
+            if (n == nb1) {
+                // the box of the next kSweptBlock points, for swept certificates: a lane
+                // whose hint solid blocks its sample from the whole box skips its other points
+                nb1 = min(n1, n + kSweptBlock);
+                const bool in = lane < nb1 - n;
+                const float *Xb = pts + 3 * (in ? n + lane : n);
+                // (wave-uniform: kept in scalar registers)
+                auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+                bl = make_float4(uni(wave_min(Xb[0])), uni(wave_min(Xb[1])), uni(wave_min(Xb[2])), 0.f);
+                bh = make_float4(uni(wave_max(Xb[0])), uni(wave_max(Xb[1])), uni(wave_max(Xb[2])), 0.f);
+                swept = tried = false;
+            }
             xx = pts[3 * n];
             xy = pts[3 * n + 1];
             xz = pts[3 * n + 2];
@@ -2538,7 +2535,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 }
             }
             // one swept certificate per lane and unit, while enough points remain
-            if (by_solid && !tried && hint != own && n + kSweptMinLeft < n1) {
+            if (by_solid && !tried && hint != own && n + kSweptMinLeft < nb1) {
                 tried = true;
                 swept = swept_solid(sc, hint, bl, bh, P, c);
             }
@@ -2671,14 +2668,31 @@ __global__ void k_check_points(SceneDev sc, int N, const float *tx, const float 
     if (bad) atomicOr(sc.status, bad);
 }
 
-// Work units of the Tx/Rx kernel: (side, chunk of 64 samples, block of kSnapBlock snapshots).
-long long point_units(const Scene &scn, int N) {
+// Work units of the Tx/Rx kernel: (side, chunk of 64 samples, block of U snapshots).
+long long point_units(const Scene &scn, int N, int U) {
     const int nch = (scn.dev.S + kWave - 1) / kWave;
-    return (scn.dev.S > 0 && scn.dev.F > 0 && N > 0) ? (long long)2 * nch * ((N + kSnapBlock - 1) / kSnapBlock) : 0;
+    return (scn.dev.S > 0 && scn.dev.F > 0 && N > 0) ? (long long)2 * nch * ((N + U - 1) / U) : 0;
+}
+
+// Snapshots per Tx/Rx work unit for jobs with S[k] samples and N[k] snapshots:
+// the longest of kSweptBlock, 2 kSweptBlock, ..., kUnitMax that still leaves at
+// least 16 units per wave (a wave's hints start afresh with each unit, and the
+// last units taken set the tail of the launch).
+int point_unit_len(const int *S, const int *N, int n_jobs, int grid_blocks) {
+    const long long waves = (long long)grid_blocks * kWavesPerBlock;
+    int best = kSweptBlock;
+    for (int U = 2 * kSweptBlock; U <= kUnitMax; U *= 2) {
+        long long units = 0;
+        for (int k = 0; k < n_jobs; ++k)
+            if (S[k] > 0 && N[k] > 0) units += 2ll * ((S[k] + kWave - 1) / kWave) * ((N[k] + U - 1) / U);
+        if (units < 16 * waves) break;
+        best = U;
+    }
+    return best;
 }
 
 PointJob make_point_job(Scene &scn, int N, const float *tx, const float *rx, uint64_t *txv, uint64_t *rxv,
-                        long long unit_base) {
+                        long long unit_base, int U) {
     PointJob j;
     j.sc = scn.dev;
     j.N = N;
@@ -2687,6 +2701,7 @@ PointJob make_point_job(Scene &scn, int N, const float *tx, const float *rx, uin
     j.txv = txv;
     j.rxv = rxv;
     j.unit_base = unit_base;
+    j.U = U;
     return j;
 }
 
@@ -2941,12 +2956,13 @@ hipError_t launch_edge_rows(Scene &scn, const TraverseOpts &o, int E, int s, con
     return hipGetLastError();
 }
 
-hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_units, const TraverseOpts &o,
-                             ivm_stats *stats, hipStream_t s) {
+hipError_t launch_point_jobs(const PointJob *d_jobs, int n_jobs, long long total_units, uint32_t *d_queue,
+                             const TraverseOpts &o, ivm_stats *stats, hipStream_t s) {
     if (total_units <= 0) return hipSuccess;
     PointJob none{};
-    hipLaunchKernelGGL(k_points<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, n_jobs, total_units, o,
-                       stats);
+    // (the unit counter is cleared with the rest of the queue slots at the batch's start)
+    hipLaunchKernelGGL(k_points<true>, dim3(o.grid_blocks), dim3(kBlock), 0, s, none, d_jobs, n_jobs, total_units,
+                       (unsigned long long *)(d_queue + kQueuePoints), o, stats);
     return hipGetLastError();
 }
 
@@ -2956,11 +2972,14 @@ hipError_t launch_points(Scene &scn, const TraverseOpts &o, int N, const float *
     if ((e = launch_points_prep(scn, N, tx, rx, txv, rxv, s)) != hipSuccess) return e;
     if (N == 0) return hipSuccess;
     if (o.events && (e = hipEventRecord(o.events[0], s)) != hipSuccess) return e;
-    const long long units = point_units(scn, N);
+    const int U = point_unit_len(&scn.dev.S, &N, 1, o.grid_blocks);
+    const long long units = point_units(scn, N, U);
     if (units > 0) {
-        const PointJob job = make_point_job(scn, N, tx, rx, txv, rxv, 0);
+        const PointJob job = make_point_job(scn, N, tx, rx, txv, rxv, 0, U);
+        uint32_t *ctr = (uint32_t *)((char *)scn.ws + scn.lay.queue) + kQueuePoints;
+        if ((e = launch_fill_u32(ctr, 0u, 2, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_points<false>, dim3(o.grid_blocks), dim3(kBlock), 0, s, job, (const PointJob *)nullptr, 1,
-                           units, o, stats);
+                           units, (unsigned long long *)ctr, o, stats);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (o.events && (e = hipEventRecord(o.events[1], s)) != hipSuccess) return e;
