@@ -2291,7 +2291,7 @@ __device__ unsigned certify_point_facets(const SceneDev &sc, int nf, int f0, int
 }
 
 template <bool MULTI>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_points(PointJob one, const PointJob *many, int n_jobs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_points(PointJob one, const PointJob *many, int n_jobs,
                                                    long long n_units, unsigned long long *counter, TraverseOpts o,
                                                    ivm_stats *st) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
@@ -2487,10 +2487,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             bool need = false;
             const float4 P = fl >= 0 ? (float4)sc.smp[sidx] : make_float4(0.f, 0.f, 0.f, 0.f);
             bool by_solid = false;  // decided by a solid at this point
-            if (fl >= 0 && !swept) {
+            if (fl >= 0 && !swept)
                 need = orient(sc.fplane + 6 * fl, xx, xy, xz) > 0.0 && !((row[fl >> 6] >> (fl & 63)) & 1ull);
-                if (need && !o.exhaustive) {
-                    ++segs;
+            segs += __popcll(__ballot(need));  // (a wave-uniform count)
+            if (need) {
+                if (!o.exhaustive) {
                     // the hint first
                     if (hint >= 0) {
                         if (solid_segment_global(sc, hint, X4, P, c)) {
@@ -2530,8 +2531,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                             }
                         }
                     }
-                } else if (need) {
-                    ++segs;
                 }
             }
             // one swept certificate per lane and unit, while enough points remain
@@ -2624,12 +2623,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 nmiss += __popcll(nm);
             }
             wave_sync();
-            pump(J, false);
+            // (the unit's last point empties the queues)
+            pump(J, n + 1 == n1);
         }
-        // drain the queues at the unit's end
-        if (np > 0 || nmiss > 0) pump(J, true);
     }
-    flush_counters(st, c, segs, 0, items);
+    flush_counters(st, c, lane == 0 ? segs : 0ull, 0, items);
     if (st && lane == 0 && nsolidf) atomicAdd((unsigned long long *)&st->solid_certified, nsolidf);
 }
 
