@@ -2725,41 +2725,130 @@ hipError_t launch_los(Scene &scn, const TraverseOpts &o, int N, const float *tx,
 // diffracting edge is found the way a reflecting face is).  Edge e, where facets
 // fa and fb meet, is seen from X when X lies strictly on the visible side of fa
 // or of fb and the segment from X to one of the edge's s sample points meets no
-// triangle outside fa and fb.  One lane per (snapshot, side, edge, sample): G
-// consecutive lanes (G = s rounded up to a power of two) hold the samples of one
-// edge, so a wave covers 64 / G edges of one point; a ballot over the group sets
-// the edge's bit.
+// triangle outside fa and fb.  One wave per (side, 64 / G edges, block of
+// kEdgeBlock consecutive snapshots): G consecutive lanes (G = s rounded up to a
+// power of two) hold the samples of one edge, and the wave follows them along
+// the trajectory with the table kernel's tools: each lane first tests the solid
+// or triangle that blocked its sample at the previous point, tries one swept
+// certificate for the box of the block's points, and the rest is traversed
+// wave-synchronously, the lanes whose sample was seen before first (a clear
+// lane settles its edge and stops the others of its group).  A ballot over the
+// group sets the edge's bit.  Hints only order exact tests.
+constexpr int kEdgeBlock = kSweptBlock;
+
 __global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int s, int G, int We, const int *efac,
                                                   const float *esmp, const float *tx, const float *rx,
                                                   uint64_t *txe, uint64_t *rxe, TraverseOpts o) {
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
-    const int wv = threadIdx.x >> 6, lane = lane_id();
+    __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
+    __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = lane_id();
     const int per_wave = kWave / G;
-    const long long nb = (E + per_wave - 1) / per_wave;
+    const long long nch = (E + per_wave - 1) / per_wave;
+    const int nb = (N + kEdgeBlock - 1) / kEdgeBlock;
     const long long q = (long long)blockIdx.x * kWavesPerBlock + wv;
-    if (q >= 2LL * N * nb) return;  // (wave-uniform)
-    const int n = (int)(q / (2 * nb)), side = (int)((q / nb) & 1);
-    const int e = (int)(q % nb) * per_wave + lane / G, j = lane % G;
-    const float *X = (side ? rx : tx) + 3 * (size_t)n;
-    bool clear = false;
-    if (e < E && j < s) {
-        const int fa = efac[2 * e], fb = efac[2 * e + 1];
-        if (fa >= 0 && fa < sc.F && fb >= -1 && fb < sc.F && fb != fa) {
-            const bool front = orient(sc.fplane + 6 * (size_t)fa, X[0], X[1], X[2]) > 0.0 ||
-                               (fb >= 0 && orient(sc.fplane + 6 * (size_t)fb, X[0], X[1], X[2]) > 0.0);
-            if (front) {
-                const float *p = esmp + 3 * ((size_t)e * s + j);
-                const Seg sg = make_seg(X[0], X[1], X[2], p[0], p[1], p[2]);
-                Cnt c;
-                clear = any_hit(sc, sg, fa, fb, kIdentOrder, kTreelets, &sStack[wv][lane], o.stack_depth, o.eps6,
-                                o.fp64_only != 0, c) < 0;
+    if (q >= 2LL * nch * nb) return;  // (wave-uniform)
+    // consecutive waves take consecutive blocks of one chunk (the same scene data)
+    const int blk = (int)(q % nb);
+    const long long kx = q / nb;
+    const int side = (int)(kx / nch);
+    const int chunk = (int)(kx - (long long)side * nch);
+    const int grp = lane / G, j = lane % G;
+    const int e = chunk * per_wave + grp;
+    const unsigned long long gm = (G == kWave ? ~0ull : ((1ull << G) - 1ull)) << (grp * G);
+    const float *pts = side ? rx : tx;
+    uint64_t *out = side ? rxe : txe;
+    int fa = -1, fb = -1;
+    bool valid = e < E && j < s;
+    if (valid) {
+        fa = efac[2 * e];
+        fb = efac[2 * e + 1];
+        valid = fa >= 0 && fa < sc.F && fb >= -1 && fb < sc.F && fb != fa;
+    }
+    const int exb = fb >= 0 ? fb : fa;
+    const int own_a = valid ? sc.fsolid[fa] : -1, own_b = valid && fb >= 0 ? sc.fsolid[fb] : -1;
+    float4 P = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+        const float *pp = esmp + 3 * ((size_t)e * s + j);
+        P = make_float4(pp[0], pp[1], pp[2], 0.f);
+    }
+    const int n0 = blk * kEdgeBlock, n1 = min(N, n0 + kEdgeBlock);
+    // the box of the block's points (swept certificates) and a treelet order from
+    // its first point (a heuristic only)
+    float4 bl, bh;
+    {
+        const float *Xb = pts + 3 * (lane < n1 - n0 ? n0 + lane : n0);
+        auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+        bl = make_float4(uni(wave_min(Xb[0])), uni(wave_min(Xb[1])), uni(wave_min(Xb[2])), 0.f);
+        bh = make_float4(uni(wave_max(Xb[0])), uni(wave_max(Xb[1])), uni(wave_max(Xb[2])), 0.f);
+    }
+    int n_order;
+    {
+        const float xq[3] = {pts[3 * n0], pts[3 * n0 + 1], pts[3 * n0 + 2]};
+        unsigned long long tk = ~0ull;
+        if (lane < kTreelets && sc.tl_root[lane] != kNone) {
+            const float *b = sc.tl_box + 6 * lane;
+            float d2 = 0.f;
+            for (int k = 0; k < 3; ++k) {
+                const float cq = fmaxf(fmaxf(b[k] - xq[k], xq[k] - b[3 + k]), 0.f);
+                d2 += cq * cq;
+            }
+            tk = __float_as_uint(d2);
+        }
+        n_order = wave_rank_order(tk, sKey[wv], sOrder[wv]);
+    }
+    int *stk = &sStack[wv][lane];
+    const bool f64 = o.fp64_only != 0;
+    Cnt c;
+    int hint = kHintNone;
+    bool swept = false, tried = false;
+    for (int n = n0; n < n1; ++n) {
+        const float xx = pts[3 * n], xy = pts[3 * n + 1], xz = pts[3 * n + 2];
+        const float4 X4 = make_float4(xx, xy, xz, 0.f);
+        bool need = valid && !swept &&
+                    (orient(sc.fplane + 6 * (size_t)fa, xx, xy, xz) > 0.0 ||
+                     (fb >= 0 && orient(sc.fplane + 6 * (size_t)fb, xx, xy, xz) > 0.0));
+        bool by_solid = false;
+        if (need && !o.exhaustive) {
+            if (hint >= 0) {
+                if (solid_segment_global(sc, hint, X4, P, c)) {
+                    need = false;
+                    by_solid = true;
+                } else {
+                    hint = kHintNone;
+                }
+            } else if (hint <= -3) {
+                const int r = -(hint + 3);
+                const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+                ++c.tests;
+                if (tri_hit(sg, sc.tri[3 * r], sc.tri[3 * r + 1], sc.tri[3 * r + 2], o.eps6, f64, c.rechecks))
+                    need = false;
+                else
+                    hint = kHintNone;
             }
         }
-    }
-    const unsigned long long bal = __ballot(clear);
-    if (j == 0 && e < E) {
-        const unsigned long long gm = (G == kWave ? ~0ull : ((1ull << G) - 1ull)) << lane;
-        if (bal & gm) atomicOr((unsigned long long *)((side ? rxe : txe) + (size_t)n * We + (e >> 6)), 1ull << (e & 63));
+        if (by_solid && !tried && hint != own_a && hint != own_b && n + kSweptMinLeft < n1) {
+            tried = true;
+            swept = swept_solid(sc, hint, bl, bh, P, c);
+        }
+        // traversals: first the lanes whose sample was seen before (or whose edge has
+        // no such lane), then the rest of the edges still unseen
+        const unsigned long long clm = __ballot(need && hint == kHintClear);
+        const bool first = need && (hint == kHintClear || (clm & gm) == 0ull);
+        bool vis = false;
+        for (int round = 0; round < 2; ++round) {
+            const bool act = round == 0 ? first : need && !first && !vis;
+            if (!__ballot(act)) continue;
+            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
+            if (act) ++c.traversed;
+            const int hit = any_hit_wave(sc, sg, act, fa, exb, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64,
+                                         c, kAbortSameKey, grp);
+            if (act && hit == -1) hint = kHintClear;
+            else if (act && hit >= 0) hint = hint_of_hit(sc, hit);
+            vis = vis || (__ballot(act && hit == -1) & gm) != 0ull;
+        }
+        if (j == 0 && e < E && vis)
+            atomicOr((unsigned long long *)(out + (size_t)n * We + (e >> 6)), 1ull << (e & 63));
     }
 }
 
@@ -2917,7 +3006,7 @@ hipError_t launch_edges(Scene &scn, const TraverseOpts &o, int N, int E, int s, 
         int G = 1;
         while (G < s) G <<= 1;
         const long long per_wave = kWave / G;
-        const long long waves = 2LL * N * ((E + per_wave - 1) / per_wave);
+        const long long waves = 2LL * ((E + per_wave - 1) / per_wave) * ((N + kEdgeBlock - 1) / kEdgeBlock);
         hipLaunchKernelGGL(k_edges, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)), dim3(kBlock), 0,
                            st, sc, N, E, s, G, We, efac, esmp, tx, rx, txe, rxe, o);
     }
