@@ -1418,6 +1418,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     int ncache = 0, cpos = 0;
     int nsol = 0, sspos = 0;
     int cur_js = -1;
+    int vh_i = -1, vh_a = 0, vh_b = 0;  // the wave's last visible pair: facet i and the clear segment's samples
     uint32_t g_next = 0, g_end = 0;
     // decode state: the previous pair's candidate word and its bits from that pair on
     int d_item = 0;
@@ -1451,6 +1452,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const SceneDev &sc = J.sc;
         if (js != cur_js) {
             cur_js = js;
+            vh_i = -1;
             ncache = cpos = nsol = sspos = 0;
             d_m = 0ull;  // (d_gl + 1 wraps to 0, the new scene's first pair: an empty word forces a full decode)
             d_gl = 0xffffffffu;
@@ -1471,10 +1473,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const double *pli = sc.fplane + 6 * i, *plj = sc.fplane + 6 * j;
         const int si0 = sc.soff[i], ni = min(sc.soff[i + 1] - si0, kWave);
         const int sj0 = sc.soff[j], nj = min(sc.soff[j + 1] - sj0, kWave);
-        const float4 p = lane < ni ? (float4)sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
-        const float4 q = lane < nj ? (float4)sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
+        float4 p = lane < ni ? (float4)sc.smp[si0 + lane] : make_float4(0, 0, 0, 0);
+        float4 q = lane < nj ? (float4)sc.smp[sj0 + lane] : make_float4(0, 0, 0, 0);
         const bool okp = lane < ni && orient(plj, p.x, p.y, p.z) > 0.0;
         const bool okq = lane < nj && orient(pli, q.x, q.y, q.z) > 0.0;
+        p.w = __int_as_float(lane);  // (the sample's index in its facet, for the visible-pair hint)
+        q.w = __int_as_float(lane);
         const int clp = lane < ni ? sc.scluster[si0 + lane] : 0;
         const int clq = lane < nj ? sc.scluster[sj0 + lane] : 0;
         // compact admissible samples grouped by cluster: cluster c of i occupies
@@ -1646,8 +1650,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         int nseg = R.pre[R.n];
         bool vis = false, done = false, first_traversal = true;
         int nmiss = 0;
+        // a first batch of one segment: between the samples at the positions of the
+        // clear segment of the wave's last visible pair with the same facet i
+        bool hint_batch = false;
+        if (vh_i == i && !o.exhaustive && nseg > 1) {
+            const unsigned long long ma = __ballot(lane < np && __float_as_int(sP[wv][lane].w) == vh_a);
+            const unsigned long long mb = __ballot(lane < nq && __float_as_int(sQ[wv][lane].w) == vh_b);
+            if (ma && mb) {
+                if (lane == 0) miss[0] = (__ffsll((long long)ma) - 1) | ((__ffsll((long long)mb) - 1) << 8);
+                nmiss = 1;
+                hint_batch = true;
+                wave_sync();
+            }
+        }
         for (int base = 0; !done; base += kWave) {
-            const bool more = base < nseg;
+            const bool more = base < nseg && !hint_batch;
             if (more) {
                 // cache pass: each lane takes one segment in spread order (the first
                 // batch pairs many different p with many q) and tests the recent blockers
@@ -1694,7 +1711,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 wave_sync();
             }
             // traversal passes over full batches of queued segments (and the tail)
-            while (!done && (nmiss >= kWave || (!more && nmiss > 0))) {
+            while (!done && (nmiss >= kWave || ((!more || hint_batch) && nmiss > 0))) {
                 const int k = min(kWave, nmiss);
                 int hit = -1;
                 bool clear = false;
@@ -1710,6 +1727,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                                            c, kAbortAll, 0);
                     }
                     clear = lane < k && hit == -1;
+                    const unsigned long long cm = __ballot(clear);
+                    if (cm) {
+                        const int abv = __shfl(ab, __ffsll((long long)cm) - 1);
+                        vh_i = i;
+                        vh_a = __float_as_int(sP[wv][abv & 255].w);
+                        vh_b = __float_as_int(sQ[wv][abv >> 8].w);
+                    }
                 }
                 nmiss -= k;
                 wave_sync();
@@ -1730,7 +1754,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     if (ncache < kCache) cache[ncache++] = r;
                     else { cache[cpos] = r; cpos = (cpos + 1) % kCache; }
                 }
-                if (first_traversal && nseg > kWave && !o.exhaustive) {
+                if (first_traversal && !hint_batch && nseg > kWave && !o.exhaustive) {
                     first_traversal = false;
                     // the first traversal batch is all blocked: try to prove the whole pair
                     // blocked by the facet that blocked its first lane, then its last lane's
@@ -1791,6 +1815,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         }
                     }
                 }
+            }
+            if (hint_batch) {
+                // (the hint's batch is over: the pass over the segments starts)
+                hint_batch = false;
+                base -= kWave;
+                continue;
             }
             if (!more && nmiss == 0) done = true;
         }
