@@ -2893,7 +2893,9 @@ __global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int
 // One lane per (row edge, target node, edge sample): G consecutive lanes (G = s
 // rounded up to a power of two) hold one edge-target pair, so a wave covers
 // 64 / G targets of one row.  A lane walks the target's samples in order,
-// tests the triangle that blocked its previous segment before a traversal, and
+// tests the verified solid and the triangle that blocked its previous segment
+// before a traversal (a solid that holds one of the four side facets is never
+// tested: its faces would include excluded triangles), and
 // stops at the first clear segment or when another lane of its group has found
 // one (a flag in LDS); a ballot over the group sets the target's bit.
 __global__ __launch_bounds__(kBlock) void k_edge_rows(SceneDev sc, int E, int s, int G, const int *efac,
@@ -2936,7 +2938,12 @@ __global__ __launch_bounds__(kBlock) void k_edge_rows(SceneDev sc, int E, int s,
                                           (tb >= 0 && orient(sc.fplane + 6 * (size_t)tb, p[0], p[1], p[2]) > 0.0));
         if (p_front) {
             const Ex4 ex{fa, fb, ta, tb};
-            int last = -1;
+            int last = -1, lsol = -1;  // the triangle that blocked the previous segment, and its verified solid
+            // (a solid that holds one of the four side facets is never used: its faces
+            // would include excluded triangles)
+            const int sa = sc.fsolid[fa], sb = fb >= 0 ? sc.fsolid[fb] : -1;
+            const int sta = sc.fsolid[ta], stb = tb >= 0 ? sc.fsolid[tb] : -1;
+            const float4 P4 = make_float4(p[0], p[1], p[2], 0.f);
             Cnt c;
             for (int b = 0; b < nq && !done[grp]; ++b) {
                 float qx, qy, qz;
@@ -2954,6 +2961,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_rows(SceneDev sc, int E, int s,
                 if (!(orient(sc.fplane + 6 * (size_t)fa, qx, qy, qz) > 0.0 ||
                       (fb >= 0 && orient(sc.fplane + 6 * (size_t)fb, qx, qy, qz) > 0.0)))
                     continue;
+                if (lsol >= 0 && solid_segment_global(sc, lsol, P4, make_float4(qx, qy, qz, 0.f), c)) continue;
                 const Seg sg = make_seg(p[0], p[1], p[2], qx, qy, qz);
                 if (last >= 0 && tri_hit(sg, sc.tri[3 * last], sc.tri[3 * last + 1], sc.tri[3 * last + 2], o.eps6,
                                          o.fp64_only != 0, c.rechecks))
@@ -2966,6 +2974,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_rows(SceneDev sc, int E, int s,
                     break;
                 }
                 last = h;
+                const int K = sc.fsolid[__float_as_int(sc.tri[3 * h].w)];
+                if (K >= 0 && K != sa && K != sb && K != sta && K != stb) lsol = K;
             }
         }
     }
