@@ -421,8 +421,9 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
               file=sys.stderr, flush=True)
     om = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, timing=t_pairs, exhaustive=args.exhaustive,
                        **knob)
+    # (the tuner times the matrix call: the table keeps the command line's knobs)
     op = ivm.make_opts(order_mode=order, fp64_only=args.fp64_only, timing=t_points, exhaustive=args.exhaustive,
-                       **knob)
+                       waves_per_cu=args.waves_per_cu, stack_depth=args.stack)
 
     def step(rec):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
