@@ -311,46 +311,85 @@ __device__ inline void decode_candidate(const SceneDev &sc, const uint64_t *cand
     j = (lo - i * sc.W) * 64 + bit;
 }
 
-// act: LDS [16][kHid] row-major; W: [nout][kin] global; writes out[16][nout] (+bias, ReLU).
-__device__ inline void mlp_layer16(const float *act, int kin, const float *W, const float *b, int nout, float *out,
-                                   bool relu) {
-    const int lane = threadIdx.x & 63;
-    const int r = lane & 15, kq = 4 * (lane >> 4);
-    for (int n0 = 0; n0 < nout; n0 += 16) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < kin; k0 += 16) {
-            bf16x4 a, bb;
-            for (int v = 0; v < 4; ++v) {
-                const int k = k0 + kq + v;
-                a[v] = k < kin ? to_bf16(act[r * kHid + k]) : (short)0;
-                bb[v] = k < kin ? to_bf16(W[(size_t)(n0 + r) * kin + k]) : (short)0;
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
-        }
-        for (int v = 0; v < 4; ++v) {
-            float val = acc[v] + b[n0 + r];
-            if (relu) val = fmaxf(val, 0.f);
-            out[(kq + v) * kHid + n0 + r] = val;
-        }
-    }
-}
-
 __device__ inline void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave (64 threads) per block; learned[g] = top-12 treelets by score, 5 bits
-// each (best first), count in the top 4 bits.  NaN scores rank as -inf; ties go
-// to the lower treelet index.
-__global__ __launch_bounds__(64) void k_learned(SceneDev sc, const uint64_t *cand, const uint32_t *prefix, int n_items,
-                                               const float *params, uint64_t *learned) {
-    __shared__ float actA[16 * kHid];
-    __shared__ float actB[16 * kHid];
+// In-call inference for the learned order.  Each block stages the network in
+// LDS once: every weight rounded to BF16 (the rounding the MFMA inputs get
+// anyway; biases are read in FP32 from global memory), rows padded so that the
+// 16 rows an MFMA step reads fall in different LDS banks; then its kLearnWaves
+// waves score 16 pairs at a time with the same 16 x 16 x 16 BF16 MFMA steps in
+// the same order as the training forward pass.  Hidden activations are kept as
+// BF16 (each is rounded to BF16 as the next layer's input), the scores as FP32.
+// learned[g] = top-12 treelets by score, 5 bits each (best first), count in the
+// top 4 bits.  NaN scores rank as -inf; ties go to the lower treelet index.
+constexpr int kLearnWaves = 5;
+constexpr int kRowIn = kIn + 4;     // padded row of W0 (BF16 elements)
+constexpr int kRowHid = kHid + 16;  // padded rows of W1..W3 and of the activations: 72 words, 8 banks apart
+constexpr int kLdsW0 = 0, kLdsW1 = kLdsW0 + kHid * kRowIn, kLdsW2 = kLdsW1 + kHid * kRowHid;
+constexpr int kLdsW3 = kLdsW2 + kHid * kRowHid, kLdsWEnd = kLdsW3 + kOut * kRowHid;
+constexpr size_t kLearnLds = sizeof(short) * kLdsWEnd + sizeof(short) * kLearnWaves * 2 * 16 * kRowHid +
+                             sizeof(float) * kLearnWaves * 16 * kOut;
+
+// act: [16][kRowHid] BF16 rows (LDS); W: [nout][ldw] BF16 (LDS); b: FP32 biases.
+// Writes out_bf[16][kRowHid] (BF16, + bias, ReLU) or, for the last layer, out_f[16][kOut] (FP32).
+__device__ inline void mlp_layer16_lds(const short *act, int kin, const short *W, int ldw, const float *b, int nout,
+                                       short *out_bf, float *out_f, bool relu) {
     const int lane = threadIdx.x & 63;
+    const int r = lane & 15, kq = 4 * (lane >> 4);
+    for (int n0 = 0; n0 < nout; n0 += 16) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < kin; k0 += 16) {
+            bf16x4 a, bb;
+            if (k0 + 16 <= kin) {
+                a = *(const bf16x4 *)(act + r * kRowHid + k0 + kq);
+                bb = *(const bf16x4 *)(W + (n0 + r) * ldw + k0 + kq);
+            } else {
+                for (int v = 0; v < 4; ++v) {
+                    const int k = k0 + kq + v;
+                    a[v] = k < kin ? act[r * kRowHid + k] : (short)0;
+                    bb[v] = k < kin ? W[(n0 + r) * ldw + k] : (short)0;
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+        }
+        for (int v = 0; v < 4; ++v) {
+            float val = acc[v] + b[n0 + r];
+            if (relu) val = fmaxf(val, 0.f);
+            if (out_f) out_f[(kq + v) * kOut + n0 + r] = val;
+            else out_bf[(kq + v) * kRowHid + n0 + r] = to_bf16(val);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * kLearnWaves) void k_learned(SceneDev sc, const uint64_t *cand,
+                                                              const uint32_t *prefix, int n_items, const float *params,
+                                                              uint64_t *learned) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    short *sW = (short *)lds;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    short *actA = (short *)(lds + sizeof(short) * kLdsWEnd) + wv * 2 * 16 * kRowHid;
+    short *actB = actA + 16 * kRowHid;
+    float *outS = (float *)(lds + sizeof(short) * kLdsWEnd + sizeof(short) * kLearnWaves * 2 * 16 * kRowHid) +
+                  wv * 16 * kOut;
+    // stage the four weight matrices into their padded rows
+    auto stage = [&](int off, int rows, int cols, int dst, int ld) {
+        for (int k = threadIdx.x; k < rows * cols; k += blockDim.x) {
+            const int rr = k / cols, cc = k - rr * cols;
+            sW[dst + rr * ld + cc] = to_bf16(params[off + k]);
+        }
+    };
+    stage(kOffW0, kHid, kIn, kLdsW0, kRowIn);
+    stage(kOffW1, kHid, kHid, kLdsW1, kRowHid);
+    stage(kOffW2, kHid, kHid, kLdsW2, kRowHid);
+    stage(kOffW3, kOut, kHid, kLdsW3, kRowHid);
+    __syncthreads();
     const uint32_t total = prefix[n_items];
-    for (uint32_t g0 = blockIdx.x * 16u; g0 < total; g0 += gridDim.x * 16u) {
+    const uint32_t stride = gridDim.x * (uint32_t)kLearnWaves * 16u;
+    for (uint32_t g0 = (blockIdx.x * (uint32_t)kLearnWaves + (uint32_t)wv) * 16u; g0 < total; g0 += stride) {
         if (lane < 16) {
             float x[kIn];
             if (g0 + lane < total) {
@@ -360,25 +399,25 @@ __global__ __launch_bounds__(64) void k_learned(SceneDev sc, const uint64_t *can
             } else {
                 for (int m = 0; m < kIn; ++m) x[m] = 0.f;
             }
-            for (int m = 0; m < kIn; ++m) actA[lane * kHid + m] = x[m];
+            for (int m = 0; m < kIn; ++m) actA[lane * kRowHid + m] = to_bf16(x[m]);
         }
         wave_fence();
-        mlp_layer16(actA, kIn, params + kOffW0, params + kOffB0, kHid, actB, true);
+        mlp_layer16_lds(actA, kIn, sW + kLdsW0, kRowIn, params + kOffB0, kHid, actB, nullptr, true);
         wave_fence();
-        mlp_layer16(actB, kHid, params + kOffW1, params + kOffB1, kHid, actA, true);
+        mlp_layer16_lds(actB, kHid, sW + kLdsW1, kRowHid, params + kOffB1, kHid, actA, nullptr, true);
         wave_fence();
-        mlp_layer16(actA, kHid, params + kOffW2, params + kOffB2, kHid, actB, true);
+        mlp_layer16_lds(actA, kHid, sW + kLdsW2, kRowHid, params + kOffB2, kHid, actB, nullptr, true);
         wave_fence();
-        mlp_layer16(actB, kHid, params + kOffW3, params + kOffB3, kOut, actA, false);
+        mlp_layer16_lds(actB, kHid, sW + kLdsW3, kRowHid, params + kOffB3, kOut, nullptr, outS, false);
         wave_fence();
         for (int p = 0; p < 16 && g0 + p < total; ++p) {
-            float sv = lane < kOut ? actA[p * kHid + lane] : -INFINITY;
+            float sv = lane < kOut ? outS[p * kOut + lane] : -INFINITY;
             if (sv != sv) sv = -INFINITY;
             unsigned long long code = 0;
             if (lane < kOut) {
                 int rank = 0;
                 for (int m = 0; m < kOut; ++m) {
-                    float sm = actA[p * kHid + m];
+                    float sm = outS[p * kOut + m];
                     if (sm != sm) sm = -INFINITY;
                     rank += (sm > sv) || (sm == sv && m < lane);
                 }
@@ -394,11 +433,14 @@ __global__ __launch_bounds__(64) void k_learned(SceneDev sc, const uint64_t *can
 hipError_t launch_learned_order(Scene &scn, const Model &m, hipStream_t s) {
     char *ws = (char *)scn.ws;
     const Layout &L = scn.lay;
-    const int blocks = device_cu_count() * 8;
-    // over the pairs the probes left undecided (the ones the pair kernel visits)
-    hipLaunchKernelGGL(k_learned, dim3(blocks), dim3(64), 0, s, scn.dev, (const uint64_t *)(ws + L.und),
-                       (const uint32_t *)(ws + L.uprefix), scn.n_items, (const float *)m.params,
-                       (uint64_t *)(ws + L.learned));
+    hipError_t e = hipFuncSetAttribute((const void *)k_learned, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kLearnLds);
+    if (e != hipSuccess) return e;
+    // one block per CU (the staged network fills most of its LDS), over the pairs
+    // the probes left undecided (the ones the pair kernel visits)
+    hipLaunchKernelGGL(k_learned, dim3(device_cu_count()), dim3(64 * kLearnWaves), kLearnLds, s, scn.dev,
+                       (const uint64_t *)(ws + L.und), (const uint32_t *)(ws + L.uprefix), scn.n_items,
+                       (const float *)m.params, (uint64_t *)(ws + L.learned));
     return hipGetLastError();
 }
 
