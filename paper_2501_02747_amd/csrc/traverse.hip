@@ -2759,11 +2759,14 @@ hipError_t launch_los(Scene &scn, const TraverseOpts &o, int N, const float *tx,
 // kEdgeBlock consecutive snapshots): G consecutive lanes (G = s rounded up to a
 // power of two) hold the samples of one edge, and the wave follows them along
 // the trajectory with the table kernel's tools: each lane first tests the solid
-// or triangle that blocked its sample at the previous point, tries one swept
-// certificate for the box of the block's points, and the rest is traversed
-// wave-synchronously, the lanes whose sample was seen before first (a clear
-// lane settles its edge and stops the others of its group).  A ballot over the
-// group sets the edge's bit.  Hints only order exact tests.
+// or triangle that blocked its sample at the previous point and tries one swept
+// certificate for the box of the block's points.  The rest goes into two queues
+// of (point, lane) entries traversed in full 64-lane batches that mix the block's
+// points: one probe per (point, edge), the sample seen from an earlier point,
+// whose edge's other samples follow only if it is blocked (less those its
+// blocking triangle also blocks); and, for edges with no such sample, all their
+// samples at once (a clear lane stops the others of its point and edge).  Hints
+// only order exact tests.
 constexpr int kEdgeBlock = kSweptBlock;
 
 __global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int s, int G, int We, const int *efac,
@@ -2772,6 +2775,11 @@ __global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int
     __shared__ int sStack[kWavesPerBlock][kWave * IVM_MAX_STACK];
     __shared__ unsigned long long sKey[kWavesPerBlock][kTreelets];
     __shared__ uint8_t sOrder[kWavesPerBlock][kTreelets];
+    __shared__ int sMiss[kWavesPerBlock][2 * kWave];
+    __shared__ int sProbe[kWavesPerBlock][2 * kWave];
+    __shared__ unsigned long long sPMask[kWavesPerBlock][2 * kWave];
+    __shared__ int sPSnap[kWavesPerBlock][2 * kWave];
+    __shared__ int sUpd[kWavesPerBlock][kWave];
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = lane_id();
     const int per_wave = kWave / G;
     const long long nch = (E + per_wave - 1) / per_wave;
@@ -2828,10 +2836,82 @@ __global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int
         n_order = wave_rank_order(tk, sKey[wv], sOrder[wv]);
     }
     int *stk = &sStack[wv][lane];
+    int *miss = sMiss[wv];
     const bool f64 = o.fp64_only != 0;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     Cnt c;
     int hint = kHintNone;
     bool swept = false, tried = false;
+    int np = 0, nexp = 0, nmiss = 0;
+    sUpd[wv][lane] = kNoUpdate;
+    // Runs the traversals the queues call for (entries are point offset * 64 +
+    // lane): full batches of misses; the other samples of an edge whose probe was
+    // blocked (less those its blocking triangle also blocks) into the miss queue;
+    // batches of up to 64 probes.  `fin` empties the queues.
+    auto pump = [&](bool fin) __attribute__((always_inline)) {
+        while (true) {
+            const bool do_miss = nmiss >= kWave || (fin && nmiss > 0 && nexp == 0);
+            if (!do_miss && nexp > 0) {
+                const int ex = np + nexp - 1;
+                const unsigned long long m = sPMask[wv][ex];
+                const int h = sProbe[wv][ex], d = sPSnap[wv][ex];
+                --nexp;
+                bool keep = (m >> lane) & 1ull;
+                if (keep) {
+                    const float *X = pts + 3 * (n0 + d);
+                    const Seg sg3 = make_seg(X[0], X[1], X[2], P.x, P.y, P.z);
+                    ++c.tests;
+                    keep = !tri_hit(sg3, sc.tri[3 * h], sc.tri[3 * h + 1], sc.tri[3 * h + 2], o.eps6, f64, c.rechecks);
+                    if (!keep) hint = hint_of_hit(sc, h);
+                }
+                const unsigned long long km = __ballot(keep);
+                if (keep) miss[nmiss + __popcll(km & lt)] = d * kWave + lane;
+                nmiss += __popcll(km);
+                wave_sync();
+                continue;
+            }
+            if (!do_miss && !(np >= kWave || (fin && np > 0))) break;
+            const int k = min(kWave, do_miss ? nmiss : np);
+            const bool act = lane < k;
+            const int q = (do_miss ? nmiss : np) - (act ? k - lane : 1);
+            const int code = do_miss ? miss[q] : sProbe[wv][q];
+            const unsigned long long pm = do_miss || !act ? 0ull : sPMask[wv][q];
+            const int d = code >> 6, sl = code & (kWave - 1);
+            // the entry's lane: its edge, sample and side facets
+            const float Px = __shfl(P.x, sl), Py = __shfl(P.y, sl), Pz = __shfl(P.z, sl);
+            const int ea = __shfl(fa, sl), eb = __shfl(exb, sl), eg = sl / G;
+            const float *X = pts + 3 * (n0 + d);
+            const Seg sg = make_seg(X[0], X[1], X[2], Px, Py, Pz);
+            if (act) ++c.traversed;
+            const int hit = any_hit_wave(sc, sg, act, ea, eb, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64, c,
+                                         kAbortSameKey, d * kWave + eg);
+            const bool clear = act && hit == -1;
+            if (do_miss) nmiss -= k;
+            else np -= k;
+            wave_sync();
+            const int ee = chunk * per_wave + eg;
+            if (clear) atomicOr((unsigned long long *)(out + (size_t)(n0 + d) * We + (ee >> 6)), 1ull << (ee & 63));
+            if (act && (clear || hit >= 0)) sUpd[wv][sl] = clear ? kHintClear : hint_of_hit(sc, hit);
+            if (!do_miss) {
+                const bool blk = act && hit >= 0 && pm != 0ull;
+                const unsigned long long bm = __ballot(blk);
+                if (blk) {
+                    const int pos = np + __popcll(bm & lt);
+                    sProbe[wv][pos] = hit;
+                    sPMask[wv][pos] = pm;
+                    sPSnap[wv][pos] = d;
+                }
+                nexp = __popcll(bm);
+            }
+            wave_sync();
+            const int u = sUpd[wv][lane];
+            if (u != kNoUpdate) {
+                hint = u;
+                sUpd[wv][lane] = kNoUpdate;
+            }
+            wave_sync();
+        }
+    };
     for (int n = n0; n < n1; ++n) {
         const float xx = pts[3 * n], xy = pts[3 * n + 1], xz = pts[3 * n + 2];
         const float4 X4 = make_float4(xx, xy, xz, 0.f);
@@ -2861,24 +2941,23 @@ __global__ __launch_bounds__(kBlock) void k_edges(SceneDev sc, int N, int E, int
             tried = true;
             swept = swept_solid(sc, hint, bl, bh, P, c);
         }
-        // traversals: first the lanes whose sample was seen before (or whose edge has
-        // no such lane), then the rest of the edges still unseen
+        // one probe per edge with a sample seen before; the other edges' samples all
         const unsigned long long clm = __ballot(need && hint == kHintClear);
-        const bool first = need && (hint == kHintClear || (clm & gm) == 0ull);
-        bool vis = false;
-        for (int round = 0; round < 2; ++round) {
-            const bool act = round == 0 ? first : need && !first && !vis;
-            if (!__ballot(act)) continue;
-            const Seg sg = make_seg(xx, xy, xz, P.x, P.y, P.z);
-            if (act) ++c.traversed;
-            const int hit = any_hit_wave(sc, sg, act, fa, exb, sOrder[wv], n_order, stk, o.stack_depth, o.eps6, f64,
-                                         c, kAbortSameKey, grp);
-            if (act && hit == -1) hint = kHintClear;
-            else if (act && hit >= 0) hint = hint_of_hit(sc, hit);
-            vis = vis || (__ballot(act && hit == -1) & gm) != 0ull;
+        const unsigned long long nmm = __ballot(need);
+        const unsigned long long mine = clm & gm;
+        const bool probe = mine != 0ull && lane == __ffsll((long long)mine) - 1;
+        const bool direct = need && (clm & gm) == 0ull;
+        const unsigned long long pb = __ballot(probe), db = __ballot(direct);
+        if (probe) {
+            const int pos = np + __popcll(pb & lt);
+            sProbe[wv][pos] = (n - n0) * kWave + lane;
+            sPMask[wv][pos] = nmm & gm & ~(1ull << lane);
         }
-        if (j == 0 && e < E && vis)
-            atomicOr((unsigned long long *)(out + (size_t)n * We + (e >> 6)), 1ull << (e & 63));
+        if (direct) miss[nmiss + __popcll(db & lt)] = (n - n0) * kWave + lane;
+        np += __popcll(pb);
+        nmiss += __popcll(db);
+        wave_sync();
+        pump(n + 1 == n1);
     }
 }
 
