@@ -1710,8 +1710,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 nmiss += __popcll(nm);
                 wave_sync();
             }
-            // traversal passes over full batches of queued segments (and the tail)
-            while (!done && (nmiss >= kWave || ((!more || hint_batch) && nmiss > 0))) {
+            // the misses of each cache pass are traversed at once rather than collected
+            // into full batches: their blockers then serve the next passes (fewer misses
+            // in all), and a visible pair ends at its first clear segment sooner
+            while (!done && nmiss > 0) {
                 const int k = min(kWave, nmiss);
                 int hit = -1;
                 bool clear = false;
