@@ -617,7 +617,7 @@ __device__ inline void decode_pair(const SceneDev &sc, const uint64_t *cand, con
 constexpr int kCache = 2;  // recent blockers tested before a traversal
 constexpr int kSolidTries = 4;  // distinct solids tried per certificate attempt
 constexpr int kScanMaxSolids = 4096;  // scenes with at most this many solids scan them all per pair
-constexpr int kScanTries = 4;         // solids from the scan tried per pair
+constexpr int kScanTries = 6;         // solids from the scan tried per pair (and per point certificate)
 constexpr int kScanLinearMax = 256;   // up to this many solids a scan reads them all instead of the grid
 constexpr int kScanMaxSolidsPoint = 4096;  // the same scan per (point, facet) in the Tx/Rx kernel
 constexpr int kPairChunk = 4;   // consecutive undecided pairs taken by a wave at a time (small jobs)
