@@ -40,11 +40,13 @@
  *     stream has been synchronised.
  *   - Hot calls (matrix, table, candidates in count mode) allocate no device
  *     memory; all device state lives in the caller-provided scene workspace.
- *   - Calls on one scene that only read it (candidates, relations, angles,
- *     ranges, edges, path validation) may run concurrently on different
- *     streams; ivm_intervisibility_matrix and ivm_txrx_visibility_table use the
- *     scene's scratch area (work queues) and must not overlap a matrix or table
- *     call on the same scene.
+ *   - Calls on one scene that only read it (candidates of orders 1-2,
+ *     relations, angles, ranges, edges, path validation) may run concurrently
+ *     on different streams; ivm_intervisibility_matrix and
+ *     ivm_txrx_visibility_table use the scene's scratch area (work queues) and
+ *     must not overlap a matrix or table call on the same scene; candidates of
+ *     orders 3-4 use the pair scratch and must not overlap a matrix call or
+ *     another order-3/4 call on the same scene.
  *   - Bit layout of every facet bit set: bit j of row r is word j >> 6, bit
  *     j & 63, of row r; rows have W = ceil(F / 64) uint64 words; padding bits
  *     are zero.
@@ -176,7 +178,7 @@ typedef struct ivm_matrix_opts {
     int32_t order_mode;     /* IVM_ORDER_* */
     int32_t fp64_only;      /* 1: decide every segment/triangle test in FP64 */
     int32_t stack_depth;    /* 2..IVM_MAX_STACK; 0 = default; overflow scans linearly */
-    int32_t waves_per_cu;   /* persistent grid size; 0 = default */
+    int32_t waves_per_cu;   /* persistent grid size in waves per compute unit, 1..64; 0 = 24 */
     float eps;              /* FP32 filter margin relative to the magnitude bound;
                                0 = default 1e-5; values < 1e-5 are raised to 1e-5;
                                +inf sends every test to FP64 */
@@ -190,7 +192,7 @@ typedef struct ivm_matrix_opts {
                                   rounds and the pair kernel; the table: the point kernel) */
     int32_t tile_cap;       /* near-field tile capacity in triangles, 1..64; 0 = 64 */
     int32_t tile_treelets;  /* gather a near-field tile only for segment bundles whose box
-                               meets at most this many treelets, 1..32; 0 = 6 */
+                               meets at most this many treelets, 1..32; 0 = 2 */
     int32_t pair_chunk;     /* pair-to-wave mapping: consecutive undecided pairs a wave takes
                                from the queue at a time, 1..256; 0 = 4, or 32 when there are
                                more than 2048 pairs per wave */
@@ -259,8 +261,10 @@ ivm_status ivm_txrx_visibility_table(ivm_scene *scene, const ivm_matrix_opts *op
  * Table II: transmitter -> reference face -> aim face; orders 3 and 4 are the
  * iteration of Section II-C to the orders timed in Section IV-C).  d_M need not
  * be symmetric.  d_counts is int64[N][max_order + 1] with column 0 = line of
- * sight; counts are exact (orders 3 and 4 need 1 <= F <= 40960 and an LDS of
- * about 4 F bytes per block, else IVM_ERR_INVALID_ARGUMENT).  If d_paths is NULL
+ * sight; counts are exact (orders 3 and 4 need 1 <= F <= 40960, else
+ * IVM_ERR_INVALID_ARGUMENT).  Orders 3 and 4 are integer matrix products over
+ * slabs of snapshots held in the scene's pair scratch: such a call must not
+ * overlap a matrix call or another order-3/4 call on the same scene.  If d_paths is NULL
  * only counts are produced (asynchronous).  Otherwise d_offsets (int64[N *
  * max_order + 1]) receives CSR offsets of the lists (snapshot-major, order-minor)
  * and d_paths the k-tuples as int32 in lexicographic order; this mode

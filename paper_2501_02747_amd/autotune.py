@@ -40,7 +40,7 @@ KNOBS: Dict[str, Tuple[int, ...]] = {
     "pair_chunk": (0, 2, 4, 8, 16, 32, 64),
     "xcd_parts": (1, 8),
 }
-DEFAULTS = {"waves_per_cu": 16, "stack_depth": 24, "tile_cap": 64, "tile_treelets": 6, "pair_chunk": 0, "xcd_parts": 1}
+DEFAULTS = {"waves_per_cu": 24, "stack_depth": 24, "tile_cap": 64, "tile_treelets": 2, "pair_chunk": 0, "xcd_parts": 1}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ivm_autotune.json")
 
 

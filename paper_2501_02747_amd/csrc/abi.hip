@@ -53,7 +53,7 @@ TraverseOpts make_opts(const ivm_matrix_opts *o) {
     float eps = (o && o->eps > 0.f) ? o->eps : kDefaultEps;
     if (!(eps >= kDefaultEps)) eps = kDefaultEps;  // never below the sound margin (NaN -> default)
     t.eps6 = std::isinf(eps) ? INFINITY : 6.0f * eps;
-    int wpc = (o && o->waves_per_cu > 0) ? o->waves_per_cu : 16;
+    int wpc = (o && o->waves_per_cu > 0) ? o->waves_per_cu : kDefaultWavesPerCu;
     if (wpc > 64) wpc = 64;
     long long blocks = (long long)device_cu_count() * wpc / 4;
     if (blocks < 1) blocks = 1;
@@ -63,7 +63,7 @@ TraverseOpts make_opts(const ivm_matrix_opts *o) {
     t.no_tile = (o ? o->no_tile : 0) || t.exhaustive;
     const int cap = (o && o->tile_cap > 0) ? o->tile_cap : 64;
     t.tile_cap = cap > 64 ? 64 : cap;
-    const int tt = (o && o->tile_treelets > 0) ? o->tile_treelets : 6;
+    const int tt = (o && o->tile_treelets > 0) ? o->tile_treelets : kDefaultTileTreelets;
     t.tile_treelets = tt > kTreelets ? kTreelets : tt;
     const int pc = o ? o->pair_chunk : 0;
     t.pair_chunk = pc <= 0 ? 0 : (pc > 256 ? 256 : pc);
@@ -250,8 +250,11 @@ ivm_status ivm_image_tree_candidates(ivm_scene *scene, const uint64_t *d_M, int3
     const SceneDev &d = scene->s.dev;
     if (n_snap == 0) return IVM_OK;
     if (max_order >= 3 && !candidates_high_fits(d.F)) return IVM_ERR_INVALID_ARGUMENT;
-    if (launch_candidates_count(d, d_M, n_snap, d_tx_vis, d_rx_vis, d_los, max_order, d_counts, stream) != hipSuccess)
-        return IVM_ERR_HIP;
+    const hipError_t ce =
+        max_order >= 3
+            ? launch_candidates_high(scene->s, d_M, n_snap, d_tx_vis, d_rx_vis, d_los, max_order, d_counts, stream)
+            : launch_candidates_count(d, d_M, n_snap, d_tx_vis, d_rx_vis, d_los, max_order, d_counts, stream);
+    if (ce != hipSuccess) return IVM_ERR_HIP;
     if (!d_paths) {
         if (d_offsets && launch_candidates_offsets(n_snap, max_order, d_counts, d_offsets, stream) != hipSuccess)
             return IVM_ERR_HIP;

@@ -10,16 +10,14 @@
 // a bandwidth-bound stream of |tx| rows of M per snapshot.
 //
 // Orders 3 and 4 (the higher orders the paper iterates to, Section II-C and
-// Section IV-C) count walks through two vectors held in LDS, one block per
-// snapshot: v[g] = popcount(M[g] & rx), the walks g -> ... of one step that end
-// on an Rx-visible facet, and u[g] = sum over f in tx of M[f][g], the walks from
-// the Tx side that reach g in one step.  Then
-//   order 2 = sum over g in tx of v[g]
+// Section IV-C) are t^T M^(k-1) r written out with u = M^T t and v = M r:
+//   order 2 = sum over g of u[g] r[g]
 //   order 3 = sum over g of u[g] v[g]
-//   order 4 = sum over g of u[g] (sum over h in M[g] of v[h])
-// which is t^T M^(k-1) r written out; no symmetry of M is assumed.  Every term
-// is a non-negative integer, so the int64 sums are exact below 2^63 (F^4 bounds
-// them; F <= 40960 keeps F^4 < 2^63).
+//   order 4 = sum over h of (sum over g of u[g] M[g][h]) v[h]
+// computed for a slab of snapshots at a time as integer matrix products on the
+// matrix cores (below); no symmetry of M is assumed.  Every term is a
+// non-negative integer, so the int64 sums are exact below 2^63 (F^4 bounds
+// them; F <= 40960 keeps F^4 < 2^63 and u below 2^16).
 #include "ivm_internal.h"
 
 namespace ivm {
@@ -61,110 +59,310 @@ __global__ __launch_bounds__(256) void k_cand_count(int F, int W, const uint64_t
     }
 }
 
-constexpr int kHighThreads = 512;
-constexpr int kLanesPerRow = 8, kRowsPerWave = 64 / kLanesPerRow;
+// ---------------------------------------------------------------------------
+// orders 3 and 4 on the matrix cores
+// ---------------------------------------------------------------------------
+// Over a slab of snapshots the walk counts are bilinear forms of three dense
+// integer products (T, R: the slab's Tx and Rx rows; every factor is 0/1 but U):
+//   U = T M      U[n][g] = sum_f t_n[f] M[f][g]   (u of snapshot n)
+//   V = R M^T    V[n][g] = sum_h M[g][h] r_n[h]   (v of snapshot n)
+//   X = U M      X[n][h] = sum_g U[n][g] M[g][h]
+// order 2 = sum_g U r, order 3 = sum_g U V, order 4 = sum_h X V.  Each product
+// runs on v_mfma_i32_16x16x64_i8 (i8 x i8, exact int32 sums): the 0/1 operands
+// are bit rows expanded to bytes, and U < 2^16 enters X as two byte planes
+// a - 128 and b - 128 (U = a + 256 b), so X = X_a + 256 X_b + 32896 c[h] with
+// c[h] = sum_g M[g][h].  Every operand is read along its K index: M^T (bits,
+// zero-padded to Fp = 64 W rows) is built once per call.
+//
+// Tile: a block of 4 waves owns 64 snapshots x 256 facets; wave w the 64
+// facets of bit word 4 blockIdx.y + w, as 4 x 4 MFMA tiles of 16 x 16.  One K
+// step is one bit word (64 facets).  The 64-row A panel of a step (expanded
+// bits, or the byte planes of U) is staged once per block in LDS, double
+// buffered; each wave expands its own B bits in registers.  MFMA operands:
+// lane l holds row (or column) l % 16 and bytes 16 (l / 16) .. +15 of the K
+// step, byte v being K index 16 (l / 16) + v in both operands (the unit sums
+// over every byte pair alike); the result holds D[4 (l / 16) + v][l % 16].
 
-// LDS of k_cand_high for F facets: u as 16-bit halves of uint32 words (LDS
-// atomics are 32-bit; a count never exceeds F < 2^16, so halves never carry),
-// v as uint16 (a row popcount never exceeds F).
-__host__ __device__ inline size_t cand_high_lds(int F) {
-    const size_t uw = ((size_t)F + 1) / 2;
-    return 4 * uw + 2 * (((size_t)F + 1) & ~(size_t)1);
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kHiRows = 64;             // snapshots per block
+constexpr int kHiWaves = 4;             // bit words (64 facets each) per block
+constexpr int kHiPitch = 80;            // LDS bytes per panel row (64 + 16: conflict-free 16-byte reads)
+constexpr int kHiPanel = kHiRows * kHiPitch;
+
+// 16 bits -> 16 bytes of 0/1 (byte v = bit v): each nibble spread by one
+// 24-bit multiply (shifts 0, 7, 14, 21 place bit m at bit 8 m, no carries).
+__device__ inline i32x4 expand16(unsigned c) {
+    i32x4 r;
+    r[0] = (int)(((c & 15u) * 0x204081u) & 0x01010101u);
+    r[1] = (int)((((c >> 4) & 15u) * 0x204081u) & 0x01010101u);
+    r[2] = (int)((((c >> 8) & 15u) * 0x204081u) & 0x01010101u);
+    r[3] = (int)((((c >> 12) & 15u) * 0x204081u) & 0x01010101u);
+    return r;
 }
 
-__device__ inline unsigned long long block_sum_u64(unsigned long long v, unsigned long long *sh) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    v = wsum(v);
-    if (lane == 0) sh[wv] = v;
-    __syncthreads();
-    unsigned long long s = 0;
-    for (int k = 0; k < kHighThreads / 64; ++k) s += sh[k];
-    __syncthreads();
-    return s;
+// Scratch of the products inside the scene's pair scratch (see hi_slab).
+struct HiScratch {
+    uint64_t *mt;     // M^T bits, Fp x W words (rows >= F and bits >= F zero)
+    int *csum;        // c[h] = popcount(M^T row h), Fp
+    int8_t *ua, *ub;  // byte planes of U, NBp x Fp
+    uint16_t *v;      // V, NBp x Fp
+    int nbp;          // slab rows (a multiple of kHiRows)
+};
+
+// M^T and its row popcounts: wave (hw, chunk) transposes 64 x 64 blocks of
+// rows 64 gw .. +63 (gw over its chunk of words) and bit word hw by ballots.
+__global__ __launch_bounds__(256) void k_hi_transpose(int F, int W, int chunks, const uint64_t *M, uint64_t *mt,
+                                                      int *csum) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wave >= W * chunks) return;
+    const int hw = wave / chunks, ch = wave - (wave / chunks) * chunks;
+    const int per = (W + chunks - 1) / chunks, g0 = ch * per, g1 = min(W, g0 + per);
+    const int hb = F - 64 * hw;  // valid bits of word hw
+    const uint64_t hmask = hb >= 64 ? ~0ull : (hb > 0 ? (1ull << hb) - 1ull : 0ull);
+    int cnt = 0;
+    for (int gw = g0; gw < g1; ++gw) {
+        const int g = 64 * gw + lane;
+        const uint64_t x = g < F ? (M[(size_t)g * W + hw] & hmask) : 0ull;
+        uint64_t mine = 0;
+        for (int b = 0; b < 64; ++b) {
+            const uint64_t col = __ballot((x >> b) & 1ull);
+            if (lane == b) mine = col;
+        }
+        mt[(size_t)(64 * hw + lane) * W + gw] = mine;
+        cnt += __popcll(mine);
+    }
+    if (g1 > g0) atomicAdd(&csum[64 * hw + lane], cnt);
 }
 
-__global__ __launch_bounds__(kHighThreads) void k_cand_high(int F, int W, const uint64_t *M, int N,
-                                                            const uint64_t *txv, const uint64_t *rxv,
-                                                            const uint8_t *los, int K, int64_t *counts) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ unsigned long long red[kHighThreads / 64];
-    const int Fh = (F + 1) / 2;
-    unsigned *u = (unsigned *)lds;
-    unsigned short *v = (unsigned short *)(lds + 4 * (size_t)Fh);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = kHighThreads / 64;
-    const int grp = lane / kLanesPerRow, sub = lane % kLanesPerRow;
-    for (int n = blockIdx.x; n < N; n += gridDim.x) {
-        const uint64_t *t = txv + (size_t)n * W, *r = rxv + (size_t)n * W;
-        for (int i = tid; i < Fh; i += kHighThreads) u[i] = 0u;
+// counts[n][0] = line of sight, [1] = popcount(t & r), [2..K] = 0 (the product
+// kernels add into them).
+__global__ __launch_bounds__(256) void k_hi_init(int F, int W, int N, const uint64_t *txv, const uint64_t *rxv,
+                                                 const uint8_t *los, int K, int64_t *counts) {
+    const int lane = threadIdx.x & 63;
+    const int n = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (n >= N) return;
+    const uint64_t tail = (F & 63) ? (1ull << (F & 63)) - 1ull : ~0ull;
+    unsigned long long c1 = 0;
+    for (int w = lane; w < W; w += 64) {
+        uint64_t x = txv[(size_t)n * W + w] & rxv[(size_t)n * W + w];
+        if (w == W - 1) x &= tail;
+        c1 += __popcll(x);
+    }
+    c1 = wsum(c1);
+    if (lane == 0) {
+        int64_t *o = counts + (size_t)n * (K + 1);
+        o[0] = los[n] ? 1 : 0;
+        o[1] = (int64_t)c1;
+        for (int k = 2; k <= K; ++k) o[k] = 0;
+    }
+}
+
+// Sums of 16 lanes (one result row group) of a wave.
+__device__ inline unsigned long long sum16(unsigned long long x) {
+    for (int o = 8; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// Adds a wave's per-row partial sums (lane l: rows 16 i + 4 (l / 16) + v) into
+// the block's LDS row sums.
+__device__ inline void add_rows(unsigned long long (&p)[4][4], unsigned long long *rows) {
+    const int lane = threadIdx.x & 63;
+    for (int i = 0; i < 4; ++i)
+        for (int v = 0; v < 4; ++v) {
+            const unsigned long long s = sum16(p[i][v]);
+            if ((lane & 15) == 0) atomicAdd(&rows[16 * i + 4 * (lane >> 4) + v], s);
+        }
+}
+
+// U and V of a slab (rows n0 .. n0 + nb - 1), their byte planes and V stored,
+// orders 2 and 3 added into counts.
+__global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int nb, const uint64_t *txv,
+                                               const uint64_t *rxv, const uint64_t *M, HiScratch hs, int K,
+                                               int64_t *counts) {
+    __shared__ __align__(16) unsigned char panel[2][2][kHiPanel];  // [buffer][T, R]
+    __shared__ unsigned long long rows[2][kHiRows];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int rb = blockIdx.x * kHiRows;          // slab row of the block
+    const int cw = blockIdx.y * kHiWaves + wv;    // the wave's bit word (facets 64 cw ..)
+    const bool active = cw < W;
+    const size_t Fp = (size_t)64 * W;
+    const uint64_t tail = (F & 63) ? (1ull << (F & 63)) - 1ull : ~0ull;
+    if (tid < 2 * kHiRows) rows[tid >> 6][tid & 63] = 0ull;
+    // A panel producer: thread -> (source, row, 32-bit half)
+    const int pg = tid >> 7, pr = (tid >> 1) & 63, ph = tid & 1;
+    const int pn = n0 + rb + pr;
+    const bool prow = rb + pr < nb;
+    const uint32_t *psrc = (const uint32_t *)((pg ? rxv : txv) + (size_t)(prow ? pn : 0) * W);
+    // B rows of the wave: column g = 64 cw + 16 j + (lane & 15)
+    const int q = lane >> 4, c16 = lane & 15;
+    const uint64_t *bt[4], *bm[4];
+    bool bmv[4];
+    for (int j = 0; j < 4; ++j) {
+        const int g = 64 * (active ? cw : 0) + 16 * j + c16;
+        bt[j] = hs.mt + (size_t)g * W;
+        bmv[j] = active && g < F;
+        bm[j] = M + (size_t)(bmv[j] ? g : 0) * W;
+    }
+    i32x4 accU[4][4], accV[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            accU[i][j] = i32x4{0, 0, 0, 0};
+            accV[i][j] = i32x4{0, 0, 0, 0};
+        }
+    uint32_t pa = prow ? psrc[ph] : 0u;
+    uint64_t wt[4], wm[4];
+    for (int j = 0; j < 4; ++j) {
+        wt[j] = active ? bt[j][0] : 0ull;
+        wm[j] = bmv[j] ? bm[j][0] : 0ull;
+    }
+    for (int kw = 0; kw < W; ++kw) {
+        const int buf = kw & 1;
+        {
+            uint32_t h = pa;
+            if (kw == W - 1) h &= (uint32_t)(tail >> (32 * ph));
+            i32x4 *dst = (i32x4 *)(panel[buf][pg] + pr * kHiPitch + 32 * ph);
+            dst[0] = expand16(h & 0xffffu);
+            dst[1] = expand16(h >> 16);
+        }
+        if (kw + 1 < W && prow) pa = psrc[2 * (kw + 1) + ph];
         __syncthreads();
-        // one pass over the rows: v[g], and the rows of Tx-visible facets pushed into
-        // u.  Eight lanes share a row, so a wave keeps eight rows' loads in flight.
-        for (int g0 = wv * kRowsPerWave; g0 < F; g0 += nw * kRowsPerWave) {
-            const int g = g0 + grp;
-            unsigned c = 0;
-            if (g < F) {
-                const uint64_t *row = M + (size_t)g * W;
-                const bool in_t = (t[g >> 6] >> (g & 63)) & 1ull;
-                for (int w = sub; w < W; w += kLanesPerRow) {
-                    const uint64_t m = row[w];
-                    c += (unsigned)__popcll(m & r[w]);
-                    if (in_t) {
-                        uint64_t b = m;
-                        while (b) {
-                            const int h = w * 64 + __ffsll((long long)b) - 1;
-                            b &= b - 1;
-                            if (h >= F) break;
-                            atomicAdd(&u[h >> 1], 1u << (16 * (h & 1)));
+        if (active) {
+            i32x4 bU[4], bV[4];
+            for (int j = 0; j < 4; ++j) {
+                uint64_t m = wm[j];
+                if (kw == W - 1) m &= tail;
+                bU[j] = expand16((unsigned)(wt[j] >> (16 * q)) & 0xffffu);
+                bV[j] = expand16((unsigned)(m >> (16 * q)) & 0xffffu);
+            }
+            if (kw + 1 < W)
+                for (int j = 0; j < 4; ++j) {
+                    wt[j] = bt[j][kw + 1];
+                    wm[j] = bmv[j] ? bm[j][kw + 1] : 0ull;
+                }
+            for (int i = 0; i < 4; ++i) {
+                const int off = (16 * i + c16) * kHiPitch + 16 * q;
+                const i32x4 aT = *(const i32x4 *)(panel[buf][0] + off);
+                const i32x4 aR = *(const i32x4 *)(panel[buf][1] + off);
+                for (int j = 0; j < 4; ++j) {
+                    accU[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aT, bU[j], accU[i][j], 0, 0, 0);
+                    accV[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aR, bV[j], accV[i][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (active) {
+        unsigned long long p2[4][4], p3[4][4];
+        for (int i = 0; i < 4; ++i)
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * i + 4 * q + v, rl = rb + r;
+                unsigned long long s2 = 0, s3 = 0;
+                if (rl < nb) {
+                    const uint64_t rw = rxv[(size_t)(n0 + rl) * W + cw];
+                    for (int j = 0; j < 4; ++j) {
+                        const int g = 64 * cw + 16 * j + c16;
+                        const unsigned u = (unsigned)accU[i][j][v], vv = (unsigned)accV[i][j][v];
+                        if (g < F) {
+                            if ((rw >> (16 * j + c16)) & 1ull) s2 += u;
+                            s3 += (unsigned long long)u * vv;
+                        }
+                        const size_t e = (size_t)rl * Fp + g;
+                        hs.ua[e] = (int8_t)((int)(u & 255u) - 128);
+                        hs.ub[e] = (int8_t)((int)(u >> 8) - 128);
+                        hs.v[e] = (uint16_t)vv;
+                    }
+                }
+                p2[i][v] = s2;
+                p3[i][v] = s3;
+            }
+        add_rows(p2, rows[0]);
+        add_rows(p3, rows[1]);
+    }
+    __syncthreads();
+    if (tid < kHiRows && rb + tid < nb) {
+        int64_t *o = counts + (size_t)(n0 + rb + tid) * (K + 1);
+        atomicAdd((unsigned long long *)&o[2], rows[0][tid]);
+        atomicAdd((unsigned long long *)&o[3], rows[1][tid]);
+    }
+}
+
+// X = U M of a slab from the byte planes of U; order 4 added into counts.
+__global__ __launch_bounds__(256) void k_hi_x(int F, int W, int n0, int nb, HiScratch hs, int K, int64_t *counts) {
+    __shared__ __align__(16) unsigned char panel[2][2][kHiPanel];  // [buffer][plane a, plane b]
+    __shared__ unsigned long long rows[kHiRows];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int rb = blockIdx.x * kHiRows;
+    const int cw = blockIdx.y * kHiWaves + wv;
+    const bool active = cw < W;
+    const size_t Fp = (size_t)64 * W;
+    if (tid < kHiRows) rows[tid] = 0ull;
+    // A panel producer: thread -> (plane, row, 32-byte half); rows < nbp are in the slab
+    const int pg = tid >> 7, pr = (tid >> 1) & 63, ph = tid & 1;
+    const i32x4 *psrc = (const i32x4 *)((pg ? hs.ub : hs.ua) + (size_t)(rb + pr) * Fp + 32 * ph);
+    const int q = lane >> 4, c16 = lane & 15;
+    const uint64_t *bt[4];
+    for (int j = 0; j < 4; ++j) bt[j] = hs.mt + (size_t)(64 * (active ? cw : 0) + 16 * j + c16) * W;
+    i32x4 accA[4][4], accB[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            accA[i][j] = i32x4{0, 0, 0, 0};
+            accB[i][j] = i32x4{0, 0, 0, 0};
+        }
+    i32x4 pa0 = psrc[0], pa1 = psrc[1];
+    uint64_t wt[4];
+    for (int j = 0; j < 4; ++j) wt[j] = active ? bt[j][0] : 0ull;
+    for (int kw = 0; kw < W; ++kw) {
+        const int buf = kw & 1;
+        {
+            i32x4 *dst = (i32x4 *)(panel[buf][pg] + pr * kHiPitch + 32 * ph);
+            dst[0] = pa0;
+            dst[1] = pa1;
+        }
+        if (kw + 1 < W) {
+            pa0 = psrc[4 * (kw + 1)];      // 64 bytes per K step = 4 i32x4
+            pa1 = psrc[4 * (kw + 1) + 1];
+        }
+        __syncthreads();
+        if (active) {
+            i32x4 b[4];
+            for (int j = 0; j < 4; ++j) b[j] = expand16((unsigned)(wt[j] >> (16 * q)) & 0xffffu);
+            if (kw + 1 < W)
+                for (int j = 0; j < 4; ++j) wt[j] = bt[j][kw + 1];
+            for (int i = 0; i < 4; ++i) {
+                const int off = (16 * i + c16) * kHiPitch + 16 * q;
+                const i32x4 a0 = *(const i32x4 *)(panel[buf][0] + off);
+                const i32x4 a1 = *(const i32x4 *)(panel[buf][1] + off);
+                for (int j = 0; j < 4; ++j) {
+                    accA[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b[j], accA[i][j], 0, 0, 0);
+                    accB[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b[j], accB[i][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (active) {
+        unsigned long long p4[4][4];
+        long long cs[4];
+        for (int j = 0; j < 4; ++j) cs[j] = 32896ll * hs.csum[64 * cw + 16 * j + c16];
+        for (int i = 0; i < 4; ++i)
+            for (int v = 0; v < 4; ++v) {
+                const int rl = rb + 16 * i + 4 * q + v;
+                unsigned long long s4 = 0;
+                if (rl < nb)
+                    for (int j = 0; j < 4; ++j) {
+                        const int h = 64 * cw + 16 * j + c16;
+                        if (h < F) {
+                            const long long x = (long long)accA[i][j][v] + 256ll * accB[i][j][v] + cs[j];
+                            s4 += (unsigned long long)x * hs.v[(size_t)rl * Fp + h];
                         }
                     }
-                }
+                p4[i][v] = s4;
             }
-            for (int o = kLanesPerRow / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
-            if (g < F && sub == 0) v[g] = (unsigned short)c;
-        }
-        __syncthreads();
-        unsigned long long c1 = 0, c2 = 0, c3 = 0, c4 = 0;
-        if (wv == 0)
-            for (int w = lane; w < W; w += 64) c1 += __popcll(t[w] & r[w]);
-        for (int g = tid; g < F; g += kHighThreads) {
-            const unsigned ug = (u[g >> 1] >> (16 * (g & 1))) & 0xffffu;
-            const unsigned vg = v[g];
-            c3 += (unsigned long long)ug * vg;
-            if ((t[g >> 6] >> (g & 63)) & 1ull) c2 += vg;
-        }
-        if (K >= 4)
-            for (int g0 = wv * kRowsPerWave; g0 < F; g0 += nw * kRowsPerWave) {
-                const int g = g0 + grp;
-                if (g >= F) continue;
-                const unsigned ug = (u[g >> 1] >> (16 * (g & 1))) & 0xffffu;
-                if (ug == 0u) continue;
-                const uint64_t *row = M + (size_t)g * W;
-                unsigned long long sv = 0;
-                for (int w = sub; w < W; w += kLanesPerRow) {
-                    uint64_t b = row[w];
-                    while (b) {
-                        const int h = w * 64 + __ffsll((long long)b) - 1;
-                        b &= b - 1;
-                        if (h >= F) break;
-                        sv += v[h];
-                    }
-                }
-                c4 += (unsigned long long)ug * sv;  // (each lane its words' share; summed below)
-            }
-        c1 = block_sum_u64(c1, red);
-        c2 = block_sum_u64(c2, red);
-        c3 = block_sum_u64(c3, red);
-        c4 = block_sum_u64(c4, red);
-        if (tid == 0) {
-            int64_t *o = counts + (size_t)n * (K + 1);
-            o[0] = los[n] ? 1 : 0;
-            o[1] = (int64_t)c1;
-            o[2] = (int64_t)c2;
-            o[3] = (int64_t)c3;
-            if (K >= 4) o[4] = (int64_t)c4;
-        }
-        // (block_sum_u64 ends on a barrier: u may be cleared for the next snapshot)
+        add_rows(p4, rows);
     }
+    __syncthreads();
+    if (tid < kHiRows && rb + tid < nb)
+        atomicAdd((unsigned long long *)&counts[(size_t)(n0 + rb + tid) * (K + 1) + 4], rows[tid]);
 }
 
 // offsets[n*K + k-1] = start of list (n, k) in int32 elements; offsets[N*K] = total.
@@ -328,30 +526,60 @@ static unsigned waves_grid(int N) {
     return (unsigned)b;
 }
 
-bool candidates_high_fits(int F) {
-    if (F < 1 || F > kCandHighMaxF) return false;
-    int dev = 0, lds = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return false;
-    return cand_high_lds(F) + 64 * sizeof(unsigned long long) <= (size_t)lds;
+bool candidates_high_fits(int F) { return F >= 1 && F <= kCandHighMaxF; }
+
+// The products' scratch inside the scene's pair scratch [cand, hi_end): M^T,
+// c, then a slab of U planes and V as large as the rest holds (the layout
+// guarantees kHiMinSlab snapshots), never more than N needs.
+static bool hi_scratch(const Scene &sc, int N, HiScratch &hs) {
+    const size_t W = (size_t)sc.dev.W, Fp = 64 * W;
+    const size_t cap = sc.lay.hi_end - sc.lay.cand, fixed = Fp * W * 8 + Fp * 4;
+    if (cap < fixed + (size_t)kHiRows * Fp * 4) return false;
+    size_t nbp = (cap - fixed) / (4 * Fp) / kHiRows * kHiRows;
+    const size_t need = ((size_t)N + kHiRows - 1) / kHiRows * kHiRows;
+    if (nbp > need) nbp = need;
+    char *p = (char *)sc.ws + sc.lay.cand;
+    hs.mt = (uint64_t *)p;
+    p += Fp * W * 8;
+    hs.csum = (int *)p;
+    p += Fp * 4;
+    hs.ua = (int8_t *)p;
+    p += nbp * Fp;
+    hs.ub = (int8_t *)p;
+    p += nbp * Fp;
+    hs.v = (uint16_t *)p;
+    hs.nbp = (int)nbp;
+    return true;
+}
+
+hipError_t launch_candidates_high(const Scene &sc, const uint64_t *M, int N, const uint64_t *txv,
+                                  const uint64_t *rxv, const uint8_t *los, int K, int64_t *counts, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const SceneDev &d = sc.dev;
+    HiScratch hs;
+    if (K < 3 || K > 4 || !candidates_high_fits(d.F) || !hi_scratch(sc, N, hs)) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_u32((uint32_t *)hs.csum, 0u, (size_t)64 * d.W, s);
+    if (e != hipSuccess) return e;
+    int chunks = (2048 + d.W - 1) / d.W;  // about 2048 transposing waves
+    if (chunks > d.W) chunks = d.W;
+    const long long tw = (long long)d.W * chunks;
+    hipLaunchKernelGGL(k_hi_transpose, dim3((unsigned)((tw + 3) / 4)), dim3(256), 0, s, d.F, d.W, chunks, M, hs.mt,
+                       hs.csum);
+    hipLaunchKernelGGL(k_hi_init, dim3((unsigned)(((long long)N + 3) / 4)), dim3(256), 0, s, d.F, d.W, N, txv, rxv,
+                       los, K, counts);
+    const unsigned gy = (unsigned)((d.W + kHiWaves - 1) / kHiWaves);
+    for (int n0 = 0; n0 < N; n0 += hs.nbp) {
+        const int nb = N - n0 < hs.nbp ? N - n0 : hs.nbp;
+        const dim3 grid((unsigned)((nb + kHiRows - 1) / kHiRows), gy);
+        hipLaunchKernelGGL(k_hi_uv, grid, dim3(256), 0, s, d.F, d.W, N, n0, nb, txv, rxv, M, hs, K, counts);
+        if (K >= 4) hipLaunchKernelGGL(k_hi_x, grid, dim3(256), 0, s, d.F, d.W, n0, nb, hs, K, counts);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_candidates_count(const SceneDev &d, const uint64_t *M, int N, const uint64_t *txv,
                                    const uint64_t *rxv, const uint8_t *los, int K, int64_t *counts, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    if (K >= 3) {
-        const size_t lds = cand_high_lds(d.F);
-        if (lds > 65536) {
-            const hipError_t e = hipFuncSetAttribute((const void *)k_cand_high,
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-        }
-        const unsigned grid = (unsigned)(N < 8192 ? N : 8192);
-        hipLaunchKernelGGL(k_cand_high, dim3(grid), dim3(kHighThreads), lds, s, d.F, d.W, M, N, txv, rxv, los, K,
-                           counts);
-        return hipGetLastError();
-    }
     hipLaunchKernelGGL(k_cand_count, dim3(waves_grid(N)), dim3(256), 0, s, d.F, d.W, M, N, txv, rxv, los, K, counts);
     return hipGetLastError();
 }

@@ -14,6 +14,8 @@ constexpr int kWave = 64;
 constexpr int kTreelets = 32;      // top-level subtrees: contiguous equal-count Morton ranges
 constexpr int kLeafMax = 4;        // subtrees of <= kLeafMax triangles become leaves
 constexpr int kDefaultStack = 24;
+constexpr int kDefaultWavesPerCu = 24;    // persistent grid: waves per compute unit
+constexpr int kDefaultTileTreelets = 2;   // near-field tile only for bundles meeting <= this many treelets
 constexpr int kMaxSamplesPerFacet = IVM_MAX_SAMPLES_PER_FACET;
 constexpr float kDefaultEps = 1e-5f;
 constexpr int kHullMax = 8;       // sample convex hull points kept per facet (0 = none kept)
@@ -135,7 +137,7 @@ struct SceneDev {
 struct Layout {
     size_t tri, tri_orig, tri_group, nodes, tl_box, tl_root, fplane, fbox, soff, smp, sfacet;
     size_t status, extent, ibox, keys, vals, keys2, vals2, node_child, node_range, node_box;
-    size_t ffirst, cand, done, und, uprefix, prefix, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
+    size_t ffirst, cand, done, und, uprefix, prefix, hi, hi_end, queue, learned, scan_tmp, tri_caller, fhull, fhull_n, scluster, fchull, fchull_n, ffeat, fnorm;
     size_t fflags, fsolid, sol_cnt, sol_off, sol_fac, sol_rec, sol_plane, sol_nver, nodes4, sol_box;
     size_t grid_p, grid_cnt, grid_off, grid_list, grid_ent;
     size_t learned_bytes;
@@ -228,7 +230,11 @@ hipError_t launch_points(Scene &sc, const TraverseOpts &o, int N, const float *t
 // largest F they accept (F^4 < 2^63 keeps the int64 counts exact), and whether
 // the device's LDS per block holds them for F facets.
 constexpr int kCandHighMaxF = 40960;
+constexpr int kHiMinSlab = 256;  // snapshots of the smallest orders-3/4 slab the layout must hold
 bool candidates_high_fits(int F);
+// Orders 3 and 4: M^T and a slab of products in the pair scratch [cand, hi_end).
+hipError_t launch_candidates_high(const Scene &sc, const uint64_t *M, int N, const uint64_t *txv,
+                                  const uint64_t *rxv, const uint8_t *los, int K, int64_t *counts, hipStream_t s);
 hipError_t launch_candidates_count(const SceneDev &d, const uint64_t *M, int N, const uint64_t *txv,
                                    const uint64_t *rxv, const uint8_t *los, int K, int64_t *counts,
                                    hipStream_t s);

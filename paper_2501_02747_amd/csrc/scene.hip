@@ -86,6 +86,15 @@ Layout make_layout(int F, int T, int S, bool learned, int n_solids) {
     L.und = take(items * sizeof(uint64_t));
     L.uprefix = take((items + 1) * sizeof(uint32_t));
     L.prefix = take((items + 1) * sizeof(uint32_t));
+    {
+        // orders 3-4 of the candidate counts reuse [cand, hi_end) between matrix
+        // calls: M^T (64 W rows of W words), the column sums and a slab of at
+        // least kHiMinSlab snapshots (two byte planes and a uint16 row each)
+        const size_t Fp = 64 * W, need = Fp * W * 8 + Fp * 4 + (size_t)kHiMinSlab * Fp * 4;
+        const size_t have = o - L.cand;
+        L.hi = take(need > have ? need - have : 0);
+        L.hi_end = o;
+    }
     L.scan_tmp = take(((items + 1) / 4096 + 2) * sizeof(uint32_t));
     L.queue = take(256);
     L.learned_bytes = learned ? Fn * (Fn - 1) / 2 * sizeof(uint64_t) : 0;

@@ -1110,7 +1110,7 @@ __device__ __forceinline__ unsigned certify_subpairs(const SceneDev &sc, int i, 
 
 constexpr int kTile = 64;       // near-field tile capacity (triangle ranks)
 constexpr int kFrontier = 128;  // cooperative traversal frontier capacity
-// (a tile is gathered only when the bundle box meets at most TraverseOpts::tile_treelets treelets, 6 by default)
+// (a tile is gathered only when the bundle box meets at most TraverseOpts::tile_treelets treelets, kDefaultTileTreelets by default)
 
 __device__ inline bool box_overlap(float lx, float ly, float lz, float hx, float hy, float hz, const float lo[3],
                                    const float hi[3]) {

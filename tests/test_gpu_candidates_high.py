@@ -188,6 +188,93 @@ def test_orders_3_4_full_size(oracle_mod, ivm):
         assert (counts.cpu().numpy() == oracle_mod.candidates_matmul(S, tv, rv, los, K)).all(), K
 
 
+def _pack_sparse(ivm, S, F):
+    """Bit rows of a scipy sparse 0/1 matrix without a dense copy."""
+    import scipy.sparse as sps
+    C = sps.coo_matrix(S)
+    W = (F + 63) // 64
+    words = np.zeros((F, W), np.uint64)
+    np.bitwise_or.at(words, (C.row, C.col >> 6), np.left_shift(np.uint64(1), (C.col & 63).astype(np.uint64)))
+    return words.view(np.int64)
+
+
+@pytest.mark.parametrize("F,N,seed", [(130, 600, 4), (64, 300, 5), (257, 517, 6)])
+def test_orders_3_4_many_slabs(oracle_mod, ivm, F, N, seed):
+    """More snapshots than one slab of the products holds (small scenes keep a
+    slab of 256 snapshots): several slabs and a ragged last one, F on and off a
+    word boundary; a second call and a call after a matrix call (which reuses
+    the same scratch) return the same counts."""
+    import torch
+    _log(f"[orders 3-4 slabs] F={F} N={N} seed={seed}")
+    rng = np.random.default_rng(300 + seed)
+    M = rng.random((F, F)) < 0.1
+    np.fill_diagonal(M, False)
+    tv = rng.random((N, F)) < 0.2
+    rv = rng.random((N, F)) < 0.2
+    tv[N - 1] = True
+    rv[N - 1] = True
+    los = rng.random(N) < 0.5
+    g = _plate_row_scene(ivm, F)
+    dM, dtv, drv, dlos = _upload(ivm, M, tv, rv, los)
+    co = oracle_mod.candidates_matmul(M, tv, rv, los, 4)
+    c1 = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 4)
+    c3 = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 3)
+    torch.cuda.synchronize()
+    assert (c1.cpu().numpy() == co).all()
+    assert (c3.cpu().numpy() == co[:, :4]).all()
+    ivm.ivm_intervisibility_matrix(g)
+    c2 = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 4)
+    torch.cuda.synchronize()
+    assert (c2.cpu().numpy() == co).all()
+
+
+def test_orders_3_4_large_walk_counts(oracle_mod, ivm):
+    """Dense rows: u above 255 (both byte planes of the products carry) at
+    F = 1000, and u above 32767 at F = 33000 (a facet every facet sees, Tx
+    seeing all): counts against the oracle's integer products."""
+    import torch
+    import scipy.sparse as sps
+    _log("[orders 3-4 large u] F=1000")
+    rng = np.random.default_rng(4000)
+    F, N = 1000, 70
+    M = rng.random((F, F)) < 0.5
+    np.fill_diagonal(M, False)
+    tv = rng.random((N, F)) < 0.7
+    rv = rng.random((N, F)) < 0.7
+    tv[:5] = True
+    los = rng.random(N) < 0.5
+    g = _plate_row_scene(ivm, F)
+    dM, dtv, drv, dlos = _upload(ivm, M, tv, rv, los)
+    co = oracle_mod.candidates_matmul(M, tv, rv, los, 4)
+    assert (co[:, :4] >= 0).all() and co[:5, 4].min() > 2 ** 32
+    c = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 4)
+    torch.cuda.synchronize()
+    assert (c.cpu().numpy() == co).all()
+
+    _log("[orders 3-4 large u] F=33000")
+    F, N, deg, hub = 33000, 6, 3, 12345
+    rows = np.concatenate([np.repeat(np.arange(F), deg), np.arange(F), np.full(40, hub)])
+    cols = np.concatenate([rng.integers(0, F, F * deg), np.full(F, hub), rng.integers(0, F, 40)])
+    S = sps.coo_matrix((np.ones(len(rows), np.int8), (rows, cols)), shape=(F, F)).tocsr()
+    S = (S > 0).tolil()
+    S.setdiag(0)
+    S = S.tocsr().astype(np.int8)
+    S.eliminate_zeros()
+    tv = rng.random((N, F)) < 0.02
+    rv = rng.random((N, F)) < 0.02
+    tv[0] = True
+    rv[0, hub] = True
+    los = np.zeros(N, bool)
+    g = _plate_row_scene(ivm, F)
+    dM = torch.as_tensor(_pack_sparse(ivm, S, F)).cuda()
+    dtv, drv = torch.as_tensor(ivm.pack_bits(tv)).cuda(), torch.as_tensor(ivm.pack_bits(rv)).cuda()
+    dlos = torch.as_tensor(los.astype(np.uint8)).cuda()
+    co = oracle_mod.candidates_matmul(S, tv, rv, los, 4)
+    c = ivm.ivm_image_tree_candidates(g, dM, dtv, drv, dlos, 4)
+    torch.cuda.synchronize()
+    assert (c.cpu().numpy() == co).all()
+
+
 def test_order_above_4_rejected(ivm):
     import torch
     g = _plate_row_scene(ivm, 10)
