@@ -87,8 +87,10 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kHiRows = 64;             // snapshots per block
 constexpr int kHiWaves = 4;             // bit words (64 facets each) per block
-constexpr int kHiPitch = 80;            // LDS bytes per panel row (64 + 16: conflict-free 16-byte reads)
-constexpr int kHiPanel = kHiRows * kHiPitch;
+#ifndef IVM_HI_KS
+#define IVM_HI_KS 4
+#endif
+constexpr int kHiKs = IVM_HI_KS;        // bit words (64 facets each) per K step
 
 // 16 bits -> 16 bytes of 0/1 (byte v = bit v): each nibble spread by one
 // 24-bit multiply (shifts 0, 7, 14, 21 place bit m at bit 8 m, no carries).
@@ -177,24 +179,35 @@ __device__ inline void add_rows(unsigned long long (&p)[4][4], unsigned long lon
 }
 
 // U and V of a slab (rows n0 .. n0 + nb - 1), their byte planes and V stored,
-// orders 2 and 3 added into counts.
+// orders 2 and 3 added into counts.  A K step is KS bit words.
+template <int KS>
 __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int nb, const uint64_t *txv,
                                                const uint64_t *rxv, const uint64_t *M, HiScratch hs, int K,
                                                int64_t *counts) {
-    __shared__ __align__(16) unsigned char panel[2][2][kHiPanel];  // [buffer][T, R]
-    __shared__ unsigned long long rows[2][kHiRows];
+    constexpr int kPitch = 64 * KS + 16;              // LDS bytes per panel row (conflict-free 16-byte reads)
+    constexpr int kItems = 2 * kHiRows * KS / 256;    // panel words a thread expands per step
+    static_assert(kItems >= 1 && 2 * kHiRows * KS % 256 == 0, "panel split");
+    extern __shared__ __align__(16) unsigned char lds_hi[];
+    unsigned char *panel = lds_hi;                    // [buffer][T, R][row][kPitch]
+    unsigned long long *rows = (unsigned long long *)(lds_hi + 4 * kHiRows * kPitch);  // [2][kHiRows]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int rb = blockIdx.x * kHiRows;          // slab row of the block
     const int cw = blockIdx.y * kHiWaves + wv;    // the wave's bit word (facets 64 cw ..)
     const bool active = cw < W;
     const size_t Fp = (size_t)64 * W;
     const uint64_t tail = (F & 63) ? (1ull << (F & 63)) - 1ull : ~0ull;
-    if (tid < 2 * kHiRows) rows[tid >> 6][tid & 63] = 0ull;
-    // A panel producer: thread -> (source, row, 32-bit half)
-    const int pg = tid >> 7, pr = (tid >> 1) & 63, ph = tid & 1;
-    const int pn = n0 + rb + pr;
-    const bool prow = rb + pr < nb;
-    const uint32_t *psrc = (const uint32_t *)((pg ? rxv : txv) + (size_t)(prow ? pn : 0) * W);
+    if (tid < 2 * kHiRows) rows[tid] = 0ull;
+    // panel producer: item -> (source, row, word of the step)
+    const uint64_t *psrc[kItems];
+    int pdst[kItems], psw[kItems];
+    bool prow[kItems];
+    for (int p = 0; p < kItems; ++p) {
+        const int it = tid + 256 * p, src = it / (kHiRows * KS), r = (it / KS) % kHiRows;
+        psw[p] = it % KS;
+        prow[p] = rb + r < nb;
+        psrc[p] = (src ? rxv : txv) + (size_t)(prow[p] ? n0 + rb + r : 0) * W;
+        pdst[p] = src * kHiRows * kPitch + r * kPitch + 64 * psw[p];
+    }
     // B rows of the wave: column g = 64 cw + 16 j + (lane & 15)
     const int q = lane >> 4, c16 = lane & 15;
     const uint64_t *bt[4], *bm[4];
@@ -211,40 +224,54 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
             accU[i][j] = i32x4{0, 0, 0, 0};
             accV[i][j] = i32x4{0, 0, 0, 0};
         }
-    uint32_t pa = prow ? psrc[ph] : 0u;
-    uint64_t wt[4], wm[4];
-    for (int j = 0; j < 4; ++j) {
-        wt[j] = active ? bt[j][0] : 0ull;
-        wm[j] = bmv[j] ? bm[j][0] : 0ull;
-    }
-    for (int kw = 0; kw < W; ++kw) {
-        const int buf = kw & 1;
-        {
-            uint32_t h = pa;
-            if (kw == W - 1) h &= (uint32_t)(tail >> (32 * ph));
-            i32x4 *dst = (i32x4 *)(panel[buf][pg] + pr * kHiPitch + 32 * ph);
-            dst[0] = expand16(h & 0xffffu);
-            dst[1] = expand16(h >> 16);
+    // raw bit words: the panel's (pa) and the wave's B rows (wt: M^T rows, wm: M
+    // rows); each B word is reloaded with the next step's right after it has
+    // been expanded, so one register set carries a step of load latency
+    uint64_t pa[kItems], wt[4][KS], wm[4][KS];
+    auto fetch_a = [&](int kw0) {
+        for (int p = 0; p < kItems; ++p) {
+            const int kw = kw0 + psw[p];
+            uint64_t x = (prow[p] && kw < W) ? psrc[p][kw] : 0ull;
+            if (kw == W - 1) x &= tail;
+            pa[p] = x;
         }
-        if (kw + 1 < W && prow) pa = psrc[2 * (kw + 1) + ph];
+    };
+    auto fetch_b = [&](int j, int kw, uint64_t &t, uint64_t &m) {
+        t = (active && kw < W) ? bt[j][kw] : 0ull;
+        uint64_t x = (bmv[j] && kw < W) ? bm[j][kw] : 0ull;
+        if (kw == W - 1) x &= tail;
+        m = x;
+    };
+    fetch_a(0);
+    for (int s = 0; s < KS; ++s)
+        for (int j = 0; j < 4; ++j) fetch_b(j, s, wt[j][s], wm[j][s]);
+    const int steps = (W + KS - 1) / KS;
+    for (int st = 0; st < steps; ++st) {
+        unsigned char *pb = panel + (st & 1) * 2 * kHiRows * kPitch;
+        for (int p = 0; p < kItems; ++p) {
+            i32x4 *dst = (i32x4 *)(pb + pdst[p]);
+            const uint64_t x = pa[p];
+            dst[0] = expand16((unsigned)x & 0xffffu);
+            dst[1] = expand16((unsigned)(x >> 16) & 0xffffu);
+            dst[2] = expand16((unsigned)(x >> 32) & 0xffffu);
+            dst[3] = expand16((unsigned)(x >> 48));
+        }
+        fetch_a((st + 1) * KS);
         __syncthreads();
-        if (active) {
+        // (words past W and the columns of an inactive wave are zero operands:
+        // their products add nothing, and the loop stays branch-free so the
+        // accumulators keep their registers)
+        for (int s = 0; s < KS; ++s) {
             i32x4 bU[4], bV[4];
             for (int j = 0; j < 4; ++j) {
-                uint64_t m = wm[j];
-                if (kw == W - 1) m &= tail;
-                bU[j] = expand16((unsigned)(wt[j] >> (16 * q)) & 0xffffu);
-                bV[j] = expand16((unsigned)(m >> (16 * q)) & 0xffffu);
+                bU[j] = expand16((unsigned)(wt[j][s] >> (16 * q)) & 0xffffu);
+                bV[j] = expand16((unsigned)(wm[j][s] >> (16 * q)) & 0xffffu);
+                fetch_b(j, (st + 1) * KS + s, wt[j][s], wm[j][s]);
             }
-            if (kw + 1 < W)
-                for (int j = 0; j < 4; ++j) {
-                    wt[j] = bt[j][kw + 1];
-                    wm[j] = bmv[j] ? bm[j][kw + 1] : 0ull;
-                }
             for (int i = 0; i < 4; ++i) {
-                const int off = (16 * i + c16) * kHiPitch + 16 * q;
-                const i32x4 aT = *(const i32x4 *)(panel[buf][0] + off);
-                const i32x4 aR = *(const i32x4 *)(panel[buf][1] + off);
+                const int off = (16 * i + c16) * kPitch + 64 * s + 16 * q;
+                const i32x4 aT = *(const i32x4 *)(pb + off);
+                const i32x4 aR = *(const i32x4 *)(pb + kHiRows * kPitch + off);
                 for (int j = 0; j < 4; ++j) {
                     accU[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aT, bU[j], accU[i][j], 0, 0, 0);
                     accV[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aR, bV[j], accV[i][j], 0, 0, 0);
@@ -276,30 +303,44 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
                 p2[i][v] = s2;
                 p3[i][v] = s3;
             }
-        add_rows(p2, rows[0]);
-        add_rows(p3, rows[1]);
+        add_rows(p2, rows);
+        add_rows(p3, rows + kHiRows);
     }
     __syncthreads();
     if (tid < kHiRows && rb + tid < nb) {
         int64_t *o = counts + (size_t)(n0 + rb + tid) * (K + 1);
-        atomicAdd((unsigned long long *)&o[2], rows[0][tid]);
-        atomicAdd((unsigned long long *)&o[3], rows[1][tid]);
+        atomicAdd((unsigned long long *)&o[2], rows[tid]);
+        atomicAdd((unsigned long long *)&o[3], rows[kHiRows + tid]);
     }
 }
 
+template <int KS>
+constexpr size_t hi_lds() { return (size_t)4 * kHiRows * (64 * KS + 16) + 2 * kHiRows * sizeof(unsigned long long); }
+
 // X = U M of a slab from the byte planes of U; order 4 added into counts.
+template <int KS>
 __global__ __launch_bounds__(256) void k_hi_x(int F, int W, int n0, int nb, HiScratch hs, int K, int64_t *counts) {
-    __shared__ __align__(16) unsigned char panel[2][2][kHiPanel];  // [buffer][plane a, plane b]
-    __shared__ unsigned long long rows[kHiRows];
+    constexpr int kPitch = 64 * KS + 16;
+    constexpr int kItems = 2 * kHiRows * KS * 4 / 256;  // 16-byte panel chunks a thread stages per step
+    static_assert(2 * kHiRows * KS * 4 % 256 == 0, "panel split");
+    extern __shared__ __align__(16) unsigned char lds_hi[];
+    unsigned char *panel = lds_hi;                    // [buffer][plane a, plane b][row][kPitch]
+    unsigned long long *rows = (unsigned long long *)(lds_hi + 4 * kHiRows * kPitch);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int rb = blockIdx.x * kHiRows;
     const int cw = blockIdx.y * kHiWaves + wv;
     const bool active = cw < W;
     const size_t Fp = (size_t)64 * W;
     if (tid < kHiRows) rows[tid] = 0ull;
-    // A panel producer: thread -> (plane, row, 32-byte half); rows < nbp are in the slab
-    const int pg = tid >> 7, pr = (tid >> 1) & 63, ph = tid & 1;
-    const i32x4 *psrc = (const i32x4 *)((pg ? hs.ub : hs.ua) + (size_t)(rb + pr) * Fp + 32 * ph);
+    // panel producer: chunk -> (plane, row, 16 bytes of the step); rows < nbp are in the slab
+    const int8_t *psrc[kItems];
+    int pdst[kItems], pk[kItems];
+    for (int p = 0; p < kItems; ++p) {
+        const int it = tid + 256 * p, pl = it / (kHiRows * KS * 4), r = (it / (KS * 4)) % kHiRows, c = it % (KS * 4);
+        pk[p] = c >> 2;                                // word of the step
+        psrc[p] = (pl ? hs.ub : hs.ua) + (size_t)(rb + r) * Fp + 16 * c;
+        pdst[p] = pl * kHiRows * kPitch + r * kPitch + 16 * c;
+    }
     const int q = lane >> 4, c16 = lane & 15;
     const uint64_t *bt[4];
     for (int j = 0; j < 4; ++j) bt[j] = hs.mt + (size_t)(64 * (active ? cw : 0) + 16 * j + c16) * W;
@@ -309,30 +350,32 @@ __global__ __launch_bounds__(256) void k_hi_x(int F, int W, int n0, int nb, HiSc
             accA[i][j] = i32x4{0, 0, 0, 0};
             accB[i][j] = i32x4{0, 0, 0, 0};
         }
-    i32x4 pa0 = psrc[0], pa1 = psrc[1];
-    uint64_t wt[4];
-    for (int j = 0; j < 4; ++j) wt[j] = active ? bt[j][0] : 0ull;
-    for (int kw = 0; kw < W; ++kw) {
-        const int buf = kw & 1;
-        {
-            i32x4 *dst = (i32x4 *)(panel[buf][pg] + pr * kHiPitch + 32 * ph);
-            dst[0] = pa0;
-            dst[1] = pa1;
-        }
-        if (kw + 1 < W) {
-            pa0 = psrc[4 * (kw + 1)];      // 64 bytes per K step = 4 i32x4
-            pa1 = psrc[4 * (kw + 1) + 1];
-        }
+    i32x4 pa[kItems];
+    uint64_t wt[4][KS];
+    auto fetch_a = [&](int kw0) {
+        for (int p = 0; p < kItems; ++p)
+            pa[p] = kw0 + pk[p] < W ? *(const i32x4 *)(psrc[p] + 64 * (size_t)kw0) : i32x4{0, 0, 0, 0};
+    };
+    fetch_a(0);
+    for (int s = 0; s < KS; ++s)
+        for (int j = 0; j < 4; ++j) wt[j][s] = (active && s < W) ? bt[j][s] : 0ull;
+    const int steps = (W + KS - 1) / KS;
+    for (int st = 0; st < steps; ++st) {
+        unsigned char *pb = panel + (st & 1) * 2 * kHiRows * kPitch;
+        for (int p = 0; p < kItems; ++p) *(i32x4 *)(pb + pdst[p]) = pa[p];
+        fetch_a((st + 1) * KS);
         __syncthreads();
-        if (active) {
+        for (int s = 0; s < KS; ++s) {  // (zero operands past W and for an inactive wave)
             i32x4 b[4];
-            for (int j = 0; j < 4; ++j) b[j] = expand16((unsigned)(wt[j] >> (16 * q)) & 0xffffu);
-            if (kw + 1 < W)
-                for (int j = 0; j < 4; ++j) wt[j] = bt[j][kw + 1];
+            for (int j = 0; j < 4; ++j) {
+                b[j] = expand16((unsigned)(wt[j][s] >> (16 * q)) & 0xffffu);
+                const int kw = (st + 1) * KS + s;
+                wt[j][s] = (active && kw < W) ? bt[j][kw] : 0ull;
+            }
             for (int i = 0; i < 4; ++i) {
-                const int off = (16 * i + c16) * kHiPitch + 16 * q;
-                const i32x4 a0 = *(const i32x4 *)(panel[buf][0] + off);
-                const i32x4 a1 = *(const i32x4 *)(panel[buf][1] + off);
+                const int off = (16 * i + c16) * kPitch + 64 * s + 16 * q;
+                const i32x4 a0 = *(const i32x4 *)(pb + off);
+                const i32x4 a1 = *(const i32x4 *)(pb + kHiRows * kPitch + off);
                 for (int j = 0; j < 4; ++j) {
                     accA[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b[j], accA[i][j], 0, 0, 0);
                     accB[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b[j], accB[i][j], 0, 0, 0);
@@ -567,12 +610,18 @@ hipError_t launch_candidates_high(const Scene &sc, const uint64_t *M, int N, con
                        hs.csum);
     hipLaunchKernelGGL(k_hi_init, dim3((unsigned)(((long long)N + 3) / 4)), dim3(256), 0, s, d.F, d.W, N, txv, rxv,
                        los, K, counts);
+    constexpr size_t lds = hi_lds<kHiKs>();
+    if ((e = hipFuncSetAttribute((const void *)k_hi_uv<kHiKs>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+            hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)k_hi_x<kHiKs>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+            hipSuccess)
+        return e;
     const unsigned gy = (unsigned)((d.W + kHiWaves - 1) / kHiWaves);
     for (int n0 = 0; n0 < N; n0 += hs.nbp) {
         const int nb = N - n0 < hs.nbp ? N - n0 : hs.nbp;
         const dim3 grid((unsigned)((nb + kHiRows - 1) / kHiRows), gy);
-        hipLaunchKernelGGL(k_hi_uv, grid, dim3(256), 0, s, d.F, d.W, N, n0, nb, txv, rxv, M, hs, K, counts);
-        if (K >= 4) hipLaunchKernelGGL(k_hi_x, grid, dim3(256), 0, s, d.F, d.W, n0, nb, hs, K, counts);
+        hipLaunchKernelGGL(k_hi_uv<kHiKs>, grid, dim3(256), lds, s, d.F, d.W, N, n0, nb, txv, rxv, M, hs, K, counts);
+        if (K >= 4) hipLaunchKernelGGL(k_hi_x<kHiKs>, grid, dim3(256), lds, s, d.F, d.W, n0, nb, hs, K, counts);
     }
     return hipGetLastError();
 }
