@@ -649,8 +649,17 @@ def run_single(args, ivm, torch, sg, config: str, headline: bool = True) -> dict
         if k >= args.warmup:
             times.append(e0.elapsed_time(e1))
     c4np = c4.cpu().numpy()
-    out["candidates_order4"] = {"gpu_ms": statistics.median(times), "snapshots": int(c4np.shape[0]),
-                                "walks_per_order": [int(x) for x in c4np[:, 1:].sum(0)]}
+    # orders 3-4 are integer products on the matrix cores: U = T M, V = R M^T and
+    # X = U M over two byte planes of U, 4 N F^2 int8 multiply-adds on the
+    # unpadded shapes, against the dense int8 MFMA peak (5.0 POP/s)
+    ops = 8.0 * N * F * F
+    c4_ms = statistics.median(times)
+    out["candidates_order4"] = {"gpu_ms": c4_ms, "snapshots": int(c4np.shape[0]),
+                                "walks_per_order": [int(x) for x in c4np[:, 1:].sum(0)],
+                                "roofline": {"bound": "mfma", "dtype": "i8", "achieved": ops / (c4_ms / 1e3) / 1e12,
+                                             "peak": 5000.0, "unit": "TOP/s",
+                                             "frac": ops / (c4_ms / 1e3) / 5.0e15,
+                                             "ops_per_call": ops}}
     if not args.no_verify and os.path.exists(cache):
         import oracle
         z = np.load(cache, allow_pickle=False)
