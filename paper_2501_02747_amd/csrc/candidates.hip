@@ -90,7 +90,15 @@ constexpr int kHiWaves = 4;             // bit words (64 facets each) per block
 #ifndef IVM_HI_KS
 #define IVM_HI_KS 4
 #endif
+#ifndef IVM_HI_XCT
+#define IVM_HI_XCT 2
+#endif
+#ifndef IVM_HI_UCT
+#define IVM_HI_UCT 2
+#endif
 constexpr int kHiKs = IVM_HI_KS;        // bit words (64 facets each) per K step
+constexpr int kHiXct = IVM_HI_XCT;      // column tiles of 16 per wave in the X product
+constexpr int kHiUct = IVM_HI_UCT;      // column tiles of 16 per wave in the U and V products
 
 // 16 bits -> 16 bytes of 0/1 (byte v = bit v): each nibble spread by one
 // 24-bit multiply (shifts 0, 7, 14, 21 place bit m at bit 8 m, no carries).
@@ -179,21 +187,23 @@ __device__ inline void add_rows(unsigned long long (&p)[4][4], unsigned long lon
 }
 
 // U and V of a slab (rows n0 .. n0 + nb - 1), their byte planes and V stored,
-// orders 2 and 3 added into counts.  A K step is KS bit words.
-template <int KS>
-__global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int nb, const uint64_t *txv,
-                                               const uint64_t *rxv, const uint64_t *M, HiScratch hs, int K,
-                                               int64_t *counts) {
-    constexpr int kPitch = 64 * KS + 16;              // LDS bytes per panel row (conflict-free 16-byte reads)
-    constexpr int kItems = 2 * kHiRows * KS / 256;    // panel words a thread expands per step
-    static_assert(kItems >= 1 && 2 * kHiRows * KS % 256 == 0, "panel split");
+// orders 2 and 3 added into counts.  A K step is KS bit words; a block covers
+// 64 snapshots x 256 facets, each wave CT column tiles of 16.
+template <int KS, int CT>
+__global__ __launch_bounds__(64 * 16 / CT) void k_hi_uv(int F, int W, int N, int n0, int nb, const uint64_t *txv,
+                                                         const uint64_t *rxv, const uint64_t *M, HiScratch hs, int K,
+                                                         int64_t *counts) {
+    constexpr int kThreads = 64 * 16 / CT;
+    constexpr int kPitch = 64 * KS + 16;                   // LDS bytes per panel row (conflict-free 16-byte reads)
+    constexpr int kItems = 2 * kHiRows * KS / kThreads;    // panel words a thread expands per step
+    static_assert(kItems >= 1 && 2 * kHiRows * KS % kThreads == 0, "panel split");
     extern __shared__ __align__(16) unsigned char lds_hi[];
     unsigned char *panel = lds_hi;                    // [buffer][T, R][row][kPitch]
     unsigned long long *rows = (unsigned long long *)(lds_hi + 4 * kHiRows * kPitch);  // [2][kHiRows]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int rb = blockIdx.x * kHiRows;          // slab row of the block
-    const int cw = blockIdx.y * kHiWaves + wv;    // the wave's bit word (facets 64 cw ..)
-    const bool active = cw < W;
+    const int rb = blockIdx.x * kHiRows;              // slab row of the block
+    const int c0 = 256 * blockIdx.y + 16 * CT * wv;   // the wave's first column (facet)
+    const bool active = c0 < 64 * W;
     const size_t Fp = (size_t)64 * W;
     const uint64_t tail = (F & 63) ? (1ull << (F & 63)) - 1ull : ~0ull;
     if (tid < 2 * kHiRows) rows[tid] = 0ull;
@@ -202,32 +212,32 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
     int pdst[kItems], psw[kItems];
     bool prow[kItems];
     for (int p = 0; p < kItems; ++p) {
-        const int it = tid + 256 * p, src = it / (kHiRows * KS), r = (it / KS) % kHiRows;
+        const int it = tid + kThreads * p, src = it / (kHiRows * KS), r = (it / KS) % kHiRows;
         psw[p] = it % KS;
         prow[p] = rb + r < nb;
         psrc[p] = (src ? rxv : txv) + (size_t)(prow[p] ? n0 + rb + r : 0) * W;
         pdst[p] = src * kHiRows * kPitch + r * kPitch + 64 * psw[p];
     }
-    // B rows of the wave: column g = 64 cw + 16 j + (lane & 15)
+    // B rows of the wave: column g = c0 + 16 j + (lane & 15)
     const int q = lane >> 4, c16 = lane & 15;
-    const uint64_t *bt[4], *bm[4];
-    bool bmv[4];
-    for (int j = 0; j < 4; ++j) {
-        const int g = 64 * (active ? cw : 0) + 16 * j + c16;
+    const uint64_t *bt[CT], *bm[CT];
+    bool bmv[CT];
+    for (int j = 0; j < CT; ++j) {
+        const int g = (active ? c0 : 0) + 16 * j + c16;
         bt[j] = hs.mt + (size_t)g * W;
         bmv[j] = active && g < F;
         bm[j] = M + (size_t)(bmv[j] ? g : 0) * W;
     }
-    i32x4 accU[4][4], accV[4][4];
+    i32x4 accU[4][CT], accV[4][CT];
     for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < CT; ++j) {
             accU[i][j] = i32x4{0, 0, 0, 0};
             accV[i][j] = i32x4{0, 0, 0, 0};
         }
     // raw bit words: the panel's (pa) and the wave's B rows (wt: M^T rows, wm: M
     // rows); each B word is reloaded with the next step's right after it has
     // been expanded, so one register set carries a step of load latency
-    uint64_t pa[kItems], wt[4][KS], wm[4][KS];
+    uint64_t pa[kItems], wt[CT][KS], wm[CT][KS];
     auto fetch_a = [&](int kw0) {
         for (int p = 0; p < kItems; ++p) {
             const int kw = kw0 + psw[p];
@@ -244,7 +254,7 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
     };
     fetch_a(0);
     for (int s = 0; s < KS; ++s)
-        for (int j = 0; j < 4; ++j) fetch_b(j, s, wt[j][s], wm[j][s]);
+        for (int j = 0; j < CT; ++j) fetch_b(j, s, wt[j][s], wm[j][s]);
     const int steps = (W + KS - 1) / KS;
     for (int st = 0; st < steps; ++st) {
         unsigned char *pb = panel + (st & 1) * 2 * kHiRows * kPitch;
@@ -262,8 +272,8 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
         // their products add nothing, and the loop stays branch-free so the
         // accumulators keep their registers)
         for (int s = 0; s < KS; ++s) {
-            i32x4 bU[4], bV[4];
-            for (int j = 0; j < 4; ++j) {
+            i32x4 bU[CT], bV[CT];
+            for (int j = 0; j < CT; ++j) {
                 bU[j] = expand16((unsigned)(wt[j][s] >> (16 * q)) & 0xffffu);
                 bV[j] = expand16((unsigned)(wm[j][s] >> (16 * q)) & 0xffffu);
                 fetch_b(j, (st + 1) * KS + s, wt[j][s], wm[j][s]);
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
                 const int off = (16 * i + c16) * kPitch + 64 * s + 16 * q;
                 const i32x4 aT = *(const i32x4 *)(pb + off);
                 const i32x4 aR = *(const i32x4 *)(pb + kHiRows * kPitch + off);
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < CT; ++j) {
                     accU[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aT, bU[j], accU[i][j], 0, 0, 0);
                     accV[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aR, bV[j], accV[i][j], 0, 0, 0);
                 }
@@ -280,6 +290,7 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
         }
     }
     if (active) {
+        const int cw = c0 >> 6, cb = c0 & 63;   // the R word of the wave's columns, their first bit
         unsigned long long p2[4][4], p3[4][4];
         for (int i = 0; i < 4; ++i)
             for (int v = 0; v < 4; ++v) {
@@ -287,11 +298,11 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
                 unsigned long long s2 = 0, s3 = 0;
                 if (rl < nb) {
                     const uint64_t rw = rxv[(size_t)(n0 + rl) * W + cw];
-                    for (int j = 0; j < 4; ++j) {
-                        const int g = 64 * cw + 16 * j + c16;
+                    for (int j = 0; j < CT; ++j) {
+                        const int g = c0 + 16 * j + c16;
                         const unsigned u = (unsigned)accU[i][j][v], vv = (unsigned)accV[i][j][v];
                         if (g < F) {
-                            if ((rw >> (16 * j + c16)) & 1ull) s2 += u;
+                            if ((rw >> (cb + 16 * j + c16)) & 1ull) s2 += u;
                             s3 += (unsigned long long)u * vv;
                         }
                         const size_t e = (size_t)rl * Fp + g;
@@ -317,48 +328,53 @@ __global__ __launch_bounds__(256) void k_hi_uv(int F, int W, int N, int n0, int 
 template <int KS>
 constexpr size_t hi_lds() { return (size_t)4 * kHiRows * (64 * KS + 16) + 2 * kHiRows * sizeof(unsigned long long); }
 
-// X = U M of a slab from the byte planes of U; order 4 added into counts.
-template <int KS>
-__global__ __launch_bounds__(256) void k_hi_x(int F, int W, int n0, int nb, HiScratch hs, int K, int64_t *counts) {
+// X = U M of a slab from the byte planes of U; order 4 added into counts.  A
+// block covers 64 snapshots x 256 facets; each wave CT column tiles of 16
+// (256 / (16 CT) waves), so fewer accumulators per wave allow two waves per SIMD.
+template <int KS, int CT>
+__global__ __launch_bounds__(64 * 16 / CT) void k_hi_x(int F, int W, int n0, int nb, HiScratch hs, int K,
+                                                        int64_t *counts) {
+    constexpr int kThreads = 64 * 16 / CT;
     constexpr int kPitch = 64 * KS + 16;
-    constexpr int kItems = 2 * kHiRows * KS * 4 / 256;  // 16-byte panel chunks a thread stages per step
-    static_assert(2 * kHiRows * KS * 4 % 256 == 0, "panel split");
+    constexpr int kItems = 2 * kHiRows * KS * 4 / kThreads;  // 16-byte panel chunks a thread stages per step
+    static_assert(2 * kHiRows * KS * 4 % kThreads == 0, "panel split");
     extern __shared__ __align__(16) unsigned char lds_hi[];
     unsigned char *panel = lds_hi;                    // [buffer][plane a, plane b][row][kPitch]
     unsigned long long *rows = (unsigned long long *)(lds_hi + 4 * kHiRows * kPitch);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int rb = blockIdx.x * kHiRows;
-    const int cw = blockIdx.y * kHiWaves + wv;
-    const bool active = cw < W;
+    const int c0 = 256 * blockIdx.y + 16 * CT * wv;   // the wave's first column
+    const bool active = c0 < 64 * W;
     const size_t Fp = (size_t)64 * W;
     if (tid < kHiRows) rows[tid] = 0ull;
     // panel producer: chunk -> (plane, row, 16 bytes of the step); rows < nbp are in the slab
     const int8_t *psrc[kItems];
     int pdst[kItems], pk[kItems];
     for (int p = 0; p < kItems; ++p) {
-        const int it = tid + 256 * p, pl = it / (kHiRows * KS * 4), r = (it / (KS * 4)) % kHiRows, c = it % (KS * 4);
+        const int it = tid + kThreads * p, pl = it / (kHiRows * KS * 4), r = (it / (KS * 4)) % kHiRows,
+                  c = it % (KS * 4);
         pk[p] = c >> 2;                                // word of the step
         psrc[p] = (pl ? hs.ub : hs.ua) + (size_t)(rb + r) * Fp + 16 * c;
         pdst[p] = pl * kHiRows * kPitch + r * kPitch + 16 * c;
     }
     const int q = lane >> 4, c16 = lane & 15;
-    const uint64_t *bt[4];
-    for (int j = 0; j < 4; ++j) bt[j] = hs.mt + (size_t)(64 * (active ? cw : 0) + 16 * j + c16) * W;
-    i32x4 accA[4][4], accB[4][4];
+    const uint64_t *bt[CT];
+    for (int j = 0; j < CT; ++j) bt[j] = hs.mt + (size_t)((active ? c0 : 0) + 16 * j + c16) * W;
+    i32x4 accA[4][CT], accB[4][CT];
     for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < CT; ++j) {
             accA[i][j] = i32x4{0, 0, 0, 0};
             accB[i][j] = i32x4{0, 0, 0, 0};
         }
     i32x4 pa[kItems];
-    uint64_t wt[4][KS];
+    uint64_t wt[CT][KS];
     auto fetch_a = [&](int kw0) {
         for (int p = 0; p < kItems; ++p)
             pa[p] = kw0 + pk[p] < W ? *(const i32x4 *)(psrc[p] + 64 * (size_t)kw0) : i32x4{0, 0, 0, 0};
     };
     fetch_a(0);
     for (int s = 0; s < KS; ++s)
-        for (int j = 0; j < 4; ++j) wt[j][s] = (active && s < W) ? bt[j][s] : 0ull;
+        for (int j = 0; j < CT; ++j) wt[j][s] = (active && s < W) ? bt[j][s] : 0ull;
     const int steps = (W + KS - 1) / KS;
     for (int st = 0; st < steps; ++st) {
         unsigned char *pb = panel + (st & 1) * 2 * kHiRows * kPitch;
@@ -366,8 +382,8 @@ __global__ __launch_bounds__(256) void k_hi_x(int F, int W, int n0, int nb, HiSc
         fetch_a((st + 1) * KS);
         __syncthreads();
         for (int s = 0; s < KS; ++s) {  // (zero operands past W and for an inactive wave)
-            i32x4 b[4];
-            for (int j = 0; j < 4; ++j) {
+            i32x4 b[CT];
+            for (int j = 0; j < CT; ++j) {
                 b[j] = expand16((unsigned)(wt[j][s] >> (16 * q)) & 0xffffu);
                 const int kw = (st + 1) * KS + s;
                 wt[j][s] = (active && kw < W) ? bt[j][kw] : 0ull;
@@ -376,7 +392,7 @@ __global__ __launch_bounds__(256) void k_hi_x(int F, int W, int n0, int nb, HiSc
                 const int off = (16 * i + c16) * kPitch + 64 * s + 16 * q;
                 const i32x4 a0 = *(const i32x4 *)(pb + off);
                 const i32x4 a1 = *(const i32x4 *)(pb + kHiRows * kPitch + off);
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < CT; ++j) {
                     accA[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b[j], accA[i][j], 0, 0, 0);
                     accB[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b[j], accB[i][j], 0, 0, 0);
                 }
@@ -385,15 +401,15 @@ __global__ __launch_bounds__(256) void k_hi_x(int F, int W, int n0, int nb, HiSc
     }
     if (active) {
         unsigned long long p4[4][4];
-        long long cs[4];
-        for (int j = 0; j < 4; ++j) cs[j] = 32896ll * hs.csum[64 * cw + 16 * j + c16];
+        long long cs[CT];
+        for (int j = 0; j < CT; ++j) cs[j] = 32896ll * hs.csum[c0 + 16 * j + c16];
         for (int i = 0; i < 4; ++i)
             for (int v = 0; v < 4; ++v) {
                 const int rl = rb + 16 * i + 4 * q + v;
                 unsigned long long s4 = 0;
                 if (rl < nb)
-                    for (int j = 0; j < 4; ++j) {
-                        const int h = 64 * cw + 16 * j + c16;
+                    for (int j = 0; j < CT; ++j) {
+                        const int h = c0 + 16 * j + c16;
                         if (h < F) {
                             const long long x = (long long)accA[i][j][v] + 256ll * accB[i][j][v] + cs[j];
                             s4 += (unsigned long long)x * hs.v[(size_t)rl * Fp + h];
@@ -611,17 +627,17 @@ hipError_t launch_candidates_high(const Scene &sc, const uint64_t *M, int N, con
     hipLaunchKernelGGL(k_hi_init, dim3((unsigned)(((long long)N + 3) / 4)), dim3(256), 0, s, d.F, d.W, N, txv, rxv,
                        los, K, counts);
     constexpr size_t lds = hi_lds<kHiKs>();
-    if ((e = hipFuncSetAttribute((const void *)k_hi_uv<kHiKs>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+    if ((e = hipFuncSetAttribute((const void *)k_hi_uv<kHiKs, kHiUct>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
             hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)k_hi_x<kHiKs>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+        (e = hipFuncSetAttribute((const void *)k_hi_x<kHiKs, kHiXct>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
             hipSuccess)
         return e;
     const unsigned gy = (unsigned)((d.W + kHiWaves - 1) / kHiWaves);
     for (int n0 = 0; n0 < N; n0 += hs.nbp) {
         const int nb = N - n0 < hs.nbp ? N - n0 : hs.nbp;
         const dim3 grid((unsigned)((nb + kHiRows - 1) / kHiRows), gy);
-        hipLaunchKernelGGL(k_hi_uv<kHiKs>, grid, dim3(256), lds, s, d.F, d.W, N, n0, nb, txv, rxv, M, hs, K, counts);
-        if (K >= 4) hipLaunchKernelGGL(k_hi_x<kHiKs>, grid, dim3(256), lds, s, d.F, d.W, n0, nb, hs, K, counts);
+        hipLaunchKernelGGL((k_hi_uv<kHiKs, kHiUct>), grid, dim3(64 * 16 / kHiUct), lds, s, d.F, d.W, N, n0, nb, txv, rxv, M, hs, K, counts);
+        if (K >= 4) hipLaunchKernelGGL((k_hi_x<kHiKs, kHiXct>), grid, dim3(64 * 16 / kHiXct), lds, s, d.F, d.W, n0, nb, hs, K, counts);
     }
     return hipGetLastError();
 }
