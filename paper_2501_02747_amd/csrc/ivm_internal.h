@@ -230,7 +230,7 @@ hipError_t launch_points(Scene &sc, const TraverseOpts &o, int N, const float *t
 // largest F they accept (F^4 < 2^63 keeps the int64 counts exact), and whether
 // the device's LDS per block holds them for F facets.
 constexpr int kCandHighMaxF = 40960;
-constexpr int kHiMinSlab = 256;  // snapshots of the smallest orders-3/4 slab the layout must hold
+constexpr int kHiMinSlab = 1024;  // snapshots of the smallest orders-3/4 slab the layout must hold
 bool candidates_high_fits(int F);
 // Orders 3 and 4: M^T and a slab of products in the pair scratch [cand, hi_end).
 hipError_t launch_candidates_high(const Scene &sc, const uint64_t *M, int N, const uint64_t *txv,

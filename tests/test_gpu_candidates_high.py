@@ -198,10 +198,10 @@ def _pack_sparse(ivm, S, F):
     return words.view(np.int64)
 
 
-@pytest.mark.parametrize("F,N,seed", [(130, 600, 4), (64, 300, 5), (257, 517, 6)])
+@pytest.mark.parametrize("F,N,seed", [(130, 2100, 4), (64, 1100, 5), (257, 2117, 6)])
 def test_orders_3_4_many_slabs(oracle_mod, ivm, F, N, seed):
     """More snapshots than one slab of the products holds (small scenes keep a
-    slab of 256 snapshots): several slabs and a ragged last one, F on and off a
+    slab of 1024 snapshots): several slabs and a ragged last one, F on and off a
     word boundary; a second call and a call after a matrix call (which reuses
     the same scratch) return the same counts."""
     import torch
