@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256) void k_cand_count(int F, int W, const uint64_t
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kHiRows = 64;             // snapshots per block
+constexpr int kXcds = 8;                // XCDs of the MI355X (blocks reach them round-robin)
 constexpr int kHiWaves = 4;             // bit words (64 facets each) per block
 #ifndef IVM_HI_KS
 #define IVM_HI_KS 4
@@ -332,7 +333,7 @@ constexpr size_t hi_lds() { return (size_t)4 * kHiRows * (64 * KS + 16) + 2 * kH
 // block covers 64 snapshots x 256 facets; each wave CT column tiles of 16
 // (256 / (16 CT) waves), so fewer accumulators per wave allow two waves per SIMD.
 template <int KS, int CT>
-__global__ __launch_bounds__(64 * 16 / CT) void k_hi_x(int F, int W, int n0, int nb, HiScratch hs, int K,
+__global__ __launch_bounds__(64 * 16 / CT) void k_hi_x(int F, int W, int n0, int nb, int ncb, HiScratch hs, int K,
                                                         int64_t *counts) {
     constexpr int kThreads = 64 * 16 / CT;
     constexpr int kPitch = 64 * KS + 16;
@@ -342,8 +343,15 @@ __global__ __launch_bounds__(64 * 16 / CT) void k_hi_x(int F, int W, int n0, int
     unsigned char *panel = lds_hi;                    // [buffer][plane a, plane b][row][kPitch]
     unsigned long long *rows = (unsigned long long *)(lds_hi + 4 * kHiRows * kPitch);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int rb = blockIdx.x * kHiRows;
-    const int c0 = 256 * blockIdx.y + 16 * CT * wv;   // the wave's first column
+    // tiles (row block, column block) in row-major order, a contiguous run of
+    // them per XCD (blocks reach the 8 XCDs round-robin by index): the column
+    // blocks of one row block run together on one XCD and share its L2 copy of
+    // the row block's byte planes
+    const int tiles = gridDim.x, per = tiles / kXcds, extra = tiles % kXcds;
+    const int xcd = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+    const int t = xcd * per + (xcd < extra ? xcd : extra) + k;
+    const int rb = (t / ncb) * kHiRows;
+    const int c0 = 256 * (t % ncb) + 16 * CT * wv;   // the wave's first column
     const bool active = c0 < 64 * W;
     const size_t Fp = (size_t)64 * W;
     if (tid < kHiRows) rows[tid] = 0ull;
@@ -637,7 +645,9 @@ hipError_t launch_candidates_high(const Scene &sc, const uint64_t *M, int N, con
         const int nb = N - n0 < hs.nbp ? N - n0 : hs.nbp;
         const dim3 grid((unsigned)((nb + kHiRows - 1) / kHiRows), gy);
         hipLaunchKernelGGL((k_hi_uv<kHiKs, kHiUct>), grid, dim3(64 * 16 / kHiUct), lds, s, d.F, d.W, N, n0, nb, txv, rxv, M, hs, K, counts);
-        if (K >= 4) hipLaunchKernelGGL((k_hi_x<kHiKs, kHiXct>), grid, dim3(64 * 16 / kHiXct), lds, s, d.F, d.W, n0, nb, hs, K, counts);
+        if (K >= 4)
+            hipLaunchKernelGGL((k_hi_x<kHiKs, kHiXct>), dim3(grid.x * gy), dim3(64 * 16 / kHiXct), lds, s, d.F, d.W, n0,
+                               nb, (int)gy, hs, K, counts);
     }
     return hipGetLastError();
 }
